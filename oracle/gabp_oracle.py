@@ -1,0 +1,420 @@
+"""FP64 reference implementation of synchronous Gaussian BP (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY -- imported by tests, the smoke check and the
+benchmark's CPU baseline; never by the solver.  Plain NumPy, FP64, written
+from Bickson, "Gaussian Belief Propagation: Theory and Application".
+
+Notation follows the paper: node i has the prior P_ii = A_ii and mu_ii =
+b_i / A_ii (Alg. 1 step 1, from the self potential of Ch. 2 Sec. 2.3); every
+directed edge i -> j (A_ij != 0, i != j) carries a precision P_ij and a mean
+mu_ij.  A sweep is synchronous: every message of round t is computed from the
+messages of round t-1 only (parallel scheduling, Ch. 2 Sec. 2.3).  Round 0 has
+all messages zero, so the round-0 means are b_i / A_ii; the tentative means of
+round t use the messages of round t (Ch. 4 toy example tables).
+
+Stop rule (a reading: the paper only says "converged w.r.t. epsilon"): the
+relative residual ||b - A x_t||_2 / ||b||_2 <= tol, evaluated on rounds t with
+t % check_every == 0 and on the last allowed round.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+
+__all__ = [
+    "EdgeGraph", "edge_graph", "dense_from_csr", "dense_solve",
+    "dense_marginal_precisions", "residual", "naive_gabp", "broadcast_gabp",
+    "fixpoint_violation", "is_strictly_dd", "walk_rho", "walk_rho_dense",
+    "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
+    "convfix_gabp", "adjoint_gradient", "fd_gradient", "loss",
+]
+
+
+# ---------------------------------------------------------------------------
+# graph of the linear system (Ch. 2 Sec. 2.1: one node per variable, one
+# undirected edge per nonzero A_ij, i != j; each carries two directed messages)
+# ---------------------------------------------------------------------------
+
+class EdgeGraph:
+    def __init__(self, n, src, dst, a, rev, diag):
+        self.n = n          # number of nodes
+        self.src = src      # edge e is the message src[e] -> dst[e]
+        self.dst = dst
+        self.a = a          # A_{src,dst}
+        self.rev = rev      # index of the edge dst[e] -> src[e]
+        self.diag = diag    # A_ii
+
+    @property
+    def num_edges(self):
+        return len(self.src)
+
+
+def _rows_of(row_ptr):
+    n = len(row_ptr) - 1
+    return np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(row_ptr, dtype=np.int64)))
+
+
+def edge_graph(n, row_ptr, col, val):
+    """Directed edge list of a symmetric CSR matrix (stored off-diagonal nonzeros)."""
+    rows = _rows_of(row_ptr)
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    diag = np.zeros(n)
+    on_diag = rows == col
+    diag[rows[on_diag]] = val[on_diag]
+    keep = (~on_diag) & (val != 0.0)
+    src, dst, a = rows[keep], col[keep], val[keep]
+    key = src * n + dst
+    order = np.argsort(key, kind="stable")
+    rkey = dst * n + src
+    pos = np.searchsorted(key[order], rkey)
+    if len(key) and (np.any(pos >= len(key)) or np.any(key[order][np.minimum(pos, len(key) - 1)] != rkey)):
+        raise ValueError("matrix pattern is not symmetric")
+    rev = order[pos] if len(key) else np.zeros(0, dtype=np.int64)
+    return EdgeGraph(n, src, dst, a, rev, diag)
+
+
+def dense_from_csr(n, row_ptr, col, val):
+    A = np.zeros((n, n))
+    A[_rows_of(row_ptr), np.asarray(col, dtype=np.int64)] = val
+    return A
+
+
+def residual(n, row_ptr, col, val, x, b):
+    """r = b - A x and ||r||_2 / ||b||_2 (||r||_2 when b = 0)."""
+    rows = _rows_of(row_ptr)
+    Ax = np.bincount(rows, weights=np.asarray(val) * x[np.asarray(col, dtype=np.int64)], minlength=n)
+    r = b - Ax
+    nb = np.linalg.norm(b)
+    return r, (np.linalg.norm(r) / nb if nb > 0 else np.linalg.norm(r))
+
+
+# ---------------------------------------------------------------------------
+# the plain definition: x* = A^-1 b, P_i^-1 = (A^-1)_ii  (Prop. 2.1)
+# ---------------------------------------------------------------------------
+
+def dense_solve(A, b):
+    """x = A^-1 b by Cholesky (A SPD) or, for indefinite A, LU with pivoting."""
+    A = np.asarray(A, dtype=np.float64)
+    try:
+        L = np.linalg.cholesky(A)
+    except np.linalg.LinAlgError:
+        return np.linalg.solve(A, b)
+    y = scipy.linalg.solve_triangular(L, b, lower=True)
+    return scipy.linalg.solve_triangular(L.T, y, lower=False)
+
+
+def dense_marginal_precisions(A):
+    """P_i = 1 / (A^-1)_ii, the exact marginal precisions."""
+    return 1.0 / np.diag(np.linalg.inv(np.asarray(A, dtype=np.float64)))
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1 -- naive GaBP, scalar loops (exact with Fraction inputs)
+# ---------------------------------------------------------------------------
+
+def naive_gabp(A, b, sweeps):
+    """Synchronous Alg. 1 for ``sweeps`` rounds on a small dense matrix.
+
+    ``A`` is a list of rows and ``b`` a list; entries may be floats or
+    ``fractions.Fraction``.  Returns one record per round t = 0..sweeps with
+    the messages ``P[(i, j)]``, ``mu[(i, j)]`` (message i -> j), the tentative
+    means ``mean[i]`` and the marginal precisions ``prec[i]`` (Alg. 1 step 4).
+    """
+    n = len(A)
+    zero = b[0] * 0
+    nbr = [[k for k in range(n) if k != i and A[k][i] != 0] for i in range(n)]
+    Pii = [A[i][i] for i in range(n)]
+    muii = [b[i] / A[i][i] for i in range(n)]
+    P = {(k, i): zero for i in range(n) for k in nbr[i]}
+    mu = {(k, i): zero for i in range(n) for k in nbr[i]}
+
+    def infer(P, mu):
+        prec, mean = [], []
+        for i in range(n):
+            num = Pii[i] * muii[i] + sum((P[(k, i)] * mu[(k, i)] for k in nbr[i]), zero)
+            den = Pii[i] + sum((P[(k, i)] for k in nbr[i]), zero)
+            prec.append(den)
+            mean.append(num / den)
+        return prec, mean
+
+    out = []
+    prec, mean = infer(P, mu)
+    out.append({"P": dict(P), "mu": dict(mu), "mean": mean, "prec": prec})
+    for _ in range(sweeps):
+        newP, newmu = {}, {}
+        for i in range(n):
+            for j in nbr[i]:
+                # exclusion sums over N(i) \ j, from the previous round only
+                den = Pii[i] + sum((P[(k, i)] for k in nbr[i] if k != j), zero)
+                num = Pii[i] * muii[i] + sum((P[(k, i)] * mu[(k, i)] for k in nbr[i] if k != j), zero)
+                newP[(i, j)] = -A[i][j] * A[i][j] / den
+                newmu[(i, j)] = num / A[i][j]
+        P, mu = newP, newmu
+        prec, mean = infer(P, mu)
+        out.append({"P": dict(P), "mu": dict(mu), "mean": mean, "prec": prec})
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 -- broadcast GaBP, vectorised over directed edges
+# ---------------------------------------------------------------------------
+
+def _broadcast(g, Pii, muii, P, mu):
+    """Step 2, first half: every node i forms P~_i and mu~_i from all k -> i."""
+    Pt = Pii + np.bincount(g.dst, weights=P, minlength=g.n)
+    mut = (Pii * muii + np.bincount(g.dst, weights=P * mu, minlength=g.n)) / Pt
+    return Pt, mut
+
+
+def _internal_scalars(g, Pt, mut, P, mu):
+    """Step 2, second half: message i -> j from node i's broadcast minus j -> i."""
+    Pji = P[g.rev]
+    muji = mu[g.rev]
+    Pi = Pt[g.src]
+    Pnew = -g.a * g.a / (Pi - Pji)
+    munew = (Pi * mut[g.src] - Pji * muji) / g.a
+    return Pnew, munew
+
+
+def broadcast_gabp(n, row_ptr, col, val, b, tol=1e-10, max_sweeps=2000,
+                   check_every=1, history=False, return_messages=False, graph=None):
+    """Synchronous broadcast GaBP (Alg. 2) on a symmetric CSR system.
+
+    Runs rounds t = 0, 1, ... until the stop rule of the module docstring
+    holds or t == max_sweeps; ``tol <= 0`` runs exactly ``max_sweeps`` rounds.
+    Returns a dict with ``x`` (means of the last round), ``prec`` (P~),
+    ``sweeps`` (that round's index), ``converged``, ``rel_residual`` and,
+    on request, the residual history and the final messages.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    g = graph if graph is not None else edge_graph(n, row_ptr, col, val)
+    Pii = g.diag
+    muii = b / g.diag
+    P = np.zeros(g.num_edges)
+    mu = np.zeros(g.num_edges)
+    hist = []
+    t = 0
+    rel = float("nan")
+    converged = False
+    while True:
+        Pt, mut = _broadcast(g, Pii, muii, P, mu)
+        if tol > 0 and (t % check_every == 0 or t == max_sweeps):
+            _, rel = residual(n, row_ptr, col, val, mut, b)
+            hist.append((t, rel))
+            if rel <= tol:
+                converged = True
+                break
+            if not np.isfinite(rel):
+                break
+        if t >= max_sweeps:
+            break
+        P, mu = _internal_scalars(g, Pt, mut, P, mu)
+        t += 1
+    if tol <= 0:
+        _, rel = residual(n, row_ptr, col, val, mut, b)
+    out = {"x": mut, "prec": Pt, "sweeps": t, "converged": converged, "rel_residual": rel}
+    if history:
+        out["history"] = hist
+    if return_messages:
+        out.update(graph=g, P=P, mu=mu)
+    return out
+
+
+def fixpoint_violation(g, P, mu, b):
+    """Violation of Alg. 2's message equations by (P, mu), relative in the max norm."""
+    Pii = g.diag
+    muii = np.asarray(b, dtype=np.float64) / g.diag
+    Pt, mut = _broadcast(g, Pii, muii, P, mu)
+    Pn, mun = _internal_scalars(g, Pt, mut, P, mu)
+    if g.num_edges == 0:
+        return 0.0
+    # infinity-norm relative violation of each message family
+    eP = np.max(np.abs(Pn - P)) / max(np.max(np.abs(P)), 1e-300)
+    emu = np.max(np.abs(mun - mu)) / max(np.max(np.abs(mu)), 1e-300)
+    return max(eP, emu)
+
+
+# ---------------------------------------------------------------------------
+# convergence conditions and the rate bound
+# ---------------------------------------------------------------------------
+
+def is_strictly_dd(A):
+    A = np.asarray(A)
+    off = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+    return bool(np.all(np.abs(np.diag(A)) > off))
+
+
+def walk_rho_dense(A):
+    """rho(|R|) with R = I - D^-1/2 A D^-1/2, D = |diag A| (walk-summability)."""
+    A = np.asarray(A, dtype=np.float64)
+    s = 1.0 / np.sqrt(np.abs(np.diag(A)))
+    R = np.eye(len(A)) - s[:, None] * A * s[None, :]
+    return float(np.max(np.abs(np.linalg.eigvals(np.abs(R)))))
+
+
+def walk_rho(n, row_ptr, col, val, iters=2000, rtol=1e-6):
+    """rho(|R|) for sparse A by power iteration on M = |R| + I.
+
+    A is symmetric, so M is symmetric and nonnegative: the Rayleigh quotient
+    v^T M v / v^T v is a lower bound on rho(M) and, for v > 0, max_i (Mv)_i / v_i
+    is an upper bound (Collatz-Wielandt).  The shift by I keeps the Perron root
+    strictly dominant.  Returns (lower, upper) bounds on rho(|R|).
+    """
+    rows = _rows_of(row_ptr)
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    diag = np.zeros(n)
+    on = rows == col
+    diag[rows[on]] = val[on]
+    s = 1.0 / np.sqrt(np.abs(diag))
+    w = np.where(on, 0.0, np.abs(val) * s[rows] * s[col])
+    v = np.ones(n)
+    lo, hi = 0.0, float("inf")
+    for _ in range(iters):
+        Mv = v + np.bincount(rows, weights=w * v[col], minlength=n)
+        lo = float(v @ Mv / (v @ v)) - 1.0
+        pos = v > 0
+        hi = float(np.max(Mv[pos] / v[pos])) - 1.0
+        v = Mv / np.max(Mv)
+        if hi - lo <= rtol * max(1.0, hi):
+            break
+    return lo, hi
+
+
+def rate_bound(A, eps):
+    """Rounds to accuracy eps*||b||_inf from the rate bound of Ch. 3 Sec. 3.1.
+
+    eps_i = |a_ii| - sum_{j in N(i)} |a_ij| (must be > 0), gamma = max over
+    i and j in N(i) of 1 / (1 + eps_i / (|a_ij| |N(i)|)), t = ceil(log eps / log gamma).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = len(A)
+    gamma = 0.0
+    for i in range(n):
+        nbr = [j for j in range(n) if j != i and A[i, j] != 0]
+        if not nbr:
+            continue
+        gap = abs(A[i, i]) - sum(abs(A[i, j]) for j in nbr)
+        if gap <= 0:
+            raise ValueError("rate bound needs strict diagonal dominance")
+        for j in nbr:
+            gamma = max(gamma, 1.0 / (1.0 + gap / (abs(A[i, j]) * len(nbr))))
+    if gamma == 0.0:
+        return 0, gamma
+    return int(math.ceil(math.log(eps) / math.log(gamma))), gamma
+
+
+# ---------------------------------------------------------------------------
+# Ch. 5 -- diagonal loading and the iterative correction (double loop)
+# ---------------------------------------------------------------------------
+
+def dd_loading(A, delta=0.05):
+    """Gamma_ii making A + Gamma strictly diagonally dominant (Ch. 5 Sec. 5.2).
+
+    Reading of the garbled threshold: Gamma_ii = max(0, (1+delta) sum_{j!=i}
+    |A_ij| - A_ii).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    off = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+    return np.maximum(0.0, (1.0 + delta) * off - np.diag(A))
+
+
+def walk_loading(rho, delta=0.05):
+    """Normalised loading gamma with (1+gamma) > rho(|R|) (Lemma of Sec. 5.2).
+
+    gamma = (1+delta) rho - 1 when rho >= 1, else 0; applied as Gamma = gamma * diag(A).
+    """
+    return max(0.0, (1.0 + delta) * rho - 1.0)
+
+
+def convfix_dense(A, b, Gamma, x0, steps):
+    """Iterates x^{t+1} = (A + Gamma)^-1 (b + Gamma x^t) with exact inner solves."""
+    A = np.asarray(A, dtype=np.float64)
+    G = np.diag(Gamma)
+    xs = [np.asarray(x0, dtype=np.float64)]
+    for _ in range(steps):
+        xs.append(np.linalg.solve(A + G, b + Gamma * xs[-1]))
+    return xs
+
+
+def convfix_gabp(n, row_ptr, col, val, b, Gamma, tol=1e-9, max_outer=1000,
+                 inner_tol=1e-12, inner_max=100000):
+    """Double loop of Ch. 5: inner Alg. 2 on A + Gamma, outer h^{t+1} = b + Gamma x^t.
+
+    Stops when the relative residual of the original system is <= tol.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    rows = _rows_of(row_ptr)
+    loaded = np.asarray(val, dtype=np.float64).copy()
+    on = rows == np.asarray(col)
+    loaded[on] += Gamma[rows[on]]
+    g = edge_graph(n, row_ptr, col, loaded)
+    x = np.zeros(n)
+    inner_total = 0
+    for k in range(max_outer + 1):
+        _, rel = residual(n, row_ptr, col, val, x, b)
+        if rel <= tol or k == max_outer:
+            break
+        res = broadcast_gabp(n, row_ptr, col, loaded, b + Gamma * x, tol=inner_tol,
+                             max_sweeps=inner_max, graph=g)
+        inner_total += res["sweeps"]
+        x = res["x"]
+    return {"x": x, "outer": k, "inner_sweeps": inner_total, "rel_residual": rel,
+            "converged": rel <= tol}
+
+
+# ---------------------------------------------------------------------------
+# gradients of L = 0.5 ||x - target||^2 with x = A^-1 b
+# ---------------------------------------------------------------------------
+
+def loss(A, b, target):
+    x = np.linalg.solve(A, b)
+    return 0.5 * float(np.sum((x - target) ** 2))
+
+
+def adjoint_gradient(A, b, target, row_ptr, col):
+    """Dense adjoint: lambda = A^-T (x - t); dL/db = lambda; dL/dA = -lambda x^T.
+
+    A symmetric CSR value array ties A_ij and A_ji: the stored entry (i, j),
+    i != j, gets G_ij + G_ji = -(lambda_i x_j + lambda_j x_i), the derivative
+    when both mirror entries move together; a diagonal entry gets G_ii.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    x = np.linalg.solve(A, b)
+    lam = np.linalg.solve(A.T, x - target)
+    G = -np.outer(lam, x)
+    rows = _rows_of(row_ptr)
+    col = np.asarray(col, dtype=np.int64)
+    gv = np.where(rows == col, G[rows, col], G[rows, col] + G[col, rows])
+    return x, lam, gv
+
+
+def fd_gradient(A, b, target, row_ptr, col, rel_step=1e-6):
+    """Central finite differences of L over b_i and over mirror pairs of A."""
+    A = np.asarray(A, dtype=np.float64)
+    rows = _rows_of(row_ptr)
+    col = np.asarray(col, dtype=np.int64)
+    gv = np.zeros(len(col))
+    for e in range(len(col)):
+        i, j = rows[e], col[e]
+        h = rel_step * max(abs(A[i, j]), 1.0)
+        Ap = A.copy()
+        Am = A.copy()
+        Ap[i, j] += h
+        Am[i, j] -= h
+        if i != j:
+            Ap[j, i] += h
+            Am[j, i] -= h
+        gv[e] = (loss(Ap, b, target) - loss(Am, b, target)) / (2 * h)
+    gb = np.zeros(len(b))
+    for i in range(len(b)):
+        h = rel_step * max(abs(b[i]), 1.0)
+        bp = b.copy()
+        bm = b.copy()
+        bp[i] += h
+        bm[i] -= h
+        gb[i] = (loss(A, bp, target) - loss(A, bm, target)) / (2 * h)
+    return gv, gb
