@@ -1,0 +1,205 @@
+"""Benchmark: synchronous broadcast GaBP on one MI355X.
+
+Workload: a G(n, 4n) random graph, n = 2^20 (8,388,608 directed message
+slots), off-diagonals N(0,1), A_ii = 1.1 sum_j |A_ij|, b ~ N(0,1), solved to a
+relative residual of 1e-10.  A step is one full solve from zero messages (all
+sweeps, the fused residual checks, the output).  ``value`` is FP64 edge
+updates per second (E x sweeps / time); the same line reports the FP32 +
+FP64-refinement solve, the roofline of the dominant kernel and the CPU oracle.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import os
+
+# the CPU baseline is the single-threaded oracle: pin BLAS/OpenMP pools first
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import argparse  # noqa: E402
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+import numpy as np  # noqa: E402
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(n, E, elt, check=True, honly=False):
+    """Algorithmic HBM bytes of one sweep launch (each array element touched once).
+
+    Joint sweep, per slot: rev 4 + A_ij elt + gathered reverse pair 2 elt +
+    written pair 2 elt; with the fused check also col 4 + gathered x_j elt.
+    Per node: row pointer 4 + A_ii elt + b_i elt + x_i written elt; check adds
+    x_i read elt.  h-only sweep: the pair becomes one h (and A_ij the frozen
+    coefficient), the node reads 1/P~_i instead of A_ii.
+    """
+    if honly:
+        slot = 4 + elt + elt + elt
+        node = 4 + elt + elt + elt
+    else:
+        slot = 4 + elt + 2 * elt + 2 * elt
+        node = 4 + elt + elt + elt
+    if check:
+        slot += 4 + elt
+        node += elt
+    return slot * E + node * n
+
+
+def source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", "sweep.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(kernel_tag)
+    if not ent or ent.get("sweep_hip_sha") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_solves(torch, g, p, b, precision, steps, warmup, time_sweeps):
+    s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False,
+                 time_sweeps=time_sweeps)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        s.solve(b, tol=TOL, max_iter=2000, x=x)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        _, info = s.solve(b, tol=TOL, max_iter=2000, x=x)
+        infos.append(info)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    props = s.props()
+    xs = x.detach().cpu().numpy()
+    s.close()
+    return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs}
+
+
+def cpu_baseline(p, sweeps):
+    import oracle
+    g = oracle.edge_graph(p.n, p.row_ptr, p.col, p.val)
+    t0 = time.perf_counter()
+    oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=sweeps, graph=g)
+    dt = time.perf_counter() - t0
+    return p.num_offdiag * sweeps / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the sweep is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0811_2518_amd as g
+    import workloads
+
+    log("generating the G(n,4n) workload")
+    p = workloads.config2(args.n)
+    n, E = p.n, p.num_offdiag
+    b = torch.from_numpy(p.b).to("cuda")
+
+    log("FP64 solves")
+    r64 = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, time_sweeps=True)
+    log("FP32 + FP64 refinement solves")
+    r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup, time_sweeps=False)
+
+    i64 = r64["infos"][-1]
+    sweeps64 = i64["sweeps"]
+    ms_step = r64["event_ms"] / args.steps
+    value = E * sweeps64 / (ms_step * 1e-3)
+    i32 = r32["infos"][-1]
+    ms_step32 = r32["event_ms"] / args.steps
+
+    # roofline of the dominant kernel: the FP64 joint sweep with the fused check
+    per_launch_ms = sum(i["sweep_ms"] for i in r64["infos"]) / max(1, sum(i["timed_sweeps"] for i in r64["infos"]))
+    alg = sweep_bytes(n, E, 8, check=True)
+    achieved = alg / (per_launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_sweep_fp64_joint_check")
+
+    # errors against the FP64 reference x (the FP64 GPU solve is itself checked
+    # against the oracle in the tests; here the two precisions are compared)
+    nr = np.linalg.norm(r64["x"])
+    err32 = float(np.linalg.norm(r32["x"] - r64["x"]) / nr)
+    res64 = float(np.linalg.norm(p.b - p.scipy() @ r64["x"]) / np.linalg.norm(p.b))
+    res32 = float(np.linalg.norm(p.b - p.scipy() @ r32["x"]) / np.linalg.norm(p.b))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline ({args.cpu_sweeps} sweeps)")
+        rate, dt = cpu_baseline(p, args.cpu_sweeps)
+        cpu = {"value": rate, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_sweeps} sweeps of the FP64 NumPy broadcast oracle on the same "
+                         f"n={n} workload ({dt:.1f} s, single thread)"}
+
+    out = {
+        "metric": "GaBP edge-updates/s + time-to-1e-10 residual (FP64 vs FP32+refine), % HBM peak",
+        "value": value,
+        "unit": "edge-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"G(n,4n) random graph, n={n}, E={E} directed slots, "
+                               f"A_ii=1.1*sum|A_ij|, b~N(0,1), solve to rel. residual 1e-10",
+                   "n": n, "num_offdiag": E, "tol": TOL,
+                   "edges_per_block": r64["props"]["edges_per_block"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep<double,K,joint> with fused residual check",
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": per_launch_ms},
+        "cpu_baseline": cpu,
+        "fp64": {"time_to_tol_ms": ms_step, "sweeps": sweeps64, "rel_residual": res64,
+                 "wall_ms_per_step": 1e3 * r64["wall_s"] / args.steps},
+        "fp32_refine": {"time_to_tol_ms": ms_step32, "inner_sweeps": i32["sweeps"],
+                        "outer_iters": i32["outer_iters"], "rel_residual": res32,
+                        "rel_err_vs_fp64": err32,
+                        "edge_updates_per_s": E * i32["sweeps"] / (ms_step32 * 1e-3),
+                        "speedup_vs_fp64": ms_step / ms_step32},
+        "kernel_hash": source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

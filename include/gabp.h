@@ -1,0 +1,233 @@
+/*
+ * gabp.h -- C ABI of a synchronous Gaussian belief propagation (GaBP) solver
+ * for sparse symmetric linear systems A x = b on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Bickson, "Gaussian Belief Propagation: Theory and Application"
+ * (arXiv:0811.2518).  The solution x* = A^-1 b is the vector of marginal means
+ * of the Gaussian p(x) ~ exp(-x^T A x / 2 + b^T x) (Ch. 2 Sec. 2.1, Prop. 2.1).
+ * Every directed edge i -> j of the graph of A carries a precision message
+ * P_ij and a mean message; each sweep recomputes all of them from the previous
+ * sweep's messages (synchronous scheduling, Ch. 2 Sec. 2.3) in the broadcast
+ * form of Alg. 2 (Ch. 3 Sec. 3.3): node i forms P~_i = A_ii + sum_k P_ki and
+ * the matching mean sum once, and each outgoing message subtracts the reverse
+ * message j -> i.  Messages are held in information form (P_ij, h_ij = P_ij
+ * mu_ij) as in the Weiss/Johnson form of the appendix.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Array arguments are DEVICE pointers owned by the caller and only borrowed
+ *    for the duration of the call, unless stated "host".  All work is enqueued
+ *    on the stream given at create time; calls that return a gabp_info wait for
+ *    that stream before returning.
+ *  * Matrices are full symmetric CSR with the diagonal stored: int32 row_ptr
+ *    [n+1] (row_ptr[0] = 0), int32 col_idx [nnz] strictly increasing within a
+ *    row, float64 vals [nnz].  The pattern and the values must be symmetric
+ *    (|A_ij - A_ji| <= 1e-12 * max|A|) and every A_ii must be nonzero.
+ *  * Nothing throws across the ABI.  A negative status is an error (outputs
+ *    unspecified); GABP_NOT_CONVERGED still writes the last iterate.
+ *    gabp_last_error() returns a description of the last failure.
+ *  * A handle may be used by one host thread at a time.
+ */
+#ifndef GABP_H
+#define GABP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gabp_ctx *gabp_handle;
+
+typedef enum {
+  GABP_OK = 0,
+  GABP_NOT_CONVERGED = 1,     /* iteration cap reached; x holds the last iterate   */
+  GABP_E_ARG = -1,            /* bad size, pointer, option or CSR structure        */
+  GABP_E_NOT_SYMMETRIC = -2,  /* pattern or values of A not symmetric              */
+  GABP_E_ZERO_DIAG = -3,      /* some A_ii missing or zero                         */
+  GABP_E_NONFINITE = -4,      /* NaN/Inf in the input or in a message (P~_i = P_ji) */
+  GABP_E_DIVERGED = -5,       /* residual grew past 1e8 * ||b|| or became NaN      */
+  GABP_E_HIP = -6,            /* a HIP runtime call failed                         */
+  GABP_E_OOM = -7             /* device allocation failed                          */
+} gabp_status;
+
+typedef enum {
+  GABP_FP64 = 0,          /* messages, aggregates and residual in FP64              */
+  GABP_FP32_REFINE = 1    /* FP32 messages inside an FP64 iterative-refinement loop  */
+} gabp_precision;
+
+/* Solver options.  Fill with gabp_default_opts() and change what is needed. */
+typedef struct {
+  int32_t precision;        /* gabp_precision                                       */
+  int32_t check_every;      /* residual check period in sweeps (>= 1)               */
+  int32_t edges_per_block;  /* message slots per 256-lane workgroup: 512, 1024 or   */
+                            /* 2048; 0 = pick by timing at create (autotuner)       */
+  int32_t inner_max_iter;   /* cap on inner sweeps per outer step                   */
+  int32_t max_outer;        /* cap on outer steps (refinement / loading loop)       */
+  int32_t flags;            /* GABP_FLAG_* bits                                     */
+  double  gamma;            /* diagonal loading of Ch. 5: the inner solves use      */
+                            /* A + gamma * diag(A); 0 = none; < 0 = chosen from an  */
+                            /* estimate of rho(|R|) (walk-summability, Ch. 5.2)     */
+  double  loading_delta;    /* margin for gamma < 0: gamma = (1+delta) rho - 1      */
+  double  inner_tol;        /* inner relative residual target per outer step        */
+} gabp_opts;
+
+/* Reuse precision messages frozen by an earlier solve on the same handle: the
+ * P messages depend on A only (Alg. 2 step 2 has no b term), so later solves
+ * and the adjoint solve run mean-only sweeps.  Without the flag every
+ * gabp_solve runs the full synchronous iteration from zero messages. */
+#define GABP_FLAG_REUSE_PRECISION 1
+
+/* Time every main-mode sweep launch that carries the fused residual check
+ * with a pair of HIP events on the handle's stream; the total is returned in
+ * gabp_info.sweep_ms (profiling aid, adds one event record per launch). */
+#define GABP_FLAG_TIME_SWEEPS 2
+
+typedef struct {
+  int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
+  int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */
+  int32_t converged;     /* 1 if rel_residual <= tol                                  */
+  int32_t status;        /* gabp_status of the call                                   */
+  double  rel_residual;  /* ||b - A x||_2 / ||b||_2 of the returned x (||r|| if b = 0)*/
+  double  gamma;         /* loading actually used (0 if none)                         */
+  double  sweep_ms;      /* GABP_FLAG_TIME_SWEEPS: summed duration of timed sweeps    */
+  int32_t timed_sweeps;  /* number of sweep launches in sweep_ms                      */
+  int32_t sweep_mode;    /* 0: joint (P, h) sweeps were timed, 1: h-only sweeps       */
+} gabp_info;
+
+/* Static properties of a handle (host struct). */
+typedef struct {
+  int64_t n;                /* unknowns                                   */
+  int64_t num_offdiag;      /* directed message slots E = nnz - n         */
+  int32_t edges_per_block;  /* slots per workgroup in the sweep kernel    */
+  int32_t num_blocks;       /* workgroups per sweep launch                */
+  int32_t max_degree;       /* largest off-diagonal row length            */
+  int32_t precision;        /* gabp_precision                             */
+  int64_t device_bytes;     /* device memory owned by the handle          */
+} gabp_props;
+
+/* Default options: FP64, check every sweep, autotuned block size, no loading,
+ * inner_tol 1e-5, inner_max_iter 10000, max_outer 1000, reuse flag on. */
+void gabp_default_opts(gabp_opts *opts);
+
+/*
+ * gabp_create -- ingest A and prepare the solver (Alg. 2 step 1: "set the
+ * neighbourhood", the priors P_ii = A_ii).
+ *   n          number of unknowns (>= 0)
+ *   row_ptr    device int32 [n+1]
+ *   col_idx    device int32 [nnz]
+ *   vals       device float64 [nnz]
+ *   opts       host, nullable (defaults)
+ *   stream     HIP stream for all of the handle's work (0 = default stream)
+ *   out        host; receives the handle (NULL on failure)
+ * Validates the CSR (GABP_E_ARG, GABP_E_NOT_SYMMETRIC, GABP_E_ZERO_DIAG,
+ * GABP_E_NONFINITE), builds the off-diagonal CSR, the reverse-slot index and
+ * the message buffers on the device.  The handle owns copies; the caller's
+ * arrays may be freed after return.  Blocks until done.
+ */
+gabp_status gabp_create(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                        const double *vals, const gabp_opts *opts, hipStream_t stream,
+                        gabp_handle *out);
+
+/*
+ * gabp_solve -- solve A x = b.
+ *   b          device float64 [n]
+ *   x          device float64 [n] (output)
+ *   var        device float64 [n] (output, nullable): 1 / P~_i, the GaBP
+ *              marginal variances (exact on trees, Ch. 2.5; approximate on
+ *              loopy graphs).  Plain FP64 mode only, else GABP_E_ARG.
+ *   tol        stop when ||b - A x_t||_2 / ||b||_2 <= tol.  tol <= 0 runs
+ *              exactly max_iter sweeps and returns x_{max_iter} (no checks).
+ *   max_iter   cap on message sweeps (total, all outer steps)
+ *   info       host, nullable
+ * Plain FP64 (precision FP64, gamma 0): the synchronous iteration of Alg. 2,
+ * x_t being the means formed from the messages of sweep t (x_0 = b_i / A_ii),
+ * checked every check_every sweeps and at sweep max_iter.  Otherwise: the
+ * correction loop x <- x + M^-1 (b - A x), M = A + Gamma (Ch. 5 eq. of the
+ * iterative correction method; Gamma = 0 gives iterative refinement), the
+ * residual in FP64 and M^-1 applied by GaBP sweeps (FP32 messages for
+ * GABP_FP32_REFINE).  Returns GABP_OK, GABP_NOT_CONVERGED, GABP_E_DIVERGED or
+ * GABP_E_NONFINITE.
+ */
+gabp_status gabp_solve(gabp_handle h, const double *b, double *x, double *var,
+                       double tol, int32_t max_iter, gabp_info *info);
+
+/*
+ * gabp_messages -- copy the messages left by the last gabp_solve that ran
+ * with tol <= 0 (exactly max_iter sweeps), plain FP64 mode.
+ *   P, hmsg    device float64 [num_offdiag] (outputs).  Slot s is the s-th
+ *              stored off-diagonal entry (i, j) of A in CSR order (diagonal
+ *              skipped) and holds the message i -> j: its precision P_ij and
+ *              h_ij = P_ij mu_ij.
+ */
+gabp_status gabp_messages(gabp_handle h, double *P, double *hmsg);
+
+/*
+ * gabp_backward -- adjoint of x = A^-1 b for a scalar loss L(x).
+ *   x          device float64 [n]: the solution returned by gabp_solve
+ *   grad_x     device float64 [n]: dL/dx
+ *   grad_b     device float64 [n] (output): lambda = A^-1 dL/dx (A symmetric)
+ *   grad_vals  device float64 [nnz] (output, nullable), aligned with the CSR
+ *              given to gabp_create: entry (i, j), i != j, receives
+ *              -(lambda_i x_j + lambda_j x_i) (mirror entries move together);
+ *              a diagonal entry receives -lambda_i x_i.
+ *   tol, max_iter, info as in gabp_solve for the adjoint solve.
+ * The adjoint solve is a second GaBP solve against A; with
+ * GABP_FLAG_REUSE_PRECISION it reuses the precision messages of the forward
+ * solve and runs mean-only sweeps.
+ */
+gabp_status gabp_backward(gabp_handle h, const double *x, const double *grad_x,
+                          double *grad_b, double *grad_vals, double tol, int32_t max_iter,
+                          gabp_info *info);
+
+/*
+ * gabp_create_batched -- many independent systems in one handle.
+ *   num_sys      number of systems (>= 1)
+ *   sys_row_off  HOST int32 [num_sys+1]: system s owns global rows
+ *                sys_row_off[s] .. sys_row_off[s+1]-1 (sys_row_off[0] = 0)
+ *   row_ptr, col_idx, vals   device CSR of the block-diagonal matrix of all
+ *                systems with GLOBAL column indices; an entry outside its
+ *                system's block is GABP_E_ARG
+ *   opts, stream, out        as gabp_create (precision must be FP32_REFINE)
+ */
+gabp_status gabp_create_batched(int32_t num_sys, const int32_t *sys_row_off,
+                                const int32_t *row_ptr, const int32_t *col_idx,
+                                const double *vals, const gabp_opts *opts,
+                                hipStream_t stream, gabp_handle *out);
+
+/*
+ * gabp_solve_batched -- solve every system for all of its right-hand sides.
+ *   nrhs     HOST int32 [num_sys]: k_s >= 1 right-hand sides of system s
+ *   rhs_off  HOST int64 [num_sys+1]: B and X offsets; system s uses the
+ *            row-major block [n_s][k_s] at rhs_off[s] (rhs_off[s+1] -
+ *            rhs_off[s] = n_s * k_s)
+ *   B        device float64 [rhs_off[num_sys]]
+ *   X        device float64 [rhs_off[num_sys]] (output)
+ *   tol      per-RHS relative residual target (FP64 refinement)
+ *   max_iter cap on inner sweeps per system (all outer steps)
+ *   infos    HOST gabp_info [num_sys] (output, nullable)
+ * One persistent-kernel launch (captured in a HIP graph and replayed)
+ * processes all systems; precision messages are computed once per system and
+ * shared by its right-hand sides.  Returns the worst status over systems.
+ */
+gabp_status gabp_solve_batched(gabp_handle h, const int32_t *nrhs, const int64_t *rhs_off,
+                               const double *B, double *X, double tol, int32_t max_iter,
+                               gabp_info *infos);
+
+/* gabp_props -- static properties of a handle (host output). */
+gabp_status gabp_get_props(gabp_handle h, gabp_props *props);
+
+/* Release every resource of the handle (NULL is a no-op). */
+void gabp_destroy(gabp_handle h);
+
+/* Description of the last failure on h; NULL h gives the calling thread's
+ * last gabp_create / gabp_create_batched failure.  Valid until the next call. */
+const char *gabp_last_error(gabp_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABP_H */

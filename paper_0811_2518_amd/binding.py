@@ -1,0 +1,286 @@
+"""ctypes binding of libgabp (include/gabp.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the solve runs in
+the library's HIP kernels.  The binding raises if the library is missing or
+not built for this machine -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgabp.so")
+
+c_i32, c_i64, c_f64, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+# gabp_status
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_NOT_SYMMETRIC, E_ZERO_DIAG, E_NONFINITE, E_DIVERGED, E_HIP, E_OOM = -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_NOT_SYMMETRIC", -3: "E_ZERO_DIAG",
+                -4: "E_NONFINITE", -5: "E_DIVERGED", -6: "E_HIP", -7: "E_OOM"}
+FP64, FP32_REFINE = 0, 1
+FLAG_REUSE_PRECISION = 1
+FLAG_TIME_SWEEPS = 2
+
+# every entry point declared in include/gabp.h
+EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
+           "gabp_create_batched", "gabp_solve_batched", "gabp_get_props", "gabp_destroy",
+           "gabp_last_error")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", c_i32), ("check_every", c_i32), ("edges_per_block", c_i32),
+                ("inner_max_iter", c_i32), ("max_outer", c_i32), ("flags", c_i32),
+                ("gamma", c_f64), ("loading_delta", c_f64), ("inner_tol", c_f64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("sweeps", c_i32), ("outer_iters", c_i32), ("converged", c_i32), ("status", c_i32),
+                ("rel_residual", c_f64), ("gamma", c_f64), ("sweep_ms", c_f64),
+                ("timed_sweeps", c_i32), ("sweep_mode", c_i32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Props(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("num_blocks", c_i32),
+                ("max_degree", c_i32), ("precision", c_i32), ("device_bytes", c_i64)]
+
+
+class GabpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libgabp.so and declare its signatures (raises if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_0811_2518_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.gabp_default_opts.argtypes = [P(Opts)]
+    L.gabp_default_opts.restype = None
+    L.gabp_create.argtypes = [c_i32, c_void_p, c_void_p, c_void_p, P(Opts), c_void_p, P(c_void_p)]
+    L.gabp_create.restype = c_i32
+    L.gabp_solve.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32, P(Info)]
+    L.gabp_solve.restype = c_i32
+    L.gabp_messages.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.gabp_messages.restype = c_i32
+    L.gabp_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32, P(Info)]
+    L.gabp_backward.restype = c_i32
+    L.gabp_create_batched.argtypes = [c_i32, c_void_p, c_void_p, c_void_p, c_void_p, P(Opts), c_void_p,
+                                      P(c_void_p)]
+    L.gabp_create_batched.restype = c_i32
+    L.gabp_solve_batched.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32,
+                                     c_void_p]
+    L.gabp_solve_batched.restype = c_i32
+    L.gabp_get_props.argtypes = [c_void_p, P(Props)]
+    L.gabp_get_props.restype = c_i32
+    L.gabp_destroy.argtypes = [c_void_p]
+    L.gabp_destroy.restype = None
+    L.gabp_last_error.argtypes = [c_void_p]
+    L.gabp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().gabp_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _err(handle, status, what):
+    msg = lib().gabp_last_error(handle)
+    return GabpError(status, f"{what}: {msg.decode() if msg else ''}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, device):
+    """Device tensor of the given dtype (copies host arrays; keeps device tensors)."""
+    torch = _torch()
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device=device, dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s, ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One symmetric sparse system A (full CSR, diagonal stored) on the GPU."""
+
+    def __init__(self, row_ptr, col, val, *, precision="fp64", check_every=1, edges_per_block=0,
+                 gamma=0.0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
+                 reuse_precision=True, time_sweeps=False, device="cuda", stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream, sh = _stream_handle(stream)
+        self.row_ptr = _dev(row_ptr, torch.int32, self.device)
+        self.col = _dev(col, torch.int32, self.device)
+        self.val = _dev(val, torch.float64, self.device)
+        self.n = int(self.row_ptr.numel()) - 1
+        self.opts = default_opts(
+            precision={"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}[precision],
+            check_every=check_every, edges_per_block=edges_per_block, gamma=gamma,
+            loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
+            max_outer=max_outer,
+            flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0))
+        h = ctypes.c_void_p()
+        st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
+                               ctypes.byref(self.opts), sh, ctypes.byref(h))
+        if st != OK:
+            raise _err(None, st, "gabp_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def props(self) -> dict:
+        p = Props()
+        st = lib().gabp_get_props(self._h, ctypes.byref(p))
+        if st != OK:
+            raise _err(self._h, st, "gabp_get_props")
+        return {f: getattr(p, f) for f, _ in p._fields_}
+
+    def solve(self, b, tol=1e-10, max_iter=2000, *, x=None, var=False, check=True):
+        """x = A^-1 b.  Returns (x, info dict[, var])."""
+        torch = _torch()
+        b = _dev(b, torch.float64, self.device)
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device) if x is None else x
+        v = torch.empty(self.n, dtype=torch.float64, device=self.device) if var else None
+        info = Info()
+        st = lib().gabp_solve(self._h, _ptr(b), _ptr(x), _ptr(v), float(tol), int(max_iter),
+                              ctypes.byref(info))
+        if check and st < 0:
+            raise _err(self._h, st, "gabp_solve")
+        d = info.as_dict()
+        d["status"] = st
+        return (x, d, v) if var else (x, d)
+
+    def messages(self):
+        """(P, h) of the last fixed-sweep FP64 solve, slot order of the off-diagonal CSR."""
+        torch = _torch()
+        E = self.props()["num_offdiag"]
+        P = torch.empty(E, dtype=torch.float64, device=self.device)
+        hm = torch.empty(E, dtype=torch.float64, device=self.device)
+        st = lib().gabp_messages(self._h, _ptr(P), _ptr(hm))
+        if st != OK:
+            raise _err(self._h, st, "gabp_messages")
+        return P, hm
+
+    def backward(self, x, grad_x, tol=1e-12, max_iter=5000, grad_vals=True, check=True):
+        torch = _torch()
+        x = _dev(x, torch.float64, self.device)
+        gx = _dev(grad_x, torch.float64, self.device)
+        gb = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gv = torch.empty(self.val.numel(), dtype=torch.float64, device=self.device) if grad_vals else None
+        info = Info()
+        st = lib().gabp_backward(self._h, _ptr(x), _ptr(gx), _ptr(gb), _ptr(gv), float(tol), int(max_iter),
+                                 ctypes.byref(info))
+        if check and st < 0:
+            raise _err(self._h, st, "gabp_backward")
+        d = info.as_dict()
+        d["status"] = st
+        return gb, gv, d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gabp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def last_create_error() -> str:
+    m = lib().gabp_last_error(None)
+    return m.decode() if m else ""
+
+
+def try_create(row_ptr, col, val, **kw):
+    """Create and return (status, Solver or None) without raising on a gabp error."""
+    try:
+        return OK, Solver(row_ptr, col, val, **kw)
+    except GabpError as e:
+        return e.status, None
+
+
+class BatchedSolver:
+    """Many independent systems (block-diagonal CSR with global columns)."""
+
+    def __init__(self, sys_row_off, row_ptr, col, val, *, inner_tol=1e-5, check_every=1,
+                 inner_max_iter=10000, max_outer=1000, device="cuda", stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream, sh = _stream_handle(stream)
+        self.sys_row_off = np.ascontiguousarray(np.asarray(sys_row_off, dtype=np.int32))
+        self.row_ptr = _dev(row_ptr, torch.int32, self.device)
+        self.col = _dev(col, torch.int32, self.device)
+        self.val = _dev(val, torch.float64, self.device)
+        self.num_sys = len(self.sys_row_off) - 1
+        self.opts = default_opts(precision=FP32_REFINE, inner_tol=inner_tol, check_every=check_every,
+                                 inner_max_iter=inner_max_iter, max_outer=max_outer)
+        h = ctypes.c_void_p()
+        st = lib().gabp_create_batched(self.num_sys, self.sys_row_off.ctypes.data_as(c_void_p),
+                                       _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
+                                       ctypes.byref(self.opts), sh, ctypes.byref(h))
+        if st != OK:
+            raise _err(None, st, "gabp_create_batched")
+        self._h = h
+
+    def solve(self, nrhs, rhs_off, B, tol=1e-10, max_iter=100000, X=None, check=True):
+        torch = _torch()
+        nrhs = np.ascontiguousarray(np.asarray(nrhs, dtype=np.int32))
+        rhs_off = np.ascontiguousarray(np.asarray(rhs_off, dtype=np.int64))
+        B = _dev(B, torch.float64, self.device)
+        X = torch.empty_like(B) if X is None else X
+        infos = (Info * self.num_sys)()
+        st = lib().gabp_solve_batched(self._h, nrhs.ctypes.data_as(c_void_p), rhs_off.ctypes.data_as(c_void_p),
+                                      _ptr(B), _ptr(X), float(tol), int(max_iter),
+                                      ctypes.cast(infos, c_void_p))
+        if check and st < 0:
+            raise _err(self._h, st, "gabp_solve_batched")
+        return X, [i.as_dict() for i in infos], st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gabp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

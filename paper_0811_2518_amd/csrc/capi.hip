@@ -1,0 +1,284 @@
+// extern "C" entry points of libgabp (declared in include/gabp.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+static thread_local std::string tl_error;
+
+gabp_status fail(Ctx* c, gabp_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else tl_error = msg;
+  return s;
+}
+
+gabp_status hip_fail(Ctx* c, hipError_t e, const char* what) {
+  const std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? GABP_E_OOM : GABP_E_HIP, msg);
+}
+
+}  // namespace gabp
+
+using namespace gabp;
+
+namespace {
+
+#define TRY(x)                       \
+  do {                               \
+    gabp_status s_ = (x);            \
+    if (s_ != GABP_OK) return s_;    \
+  } while (0)
+
+gabp_status check_opts(Ctx* c, const gabp_opts& o) {
+  if (o.precision != GABP_FP64 && o.precision != GABP_FP32_REFINE) return fail(c, GABP_E_ARG, "precision");
+  if (o.check_every < 1) return fail(c, GABP_E_ARG, "check_every must be >= 1");
+  if (o.edges_per_block != 0 && o.edges_per_block != 512 && o.edges_per_block != 1024 &&
+      o.edges_per_block != 2048)
+    return fail(c, GABP_E_ARG, "edges_per_block must be 0, 512, 1024 or 2048");
+  if (o.inner_max_iter < 0 || o.max_outer < 0) return fail(c, GABP_E_ARG, "negative iteration cap");
+  if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
+    return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
+  return GABP_OK;
+}
+
+gabp_status common_setup(Ctx* c) {
+  GABP_HIP(c, hipHostMalloc((void**)&c->st_h, 4 * sizeof(DevStatus), hipHostMallocDefault));
+  for (auto& e : c->ev) GABP_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  TRY(dev_alloc(c, (void**)&c->st_d, 2 * sizeof(DevStatus)));
+  TRY(dev_alloc(c, (void**)&c->norms_d, 4 * sizeof(double)));
+  GABP_HIP(c, launch_reset_status(c->st_d, 2, c->stream));
+  if (c->opts.flags & GABP_FLAG_TIME_SWEEPS) {
+    c->tev.resize(2 * 2048, nullptr);
+    for (auto& e : c->tev) GABP_HIP(c, hipEventCreate(&e));
+  }
+  return GABP_OK;
+}
+
+// Buffers of the solve loops, sized for the handle's precision.
+gabp_status alloc_solver(Ctx* c) {
+  const int64_t n = c->n, E = c->E;
+  const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
+  const size_t pair = fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
+  const size_t elt = fp32 ? sizeof(float) : sizeof(double);
+  for (int i = 0; i < 2; ++i) {
+    TRY(dev_alloc(c, &c->msg_d[i], pair * E));
+    c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the pair buffers
+    TRY(dev_alloc(c, (void**)&c->x64_d[i], sizeof(double) * n));
+    TRY(dev_alloc(c, (void**)&c->pt64_d[i], sizeof(double) * n));
+    TRY(dev_alloc(c, (void**)&c->xo_d[i], sizeof(double) * n));
+    if (fp32) TRY(dev_alloc(c, (void**)&c->x32_d[i], sizeof(float) * n));
+  }
+  TRY(dev_alloc(c, &c->gcoef_d, elt * E));
+  TRY(dev_alloc(c, &c->inv_pt_d, elt * n));
+  if (fp32) TRY(dev_alloc(c, (void**)&c->rin32_d, sizeof(float) * n));
+  TRY(dev_alloc(c, (void**)&c->rin64_d, sizeof(double) * n));
+  TRY(dev_alloc(c, (void**)&c->din32_d, sizeof(float) * n));
+  // diagonal of the inner matrix A + gamma diag(A)
+  double gamma = c->opts.gamma;
+  if (gamma < 0.0) return fail(c, GABP_E_ARG, "automatic loading (gamma < 0) needs gabp_estimate_loading");
+  c->gamma_used = gamma;
+  if (gamma > 0.0) {
+    TRY(dev_alloc(c, (void**)&c->din64_d, sizeof(double) * n));
+    GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0 + gamma, c->din64_d, c->din32_d, c->n, c->stream));
+  } else {
+    c->din64_d = c->d64_d;
+    GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0, nullptr, c->din32_d, c->n, c->stream));
+  }
+  return GABP_OK;
+}
+
+bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->opts.gamma == 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+void gabp_default_opts(gabp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = GABP_FP64;
+  o->check_every = 1;
+  o->edges_per_block = 0;
+  o->inner_max_iter = 10000;
+  o->max_outer = 1000;
+  o->flags = GABP_FLAG_REUSE_PRECISION;
+  o->gamma = 0.0;
+  o->loading_delta = 0.05;
+  o->inner_tol = 1e-5;
+}
+
+gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                        const gabp_opts* opts, hipStream_t stream, gabp_handle* out) {
+  if (!out) return fail(nullptr, GABP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 0) return fail(nullptr, GABP_E_ARG, "n < 0");
+  if (n > 0 && (!row_ptr || !col_idx || !vals)) return fail(nullptr, GABP_E_ARG, "NULL CSR array");
+  gabp_ctx* c = new gabp_ctx();
+  c->n = n;
+  c->stream = stream;
+  if (opts) c->opts = *opts;
+  else gabp_default_opts(&c->opts);
+  gabp_status r = check_opts(c, c->opts);
+  if (r == GABP_OK) r = common_setup(c);
+  if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, nullptr, 0);
+  if (r == GABP_OK && n > 0) r = alloc_solver(c);
+  if (r == GABP_OK && n > 0) r = autotune(c);
+  if (r == GABP_OK) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) r = hip_fail(c, e, "hipStreamSynchronize");
+  }
+  if (r != GABP_OK) {
+    tl_error = c->err;
+    gabp_destroy(c);
+    return r;
+  }
+  *out = c;
+  return GABP_OK;
+}
+
+gabp_status gabp_solve(gabp_handle h, const double* b, double* x, double* var, double tol, int32_t max_iter,
+                       gabp_info* info) {
+  if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = h;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (c->batched) return fail(c, GABP_E_ARG, "batched handle: use gabp_solve_batched");
+  if (max_iter < 0) return fail(c, GABP_E_ARG, "max_iter < 0");
+  if (std::isnan(tol)) return fail(c, GABP_E_ARG, "tol is NaN");
+  if (c->n == 0) {
+    if (info) info->converged = 1;
+    return GABP_OK;
+  }
+  if (!b || !x) return fail(c, GABP_E_ARG, "NULL b or x");
+  if (plain_mode(c)) return solve_plain(c, b, x, var, tol, max_iter, info, true);
+  if (var) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
+  if (!(tol > 0.0)) return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
+  return solve_outer(c, b, x, tol, max_iter, info);
+}
+
+gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
+  if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = h;
+  if (c->last_msg_round < 0 || c->opts.precision != GABP_FP64)
+    return fail(c, GABP_E_ARG, "no FP64 messages from a fixed-sweep solve (tol <= 0) are held");
+  if (c->E == 0) return GABP_OK;
+  if (!P || !hm) return fail(c, GABP_E_ARG, "NULL output");
+  if (c->last_msg_round == 0) {  // round 0: every message is zero (Alg. 2 step 1)
+    GABP_HIP(c, launch_fill(P, c->E, 0.0, c->stream));
+    GABP_HIP(c, launch_fill(hm, c->E, 0.0, c->stream));
+  } else {
+    GABP_HIP(c, launch_split_pairs(c->msg_d[c->last_msg_round & 1], P, hm, c->E, c->stream));
+  }
+  GABP_HIP(c, hipStreamSynchronize(c->stream));
+  return GABP_OK;
+}
+
+gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, double* grad_b,
+                          double* grad_vals, double tol, int32_t max_iter, gabp_info* info) {
+  if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = h;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (c->batched) return fail(c, GABP_E_ARG, "batched handle");
+  if (max_iter < 0 || !(tol > 0.0)) return fail(c, GABP_E_ARG, "backward needs tol > 0 and max_iter >= 0");
+  if (c->n == 0) return GABP_OK;
+  if (!x || !grad_x || !grad_b) return fail(c, GABP_E_ARG, "NULL x, grad_x or grad_b");
+  // A is symmetric: the adjoint system A^T lambda = dL/dx is a second GaBP solve against A
+  gabp_status r = plain_mode(c) ? solve_plain(c, grad_x, grad_b, nullptr, tol, max_iter, info, true)
+                                : solve_outer(c, grad_x, grad_b, tol, max_iter, info);
+  if (r < 0) return r;
+  if (grad_vals) {
+    GABP_HIP(c, launch_grad_vals(c->row_ptr_d, c->col_d, grad_b, x, grad_vals, c->n, c->stream));
+    GABP_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return r;
+}
+
+gabp_status gabp_create_batched(int32_t num_sys, const int32_t* sys_row_off, const int32_t* row_ptr,
+                                const int32_t* col_idx, const double* vals, const gabp_opts* opts,
+                                hipStream_t stream, gabp_handle* out) {
+  if (!out) return fail(nullptr, GABP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (num_sys < 1 || !sys_row_off || sys_row_off[0] != 0) return fail(nullptr, GABP_E_ARG, "num_sys / sys_row_off");
+  for (int32_t s = 0; s < num_sys; ++s)
+    if (sys_row_off[s + 1] < sys_row_off[s]) return fail(nullptr, GABP_E_ARG, "sys_row_off decreases");
+  const int32_t n = sys_row_off[num_sys];
+  if (n > 0 && (!row_ptr || !col_idx || !vals)) return fail(nullptr, GABP_E_ARG, "NULL CSR array");
+  gabp_ctx* c = new gabp_ctx();
+  c->n = n;
+  c->stream = stream;
+  c->batched = true;
+  if (opts) c->opts = *opts;
+  else {
+    gabp_default_opts(&c->opts);
+    c->opts.precision = GABP_FP32_REFINE;
+  }
+  gabp_status r = check_opts(c, c->opts);
+  if (r == GABP_OK && c->opts.precision != GABP_FP32_REFINE)
+    r = fail(c, GABP_E_ARG, "batched solves run FP32 messages with FP64 refinement");
+  if (r == GABP_OK) r = common_setup(c);
+  int32_t* sys_d = nullptr;
+  if (r == GABP_OK) r = dev_alloc(c, (void**)&sys_d, sizeof(int32_t) * (num_sys + 1));
+  if (r == GABP_OK) {
+    hipError_t e = hipMemcpyAsync(sys_d, sys_row_off, sizeof(int32_t) * (num_sys + 1), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) r = hip_fail(c, e, "hipMemcpyAsync");
+  }
+  if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, sys_d, num_sys);
+  if (r == GABP_OK) r = batched_create(c, num_sys, sys_row_off);
+  if (r == GABP_OK) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) r = hip_fail(c, e, "hipStreamSynchronize");
+  }
+  if (r != GABP_OK) {
+    tl_error = c->err;
+    gabp_destroy(c);
+    return r;
+  }
+  *out = c;
+  return GABP_OK;
+}
+
+gabp_status gabp_solve_batched(gabp_handle h, const int32_t* nrhs, const int64_t* rhs_off, const double* B,
+                               double* X, double tol, int32_t max_iter, gabp_info* infos) {
+  if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = h;
+  if (!c->batched) return fail(c, GABP_E_ARG, "not a batched handle");
+  if (!nrhs || !rhs_off || !(tol > 0.0) || max_iter < 0) return fail(c, GABP_E_ARG, "arguments");
+  return batched_solve(c, nrhs, rhs_off, B, X, tol, max_iter, infos);
+}
+
+gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
+  if (!h || !p) return fail(h, GABP_E_ARG, "NULL argument");
+  Ctx* c = h;
+  p->n = c->n;
+  p->num_offdiag = c->E;
+  p->edges_per_block = c->K * kBlock;
+  p->num_blocks = c->nblk;
+  p->max_degree = c->max_degree;
+  p->precision = c->opts.precision;
+  p->device_bytes = c->device_bytes;
+  return GABP_OK;
+}
+
+void gabp_destroy(gabp_handle h) {
+  if (!h) return;
+  gabp_ctx* c = h;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  batched_destroy(c);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->st_h) (void)hipHostFree(c->st_h);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->tev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* gabp_last_error(gabp_handle h) {
+  if (!h) return tl_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

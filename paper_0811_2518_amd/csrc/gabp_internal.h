@@ -1,0 +1,216 @@
+// Internal declarations shared by the HIP translation units of libgabp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gabp.h"
+
+namespace gabp {
+
+constexpr int kBlock = 256;            // lanes per workgroup in the sweep kernels
+constexpr int kMaxRowsPerBlock = 256;  // one aggregate lane per row
+constexpr double kDivergeLimit = 1e8;  // relative residual treated as divergence
+
+// Device-side solver status.  Written only by the last-arriving workgroup of a
+// checking sweep (or by any workgroup for the error bits); read at the start
+// of every sweep so that sweeps enqueued after convergence return at once.
+struct DevStatus {
+  int32_t done;        // nonzero: converged or failed, later sweeps are no-ops
+  int32_t conv_round;  // round whose x met the tolerance (-1: none)
+  int32_t error;       // kErr* bits
+  uint32_t ticket;     // arrival counter of the checking workgroups
+  double last_rel;     // last relative residual computed
+  int32_t last_round;  // round of last_rel (-1: none)
+  int32_t pad;
+};
+constexpr int32_t kErrNonfinite = 1;
+constexpr int32_t kErrDiverged = 2;
+
+enum SweepMode : int {
+  kJoint = 0,   // P and h messages (Alg. 2 step 2)
+  kHOnly = 1,   // h messages with frozen precisions (coefficient per slot)
+  kAgg = 2,     // node aggregates only: x (and P~) of the current messages
+  kFreeze = 3,  // aggregates + freeze: g_s = -a_s / (P~_i - P_ji), 1 / P~_i
+  kResid = 4    // residual check only
+};
+
+// Arguments of one sweep launch.  T is the message precision.
+template <typename T>
+struct SweepArgs {
+  const int32_t* blk_row;  // [nblk+1] first row of each workgroup
+  const int32_t* off_ptr;  // [n+1] off-diagonal CSR row pointers
+  const int32_t* off_col;  // [E]
+  const int32_t* rev;      // [E] slot of the reverse edge
+  const T* a;              // [E] A_ij of slot s = (i, j)
+  const T* diag;           // [n] P_ii (possibly loaded)
+  const T* rhs;            // [n] right-hand side
+  const void* min;         // messages of the previous round (pair or h only)
+  void* mout;              // messages of this round
+  const T* gcoef;          // [E] frozen coefficient (kHOnly)
+  const T* inv_pt;         // [n] frozen 1 / P~ (kHOnly)
+  T* gcoef_out;            // kFreeze outputs
+  T* inv_pt_out;
+  T* xout;                 // [n] x of round t-1 (nullable)
+  T* ptout;                // [n] P~ of round t-1 (nullable)
+  const T* xchk;           // [n] x of round t-2 (checked)
+  double* partials;        // [nblk] per-workgroup sums of squared residuals
+  DevStatus* st;
+  const double* rhs_norm;  // device scalar ||rhs||_2
+  double tol;
+  int32_t nblk;
+  int32_t round_checked;   // round index of xchk
+  int32_t zero_in;         // previous messages are all zero (first sweep)
+  int32_t check;           // compute the residual of xchk
+};
+
+// Everything a handle owns.  Device arrays are suffixed _d.
+struct Ctx {
+  int32_t n = 0;
+  int64_t E = 0;
+  int32_t nnz = 0;
+  hipStream_t stream = nullptr;
+  gabp_opts opts{};
+  int32_t max_degree = 0;
+  int64_t device_bytes = 0;
+  std::vector<void*> allocs;
+
+  // caller's full CSR (kept for the gradient assembly)
+  int32_t* row_ptr_d = nullptr;
+  int32_t* col_d = nullptr;
+  // off-diagonal CSR
+  int32_t* off_ptr_d = nullptr;
+  int32_t* off_col_d = nullptr;
+  int32_t* rev_d = nullptr;
+  double* a64_d = nullptr;
+  double* d64_d = nullptr;     // A_ii
+  float* a32_d = nullptr;
+  float* din32_d = nullptr;    // inner diagonal in FP32 (loaded)
+  double* din64_d = nullptr;   // inner diagonal in FP64 (loaded; == d64 when gamma = 0)
+  double gamma_used = 0.0;
+
+  // workgroup partition of the rows
+  int32_t K = 0;               // slots per lane
+  int32_t nblk = 0;
+  int32_t* blk_row_d = nullptr;
+  int32_t nblk_capacity = 0;
+  int32_t partials_capacity = 0;
+  std::vector<int32_t> off_ptr_h;
+
+  // message buffers (double-buffered), frozen precisions
+  void* msg_d[2] = {nullptr, nullptr};  // double2 / float2 pairs [E]
+  void* hmsg_d[2] = {nullptr, nullptr}; // h only [E]
+  void* gcoef_d = nullptr;              // [E]
+  void* inv_pt_d = nullptr;             // [n]
+  bool frozen_valid = false;
+  int32_t frozen_prec = -1;
+  int last_msg_round = -1;              // round held by msg_d[last_msg_round & 1] (tol <= 0 solves)
+
+  // node vectors
+  double* x64_d[2] = {nullptr, nullptr};  // x of rounds (plain) / inner FP64 iterates
+  double* xo_d[2] = {nullptr, nullptr};   // outer iterates
+  double* pt64_d[2] = {nullptr, nullptr};
+  float* x32_d[2] = {nullptr, nullptr};
+  float* rin32_d = nullptr;               // inner right-hand side (FP32)
+  double* rin64_d = nullptr;              // inner right-hand side (FP64 inner)
+  double* partials_d = nullptr;
+  double* norms_d = nullptr;              // [4]: ||b||, ||r_outer||, spare
+  DevStatus* st_d = nullptr;              // [2]: inner / outer
+  DevStatus* st_h = nullptr;              // pinned host mirror [4]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // sweep timing (GABP_FLAG_TIME_SWEEPS)
+  std::vector<hipEvent_t> tev;      // pairs: start, stop
+  int tev_used = 0;
+  double sweep_ms = 0.0;
+  int timed_sweeps = 0;
+  int timed_mode = 0;
+
+  // batched
+  bool batched = false;
+  void* batch = nullptr;
+
+  std::string err;
+};
+
+// ---- helpers ---------------------------------------------------------------
+gabp_status fail(Ctx* c, gabp_status s, const std::string& msg);
+gabp_status hip_fail(Ctx* c, hipError_t e, const char* what);
+#define GABP_HIP(ctx, call)                                   \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return gabp::hip_fail((ctx), e_, #call); \
+  } while (0)
+
+gabp_status dev_alloc(Ctx* c, void** p, size_t bytes);
+
+// ---- ingest (ingest.hip) ---------------------------------------------------
+gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const double* vals,
+                   const int32_t* sys_row_off_d, int32_t num_sys);
+gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row);
+gabp_status set_partition(Ctx* c, int K);
+
+// ---- kernels (sweep.hip) ---------------------------------------------------
+template <typename T>
+hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s);
+size_t sweep_lds_bytes(int K, int elt, bool joint);
+hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_norm(const double* v, int64_t n, double* partials, int nparts, double* out,
+                       DevStatus* st, hipStream_t s);
+hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, const DevStatus* st,
+                             int32_t fallback_round, double* x, double* var, int32_t n,
+                             hipStream_t s);
+// outer correction step: x_new = x_old + d (d from the inner solve, FP32 or FP64
+// selected on the device by the inner status), r = b - A x_new in FP64, r_in =
+// r in the inner precision, ||r|| and the check against tol.
+struct OuterArgs {
+  const int32_t* blk_row;
+  const int32_t* off_ptr;
+  const int32_t* off_col;
+  const double* a;
+  const double* diag;
+  const double* b;
+  const double* xold;     // nullable (x = 0)
+  double* xnew;
+  const float* d32[2];    // inner iterates (FP32) by round parity
+  const double* d64[2];   // inner iterates (FP64) by round parity
+  const DevStatus* st_in; // selects the inner round
+  int32_t in_fallback;    // inner round when the inner solve did not converge
+  int32_t use_d;          // 0: no correction (x_new = x_old)
+  float* rin32;
+  double* rin64;
+  double* partials;
+  DevStatus* st;          // outer status
+  const double* b_norm;
+  double* r_norm;         // output ||r||
+  double tol;
+  int32_t nblk;
+  int32_t n;
+};
+hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
+hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam,
+                            const double* x, double* gv, int32_t n, hipStream_t s);
+hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n,
+                             hipStream_t s);
+hipError_t launch_split_pairs(const void* m, double* P, double* h, int64_t E, hipStream_t s);
+
+// ---- drivers (solve.hip) ---------------------------------------------------
+gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double tol,
+                        int32_t max_iter, gabp_info* info, bool allow_reuse);
+gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter,
+                        gabp_info* info);
+gabp_status autotune(Ctx* c);
+
+// ---- batched (batched.hip) -------------------------------------------------
+gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off);
+gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, const double* B,
+                          double* X, double tol, int32_t max_iter, gabp_info* infos);
+void batched_destroy(Ctx* c);
+
+}  // namespace gabp
+
+// The opaque handle type of the C ABI.
+struct gabp_ctx : public gabp::Ctx {};

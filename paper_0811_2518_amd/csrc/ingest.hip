@@ -1,0 +1,275 @@
+// CSR ingest: validation, diagonal split, reverse-slot index, workgroup partition.
+//
+// Alg. 2 step 1 sets the neighbourhood N(i) (the nonzeros of row i, diagonal
+// excluded) and the priors P_ii = A_ii.  Here that becomes an off-diagonal CSR
+// whose slot s = (i, j) holds the message i -> j, plus rev[s] = the slot of
+// (j, i), which the broadcast update subtracts (Alg. 2, P_ij = -A_ij^2 /
+// (P~_i - P_ji)).
+#include <algorithm>
+#include <cmath>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+namespace {
+
+constexpr int kFlagArg = 1;
+constexpr int kFlagZeroDiag = 2;
+constexpr int kFlagAsym = 4;
+constexpr int kFlagNonfinite = 8;
+
+struct IngestScratch {
+  int32_t flags;
+  int32_t max_degree;
+  unsigned long long maxabs_bits;  // |A| max as IEEE bits (nonnegative doubles order as integers)
+};
+
+// One lane per row: structure checks, diagonal, off-diagonal row pointers.
+__global__ void k_validate_rows(int32_t n, int32_t nnz, const int32_t* __restrict__ row_ptr,
+                                const int32_t* __restrict__ col, const double* __restrict__ vals,
+                                const int32_t* __restrict__ row_lo,  // nullable: first col allowed
+                                const int32_t* __restrict__ row_hi,  // nullable: one past last col
+                                double* __restrict__ diag, int32_t* __restrict__ off_ptr,
+                                IngestScratch* sc) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int32_t lo = row_ptr[r], hi = row_ptr[r + 1];
+  int flags = 0;
+  if (lo < 0 || hi > nnz || hi < lo) {  // never read outside col/vals
+    flags |= kFlagArg;
+    lo = hi = 0;
+  }
+  const int32_t cmin = row_lo ? row_lo[r] : 0;
+  const int32_t cmax = row_hi ? row_hi[r] : n;
+  int32_t prev = -1;
+  int ndiag = 0;
+  double dv = 0.0, maxabs = 0.0;
+  for (int32_t e = lo; e < hi; ++e) {
+    const int32_t c = col[e];
+    const double v = vals[e];
+    if (c < cmin || c >= cmax || c <= prev) flags |= kFlagArg;
+    prev = c;
+    if (!isfinite(v)) flags |= kFlagNonfinite;
+    if (c == r) {
+      ++ndiag;
+      dv = v;
+    }
+    maxabs = fmax(maxabs, fabs(v));
+  }
+  if (ndiag != 1 || dv == 0.0) flags |= kFlagZeroDiag;
+  diag[r] = dv;
+  off_ptr[r] = lo - r;
+  if (r == n - 1) off_ptr[n] = hi - n;
+  if (flags) atomicOr(&sc->flags, flags);
+  if (isfinite(maxabs)) atomicMax(&sc->maxabs_bits, (unsigned long long)__double_as_longlong(maxabs));
+  atomicMax(&sc->max_degree, hi - lo - ndiag);
+}
+
+__global__ void k_split(int32_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                        const double* __restrict__ vals, const int32_t* __restrict__ off_ptr,
+                        int32_t* __restrict__ off_col, double* __restrict__ a64, float* __restrict__ a32) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int32_t k = off_ptr[r];
+  for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+    const int32_t c = col[e];
+    if (c == r) continue;
+    off_col[k] = c;
+    a64[k] = vals[e];
+    a32[k] = (float)vals[e];
+    ++k;
+  }
+}
+
+// rev[s] for every slot of row r: binary search for column r in row col[s].
+__global__ void k_reverse(int32_t n, const int32_t* __restrict__ off_ptr,
+                          const int32_t* __restrict__ off_col, const double* __restrict__ a64,
+                          int32_t* __restrict__ rev, IngestScratch* sc) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double tolv = 1e-12 * __longlong_as_double((long long)sc->maxabs_bits);
+  int flags = 0;
+  for (int32_t s = off_ptr[r]; s < off_ptr[r + 1]; ++s) {
+    const int32_t c = off_col[s];
+    int32_t lo = off_ptr[c], hi = off_ptr[c + 1] - 1, found = -1;
+    while (lo <= hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      const int32_t v = off_col[mid];
+      if (v == r) {
+        found = mid;
+        break;
+      }
+      if (v < r) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (found < 0) {
+      flags |= kFlagAsym;
+      rev[s] = s;  // keeps every later gather in bounds
+      continue;
+    }
+    rev[s] = found;
+    if (fabs(a64[s] - a64[found]) > tolv) flags |= kFlagAsym;
+  }
+  if (flags) atomicOr(&sc->flags, flags);
+}
+
+__global__ void k_fill_rows_of_system(int32_t num_sys, const int32_t* __restrict__ sys_row_off,
+                                      int32_t* __restrict__ row_lo, int32_t* __restrict__ row_hi) {
+  const int32_t s = blockIdx.x;
+  if (s >= num_sys) return;
+  const int32_t lo = sys_row_off[s], hi = sys_row_off[s + 1];
+  for (int32_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+    row_lo[r] = lo;
+    row_hi[r] = hi;
+  }
+}
+
+}  // namespace
+
+gabp_status dev_alloc(Ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(c, GABP_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(*p);
+  c->device_bytes += (int64_t)bytes;
+  return GABP_OK;
+}
+
+#define GABP_TRY(x)                   \
+  do {                                \
+    gabp_status s_ = (x);             \
+    if (s_ != GABP_OK) return s_;     \
+  } while (0)
+
+gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const double* vals,
+                   const int32_t* sys_row_off_d, int32_t num_sys) {
+  hipStream_t s = c->stream;
+  const int32_t n = c->n;
+  int32_t bounds[2] = {0, 0};
+  GABP_HIP(c, hipMemcpyAsync(&bounds[0], row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipMemcpyAsync(&bounds[1], row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  if (bounds[0] != 0 || bounds[1] < n)
+    return fail(c, GABP_E_ARG, "row_ptr[0] must be 0 and row_ptr[n] >= n (diagonal stored)");
+  c->nnz = bounds[1];
+  c->E = (int64_t)c->nnz - n;
+
+  GABP_TRY(dev_alloc(c, (void**)&c->row_ptr_d, sizeof(int32_t) * (n + 1)));
+  GABP_TRY(dev_alloc(c, (void**)&c->col_d, sizeof(int32_t) * c->nnz));
+  GABP_HIP(c, hipMemcpyAsync(c->row_ptr_d, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+  GABP_HIP(c, hipMemcpyAsync(c->col_d, col, sizeof(int32_t) * c->nnz, hipMemcpyDeviceToDevice, s));
+
+  GABP_TRY(dev_alloc(c, (void**)&c->off_ptr_d, sizeof(int32_t) * (n + 1)));
+  GABP_TRY(dev_alloc(c, (void**)&c->d64_d, sizeof(double) * n));
+  GABP_TRY(dev_alloc(c, (void**)&c->off_col_d, sizeof(int32_t) * c->E));
+  GABP_TRY(dev_alloc(c, (void**)&c->rev_d, sizeof(int32_t) * c->E));
+  GABP_TRY(dev_alloc(c, (void**)&c->a64_d, sizeof(double) * c->E));
+  GABP_TRY(dev_alloc(c, (void**)&c->a32_d, sizeof(float) * c->E));
+
+  IngestScratch* sc = nullptr;
+  GABP_TRY(dev_alloc(c, (void**)&sc, sizeof(IngestScratch)));
+  GABP_HIP(c, hipMemsetAsync(sc, 0, sizeof(IngestScratch), s));
+
+  int32_t* row_lo = nullptr;
+  int32_t* row_hi = nullptr;
+  const int threads = 256;
+  const int blocks = (n + threads - 1) / threads;
+  if (sys_row_off_d != nullptr && num_sys > 0) {
+    // rows of system s may only reference columns of system s
+    GABP_TRY(dev_alloc(c, (void**)&row_lo, sizeof(int32_t) * n));
+    GABP_TRY(dev_alloc(c, (void**)&row_hi, sizeof(int32_t) * n));
+    hipLaunchKernelGGL(k_fill_rows_of_system, dim3(num_sys), dim3(256), 0, s, num_sys, sys_row_off_d,
+                       row_lo, row_hi);
+    GABP_HIP(c, hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_validate_rows, dim3(blocks), dim3(threads), 0, s, n, c->nnz, row_ptr, col, vals,
+                     row_lo, row_hi, c->d64_d, c->off_ptr_d, sc);
+  GABP_HIP(c, hipGetLastError());
+  IngestScratch h{};
+  GABP_HIP(c, hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  if (h.flags & kFlagArg)
+    return fail(c, GABP_E_ARG, "CSR structure: row pointers decrease, columns unsorted/duplicated or out of range");
+  if (h.flags & kFlagNonfinite) return fail(c, GABP_E_NONFINITE, "non-finite matrix value");
+  if (h.flags & kFlagZeroDiag) return fail(c, GABP_E_ZERO_DIAG, "a diagonal entry is missing or zero");
+  c->max_degree = h.max_degree;
+
+  if (c->E > 0) {
+    hipLaunchKernelGGL(k_split, dim3(blocks), dim3(threads), 0, s, n, row_ptr, col, vals,
+                       c->off_ptr_d, c->off_col_d, c->a64_d, c->a32_d);
+    GABP_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_reverse, dim3(blocks), dim3(threads), 0, s, n, c->off_ptr_d, c->off_col_d,
+                       c->a64_d, c->rev_d, sc);
+    GABP_HIP(c, hipGetLastError());
+    GABP_HIP(c, hipMemcpyAsync(&h, sc, sizeof(h), hipMemcpyDeviceToHost, s));
+    GABP_HIP(c, hipStreamSynchronize(s));
+    if (h.flags & kFlagAsym) return fail(c, GABP_E_NOT_SYMMETRIC, "pattern or values of A are not symmetric");
+  }
+
+  c->off_ptr_h.resize(n + 1);
+  GABP_HIP(c, hipMemcpyAsync(c->off_ptr_h.data(), c->off_ptr_d, sizeof(int32_t) * (n + 1),
+                             hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  return GABP_OK;
+}
+
+// Greedy packing of whole rows into workgroups of at most 256*K slots and 256
+// rows; a row longer than 256*K gets a workgroup of its own (handled by the
+// sweep kernel's long-row path).
+gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
+  const int64_t cap = (int64_t)kBlock * K;
+  blk_row.clear();
+  blk_row.push_back(0);
+  int64_t slots = 0;
+  int32_t rows = 0;
+  const auto& op = c->off_ptr_h;
+  for (int32_t r = 0; r < c->n; ++r) {
+    const int64_t d = op[r + 1] - op[r];
+    if (rows > 0 && (slots + d > cap || rows == kMaxRowsPerBlock)) {
+      blk_row.push_back(r);
+      slots = 0;
+      rows = 0;
+    }
+    slots += d;
+    ++rows;
+    if (d > cap) {  // close a long row's workgroup at once
+      blk_row.push_back(r + 1);
+      slots = 0;
+      rows = 0;
+    }
+  }
+  if (blk_row.back() != c->n) blk_row.push_back(c->n);
+  return GABP_OK;
+}
+
+gabp_status set_partition(Ctx* c, int K) {
+  std::vector<int32_t> br;
+  build_partition(c, K, br);
+  const int32_t nb = (int32_t)br.size() - 1;
+  if (c->blk_row_d == nullptr || nb > c->nblk_capacity) {
+    void* p = nullptr;
+    GABP_TRY(dev_alloc(c, &p, sizeof(int32_t) * (nb + 1)));
+    c->blk_row_d = (int32_t*)p;
+    c->nblk_capacity = nb;
+  }
+  GABP_HIP(c, hipMemcpyAsync(c->blk_row_d, br.data(), sizeof(int32_t) * (nb + 1),
+                             hipMemcpyHostToDevice, c->stream));
+  GABP_HIP(c, hipStreamSynchronize(c->stream));
+  c->K = K;
+  c->nblk = nb;
+  if (c->partials_d == nullptr || nb > c->partials_capacity) {
+    void* p = nullptr;
+    GABP_TRY(dev_alloc(c, &p, sizeof(double) * (nb + 1024)));
+    c->partials_d = (double*)p;
+    c->partials_capacity = nb;
+  }
+  return GABP_OK;
+}
+
+}  // namespace gabp

@@ -1,0 +1,445 @@
+// Host drivers: the synchronous sweep loop, the outer correction loop
+// (iterative refinement / diagonal loading of Ch. 5), the adjoint solve and
+// the block-size autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+namespace {
+
+struct RunCfg {
+  bool honly = false;           // frozen precisions, h-only sweeps
+  const void* rhs = nullptr;    // T [n]
+  const void* diag = nullptr;   // T [n]
+  const double* rhs_norm = nullptr;
+  double tol = 0.0;             // <= 0: exactly max_iter sweeps
+  int max_iter = 0;
+  int check_every = 1;
+  void* x2[2] = {nullptr, nullptr};   // T [n] x by round parity
+  void* pt2[2] = {nullptr, nullptr};  // T [n] P~ by round parity (nullable)
+  DevStatus* st = nullptr;
+};
+
+template <typename T>
+const T* coef_array(const Ctx* c) {
+  if constexpr (sizeof(T) == 8) return (const T*)c->a64_d;
+  else return (const T*)c->a32_d;
+}
+
+// Enqueue the sweeps of one solve: rounds 1..max_iter of Alg. 2 (mode joint
+// or h-only), then the aggregates of round max_iter and a last residual check.
+// Sweep t produces the messages of round t and the means x of round t-1; it
+// checks x of round t-2.  The host polls the device status once per chunk of
+// sweeps while the next chunk runs; sweeps enqueued after convergence return
+// immediately.  Does not wait for the last chunk.
+template <typename T>
+gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+  hipStream_t s = c->stream;
+  const bool exact = cfg.tol <= 0.0;
+  const int M = cfg.max_iter;
+  const int ce = std::max(1, cfg.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+
+  SweepArgs<T> a{};
+  a.blk_row = c->blk_row_d;
+  a.off_ptr = c->off_ptr_d;
+  a.off_col = c->off_col_d;
+  a.rev = c->rev_d;
+  a.a = coef_array<T>(c);
+  a.diag = (const T*)cfg.diag;
+  a.rhs = (const T*)cfg.rhs;
+  a.gcoef = (const T*)c->gcoef_d;
+  a.inv_pt = (const T*)c->inv_pt_d;
+  a.partials = c->partials_d;
+  a.st = cfg.st;
+  a.rhs_norm = cfg.rhs_norm;
+  a.nblk = c->nblk;
+  a.tol = exact ? -1.0 : cfg.tol;
+  GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
+
+  const int main_mode = cfg.honly ? kHOnly : kJoint;
+  const int last = M + 2;
+  int t = 1, chunk = 2, pending = -1, slot = 0;
+  bool stop = false;
+  while (t <= last && !stop) {
+    const int tend = std::min(last, t + chunk - 1);
+    for (; t <= tend; ++t) {
+      int mode;
+      if (t <= M) mode = main_mode;
+      else if (t == M + 1) mode = cfg.honly ? kHOnly : kAgg;
+      else mode = kResid;
+      const int j = t - 1;
+      SweepArgs<T> k = a;
+      k.zero_in = (t == 1);
+      k.min = c->msg_d[(t - 1) & 1];
+      k.mout = c->msg_d[t & 1];
+      const bool wx = (mode != kResid) && (exact ? (t == M + 1) : in_set(j));
+      k.xout = wx ? (T*)cfg.x2[j & 1] : nullptr;
+      k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[j & 1] : nullptr;
+      const bool ck = (t >= 2) && (exact ? (t == M + 2) : in_set(t - 2));
+      k.check = ck ? 1 : 0;
+      k.xchk = (const T*)cfg.x2[(t - 2) & 1];
+      k.round_checked = t - 2;
+      if (mode == kResid && !ck) continue;
+      const bool timed = (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck &&
+                         c->tev_used + 2 <= (int)c->tev.size();
+      if (timed) GABP_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
+      GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s));
+      if (timed) {
+        GABP_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+        c->tev_used += 2;
+        c->timed_mode = cfg.honly ? 1 : 0;
+      }
+    }
+    GABP_HIP(c, hipMemcpyAsync(&c->st_h[slot], cfg.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    GABP_HIP(c, hipEventRecord(c->ev[slot], s));
+    if (pending >= 0) {
+      GABP_HIP(c, hipEventSynchronize(c->ev[pending]));
+      if (c->st_h[pending].done) stop = true;
+    }
+    pending = slot;
+    slot ^= 1;
+    chunk = std::min(chunk * 2, 16);
+  }
+  return GABP_OK;
+}
+
+// Sum the recorded sweep durations (after the stream has been synchronised).
+gabp_status collect_timing(Ctx* c) {
+  for (int i = 0; i + 1 < c->tev_used; i += 2) {
+    float ms = 0.f;
+    GABP_HIP(c, hipEventElapsedTime(&ms, c->tev[i], c->tev[i + 1]));
+    c->sweep_ms += ms;
+    c->timed_sweeps += 1;
+  }
+  c->tev_used = 0;
+  return GABP_OK;
+}
+
+void reset_timing(Ctx* c) {
+  c->tev_used = 0;
+  c->sweep_ms = 0.0;
+  c->timed_sweeps = 0;
+}
+
+void report_timing(const Ctx* c, gabp_info* info) {
+  if (!info) return;
+  info->sweep_ms = c->sweep_ms;
+  info->timed_sweeps = c->timed_sweeps;
+  info->sweep_mode = c->timed_mode;
+}
+
+gabp_status read_status(Ctx* c, const DevStatus* st_d, DevStatus* out) {
+  GABP_HIP(c, hipMemcpyAsync(&c->st_h[2], st_d, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+  GABP_HIP(c, hipStreamSynchronize(c->stream));
+  *out = c->st_h[2];
+  return collect_timing(c);
+}
+
+// Freeze the precisions of the messages of round `round`: coefficient
+// g_s = -A_ij / (P~_i - P_ji) per slot and 1 / P~_i per node, so that later
+// sweeps update the h messages only (the P update has no b term).
+template <typename T>
+gabp_status freeze(Ctx* c, int round, const void* diag, const void* rhs, int prec) {
+  SweepArgs<T> k{};
+  k.blk_row = c->blk_row_d;
+  k.off_ptr = c->off_ptr_d;
+  k.off_col = c->off_col_d;
+  k.rev = c->rev_d;
+  k.a = coef_array<T>(c);
+  k.diag = (const T*)diag;
+  k.rhs = (const T*)rhs;
+  k.min = c->msg_d[round & 1];
+  k.zero_in = (round == 0);
+  k.gcoef_out = (T*)c->gcoef_d;
+  k.inv_pt_out = (T*)c->inv_pt_d;
+  k.partials = c->partials_d;
+  k.st = c->st_d + 1;  // fresh status: the freeze must not be skipped
+  k.nblk = c->nblk;
+  GABP_HIP(c, launch_reset_status(k.st, 1, c->stream));
+  GABP_HIP(c, launch_sweep<T>(kFreeze, c->K, k, c->stream));
+  c->frozen_valid = true;
+  c->frozen_prec = prec;
+  return GABP_OK;
+}
+
+gabp_status map_status(Ctx* c, const DevStatus& st, bool exact) {
+  if (st.error & kErrNonfinite) return fail(c, GABP_E_NONFINITE, "non-finite message (P~_i = P_ji or overflow)");
+  if (!exact && (st.error & kErrDiverged)) return fail(c, GABP_E_DIVERGED, "residual diverged");
+  if (exact || st.conv_round >= 0) return GABP_OK;
+  return GABP_NOT_CONVERGED;
+}
+
+}  // namespace
+
+gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double tol, int32_t max_iter,
+                        gabp_info* info, bool allow_reuse) {
+  hipStream_t s = c->stream;
+  const bool exact = tol <= 0.0;
+  const bool honly = allow_reuse && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) && c->frozen_valid &&
+                     c->frozen_prec == GABP_FP64 && !exact;
+  reset_timing(c);
+  GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
+  RunCfg cfg;
+  cfg.honly = honly;
+  cfg.rhs = b;
+  cfg.diag = c->din64_d;
+  cfg.rhs_norm = c->norms_d;
+  cfg.tol = tol;
+  cfg.max_iter = max_iter;
+  cfg.check_every = c->opts.check_every;
+  cfg.x2[0] = c->x64_d[0];
+  cfg.x2[1] = c->x64_d[1];
+  if (var && !honly) {
+    cfg.pt2[0] = c->pt64_d[0];
+    cfg.pt2[1] = c->pt64_d[1];
+  }
+  cfg.st = c->st_d;
+  gabp_status rs = run_sweeps<double>(c, cfg);
+  if (rs != GABP_OK) return rs;
+  const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
+  const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
+  GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
+  if (var && honly) GABP_HIP(c, hipMemcpyAsync(var, c->inv_pt_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
+  DevStatus st;
+  gabp_status r = read_status(c, c->st_d, &st);
+  if (r != GABP_OK) return r;
+  r = map_status(c, st, exact);
+  const int sweeps = st.conv_round >= 0 ? st.conv_round : max_iter;
+  if (info) {
+    info->sweeps = sweeps;
+    info->outer_iters = 0;
+    info->converged = (st.conv_round >= 0) ? 1 : 0;
+    info->status = r;
+    info->rel_residual = st.last_rel;
+    info->gamma = 0.0;
+    report_timing(c, info);
+  }
+  c->last_msg_round = (exact && !honly && r == GABP_OK) ? max_iter : -1;
+  if (r == GABP_OK && !exact && !honly && (c->opts.flags & GABP_FLAG_REUSE_PRECISION)) {
+    // latest round whose messages were written: sweeps stop two rounds after
+    // the converged one (lagged check) or at max_iter
+    const int last = std::min(st.conv_round + 2, max_iter);
+    gabp_status fr = freeze<double>(c, last, c->din64_d, b, GABP_FP64);
+    if (fr != GABP_OK) return fr;
+    GABP_HIP(c, hipStreamSynchronize(s));
+  }
+  return r;
+}
+
+gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter, gabp_info* info) {
+  hipStream_t s = c->stream;
+  const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
+  const int prec = c->opts.precision;
+  reset_timing(c);
+  GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
+  DevStatus* st_out = c->st_d + 1;
+  DevStatus* st_in = c->st_d;
+
+  OuterArgs o{};
+  o.blk_row = c->blk_row_d;
+  o.off_ptr = c->off_ptr_d;
+  o.off_col = c->off_col_d;
+  o.a = c->a64_d;
+  o.diag = c->d64_d;
+  o.b = b;
+  o.xold = nullptr;
+  o.xnew = c->xo_d[0];
+  o.d32[0] = c->x32_d[0];
+  o.d32[1] = c->x32_d[1];
+  o.d64[0] = fp32 ? nullptr : c->x64_d[0];
+  o.d64[1] = fp32 ? nullptr : c->x64_d[1];
+  o.st_in = st_in;
+  o.use_d = 0;
+  o.rin32 = fp32 ? c->rin32_d : nullptr;
+  o.rin64 = fp32 ? nullptr : c->rin64_d;
+  o.partials = c->partials_d;
+  o.st = st_out;
+  o.b_norm = c->norms_d;
+  o.r_norm = c->norms_d + 1;
+  o.tol = tol;
+  o.nblk = c->nblk;
+  o.n = c->n;
+  GABP_HIP(c, launch_reset_status(st_out, 1, s));
+  GABP_HIP(c, launch_outer(c->K, o, s));
+  DevStatus so, si;
+  gabp_status r = read_status(c, st_out, &so);
+  if (r != GABP_OK) return r;
+
+  int cur = 0, k = 0, total = 0;
+  gabp_status result = GABP_NOT_CONVERGED;
+  for (;;) {
+    if (so.error & (kErrDiverged | kErrNonfinite)) {
+      result = fail(c, GABP_E_DIVERGED, "outer residual diverged");
+      break;
+    }
+    if (so.conv_round >= 0) {
+      result = GABP_OK;
+      break;
+    }
+    if (k >= c->opts.max_outer || total >= max_iter) break;
+    const int budget = std::max(0, std::min(c->opts.inner_max_iter, max_iter - total));
+    RunCfg cfg;
+    cfg.honly = c->frozen_valid && c->frozen_prec == prec;
+    cfg.rhs = fp32 ? (const void*)c->rin32_d : (const void*)c->rin64_d;
+    cfg.diag = fp32 ? (const void*)c->din32_d : (const void*)c->din64_d;
+    cfg.rhs_norm = c->norms_d + 1;
+    cfg.tol = c->opts.inner_tol;
+    cfg.max_iter = budget;
+    cfg.check_every = c->opts.check_every;
+    cfg.x2[0] = fp32 ? (void*)c->x32_d[0] : (void*)c->x64_d[0];
+    cfg.x2[1] = fp32 ? (void*)c->x32_d[1] : (void*)c->x64_d[1];
+    cfg.st = st_in;
+    r = fp32 ? run_sweeps<float>(c, cfg) : run_sweeps<double>(c, cfg);
+    if (r != GABP_OK) return r;
+    r = read_status(c, st_in, &si);
+    if (r != GABP_OK) return r;
+    if (si.error & kErrNonfinite) return fail(c, GABP_E_NONFINITE, "non-finite inner message");
+    if (si.error & kErrDiverged) {
+      result = fail(c, GABP_E_DIVERGED,
+                    "inner GaBP diverged (the inner matrix is not walk-summable: use diagonal loading)");
+      break;
+    }
+    const int used = si.conv_round >= 0 ? si.conv_round : budget;
+    total += used;
+    if (!cfg.honly && si.conv_round >= 0) {
+      const int last = std::min(si.conv_round + 2, budget);
+      r = fp32 ? freeze<float>(c, last, cfg.diag, cfg.rhs, prec) : freeze<double>(c, last, cfg.diag, cfg.rhs, prec);
+      if (r != GABP_OK) return r;
+    }
+    o.xold = c->xo_d[cur];
+    o.xnew = c->xo_d[cur ^ 1];
+    o.use_d = 1;
+    o.in_fallback = budget;
+    GABP_HIP(c, launch_reset_status(st_out, 1, s));
+    GABP_HIP(c, launch_outer(c->K, o, s));
+    cur ^= 1;
+    ++k;
+    r = read_status(c, st_out, &so);
+    if (r != GABP_OK) return r;
+  }
+  GABP_HIP(c, hipMemcpyAsync(x, c->xo_d[cur], sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  if (info) {
+    info->sweeps = total;
+    info->outer_iters = k;
+    info->converged = so.conv_round >= 0 ? 1 : 0;
+    info->status = result;
+    info->rel_residual = so.last_rel;
+    info->gamma = c->gamma_used;
+    report_timing(c, info);
+  }
+  c->last_msg_round = -1;
+  return result;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: slots per workgroup
+// ---------------------------------------------------------------------------
+
+namespace {
+
+std::string tune_key(const Ctx* c) {
+  int nb = 0;
+  while ((1LL << (nb + 1)) <= (long long)std::max(1, c->n)) ++nb;
+  const double avg = c->n ? (double)c->E / c->n : 0.0;
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d", c->opts.precision == GABP_FP32_REFINE ? 32 : 64, nb,
+                (int)std::lround(avg), c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256));
+  return buf;
+}
+
+int cache_lookup(const std::string& path, const std::string& key) {
+  std::ifstream f(path);
+  std::string line;
+  int best = 0;
+  while (std::getline(f, line)) {
+    const std::string pat = "\"key\": \"" + key + "\"";
+    if (line.find(pat) == std::string::npos) continue;
+    const auto p = line.find("\"K\": ");
+    if (p != std::string::npos) best = std::atoi(line.c_str() + p + 5);
+  }
+  return (best == 2 || best == 4 || best == 8) ? best : 0;
+}
+
+void cache_store(const std::string& path, const std::string& key, int K, const double* ms) {
+  std::ofstream f(path, std::ios::app);
+  if (!f) return;
+  f << "{\"key\": \"" << key << "\", \"K\": " << K << ", \"ms_per_sweep\": {\"2\": " << ms[0]
+    << ", \"4\": " << ms[1] << ", \"8\": " << ms[2] << "}}\n";
+}
+
+template <typename T>
+gabp_status time_candidate(Ctx* c, int K, const void* ones, const void* diag, float* ms_out) {
+  gabp_status r = set_partition(c, K);
+  if (r != GABP_OK) return r;
+  RunCfg cfg;
+  cfg.rhs = ones;
+  cfg.diag = diag;
+  cfg.rhs_norm = c->norms_d;
+  cfg.tol = 0.0;
+  cfg.max_iter = 6;
+  cfg.x2[0] = sizeof(T) == 8 ? (void*)c->x64_d[0] : (void*)c->x32_d[0];
+  cfg.x2[1] = sizeof(T) == 8 ? (void*)c->x64_d[1] : (void*)c->x32_d[1];
+  cfg.st = c->st_d;
+  hipEvent_t e0, e1;
+  GABP_HIP(c, hipEventCreate(&e0));
+  GABP_HIP(c, hipEventCreate(&e1));
+  r = run_sweeps<T>(c, cfg);  // warm-up
+  if (r == GABP_OK) {
+    GABP_HIP(c, hipEventRecord(e0, c->stream));
+    r = run_sweeps<T>(c, cfg);
+    GABP_HIP(c, hipEventRecord(e1, c->stream));
+    GABP_HIP(c, hipEventSynchronize(e1));
+    GABP_HIP(c, hipEventElapsedTime(ms_out, e0, e1));
+    *ms_out /= (cfg.max_iter + 2);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return r;
+}
+
+}  // namespace
+
+gabp_status autotune(Ctx* c) {
+  const int epb = c->opts.edges_per_block;
+  if (epb != 0) return set_partition(c, epb / kBlock);
+  if (c->E < 200000) return set_partition(c, 4);
+  const std::string key = tune_key(c);
+  const char* path = std::getenv("GABP_AUTOTUNE_CACHE");
+  if (path && *path) {
+    const int K = cache_lookup(path, key);
+    if (K) return set_partition(c, K);
+  }
+  const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
+  // right-hand side: the diagonal itself (any finite vector will do)
+  const void* rhs = fp32 ? (const void*)c->din32_d : (const void*)c->din64_d;
+  GABP_HIP(c, launch_fill(c->norms_d, 1, 1.0, c->stream));
+  const int Ks[3] = {2, 4, 8};
+  double ms[3] = {0, 0, 0};
+  int best = 4;
+  float best_ms = 1e30f;
+  for (int i = 0; i < 3; ++i) {
+    float t = 0.f;
+    gabp_status r = fp32 ? time_candidate<float>(c, Ks[i], rhs, rhs, &t)
+                         : time_candidate<double>(c, Ks[i], rhs, rhs, &t);
+    if (r != GABP_OK) return r;
+    ms[i] = t;
+    if (t < best_ms) {
+      best_ms = t;
+      best = Ks[i];
+    }
+  }
+  if (path && *path) cache_store(path, key, best, ms);
+  return set_partition(c, best);
+}
+
+}  // namespace gabp

@@ -1,0 +1,574 @@
+// Synchronous broadcast GaBP sweep kernels for gfx950 (wave64).
+//
+// One launch = one round of Alg. 2 (Ch. 3 Sec. 3.3) over the whole graph.
+// Messages live in "outgoing" slot order: slot s = (i, j) of the off-diagonal
+// CSR holds the message i -> j, in information form (P_ij, h_ij = P_ij mu_ij).
+// A workgroup owns a contiguous group of rows i and, for every slot of those
+// rows,
+//   1. gathers the reverse message j -> i = msg[rev[s]] (the only irregular
+//      access), coalesced reads of rev[] and a[] in slot order,
+//   2. forms the node aggregates of Alg. 2 step 2, P~_i = A_ii + sum_k P_ki and
+//      h~_i = b_i + sum_k h_ki, with one lane per row over the row segment
+//      staged in LDS; x_i = h~_i / P~_i is the tentative mean of the round,
+//   3. writes the new outgoing messages, subtracting the reverse message
+//      (broadcast form): D = P~_i - P_ji, P_ij = -A_ij^2 / D,
+//      h_ij = -A_ij (h~_i - h_ji) / D  (the mean rule of Alg. 2 multiplied by
+//      P_ij), coalesced in slot order.
+// Steps 2 and 3 of the paper's round are thus fused: the aggregate of node i is
+// formed once, in registers/LDS, and never written to HBM.  Optionally the same
+// launch checks the residual b - A x of the previous round's x (fused
+// convergence check, wave64 reductions, deterministic last-workgroup total).
+#include <algorithm>
+#include <cmath>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<double> {
+  using type = double2;
+};
+template <>
+struct PairOf<float> {
+  using type = float2;
+};
+
+// Workgroups are dealt round-robin over the 8 XCDs of the chip.  Give each
+// XCD a contiguous range of logical row groups so that rows that exchange
+// messages (neighbours in a banded or grid ordering) share one L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int q = nb / kXcd, rem = nb % kXcd;
+  const int x = b % kXcd, j = b / kXcd;
+  return x * q + min(x, rem) + j;
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic sum over the 256 lanes of a workgroup (fixed reduction tree).
+template <typename V>
+__device__ __forceinline__ V block_sum(V v, V* s_red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Residual bookkeeping shared by the sweep and outer kernels: every workgroup
+// stores its partial sum of r_i^2; the last to arrive adds the partials in
+// index order and updates the status.
+__device__ void finish_check(double res2, double* s_red, int* s_last, double* partials, DevStatus* st,
+                             int nblk, int b, const double* rhs_norm, double tol, int round,
+                             double* norm_out) {
+  const double bs = block_sum(res2, s_red);
+  if (threadIdx.x == 0) {
+    partials[b] = bs;
+    __threadfence();
+    const unsigned tk = atomicAdd(&st->ticket, 1u);
+    *s_last = (tk == (unsigned)nblk - 1);
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  __threadfence();
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kBlock) v += load_coherent(partials + i);
+  const double tot = block_sum(v, s_red);
+  if (threadIdx.x == 0) {
+    const double nb = *rhs_norm;
+    const double rn = sqrt(tot);
+    const double rel = nb > 0.0 ? rn / nb : rn;
+    if (norm_out) *norm_out = rn;
+    st->last_rel = rel;
+    st->last_round = round;
+    if (rel <= tol) {
+      st->conv_round = round;
+      st->done = 1;
+    } else if (!(rel <= kDivergeLimit)) {
+      st->error |= kErrDiverged;
+      st->done = 1;
+    }
+    st->ticket = 0;
+  }
+}
+
+// LDS layout of the sweep kernel (bytes): row aggregates, staged incoming
+// messages, staged a_ij x_j products, row pointers, local row of each slot.
+__host__ __device__ constexpr size_t lds_layout(int K, int elt, bool joint) {
+  return (size_t)elt * (2 * kMaxRowsPerBlock + (size_t)kBlock * K * (joint ? 3 : 2)) +
+         sizeof(int32_t) * (kMaxRowsPerBlock + 4) + (size_t)kBlock * K;
+}
+
+size_t sweep_lds_bytes(int K, int elt, bool joint) { return lds_layout(K, elt, joint); }
+
+template <typename T, int MODE>
+__device__ double long_row(const SweepArgs<T>& A, int r, int e0, int ne, T* s_redT, double* s_red,
+                           T* s_bc) {
+  using P2 = typename PairOf<T>::type;
+  constexpr bool kJointLike = (MODE == kJoint || MODE == kAgg || MODE == kFreeze);
+  const int tid = threadIdx.x;
+  T pP = 0, ph = 0;
+  double pax = 0.0;
+  for (int i = tid; i < ne; i += kBlock) {
+    const int s = e0 + i;
+    if (MODE != kResid && !A.zero_in) {
+      const int rv = A.rev[s];
+      if (MODE == kHOnly) {
+        ph += ((const T*)A.min)[rv];
+      } else {
+        const P2 m = ((const P2*)A.min)[rv];
+        pP += m.x;
+        ph += m.y;
+      }
+    }
+    if (A.check) pax += (double)(A.a[s] * A.xchk[A.off_col[s]]);
+  }
+  pP = block_sum(pP, s_redT);
+  ph = block_sum(ph, s_redT);
+  pax = block_sum(pax, s_red);
+  double res2 = 0.0;
+  if (tid == 0) {
+    T Pt = kJointLike ? A.diag[r] + pP : T(0);
+    const T ht = A.rhs[r] + ph;
+    if (MODE != kResid) {
+      const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
+      if (A.xout) A.xout[r] = xr;
+      if (A.ptout && kJointLike) A.ptout[r] = Pt;
+      if (MODE == kFreeze) A.inv_pt_out[r] = T(1) / Pt;
+    }
+    if (A.check) {
+      const double acc = (double)A.rhs[r] - (double)A.diag[r] * (double)A.xchk[r] - pax;
+      res2 = acc * acc;
+    }
+    s_bc[0] = Pt;
+    s_bc[1] = ht;
+  }
+  __syncthreads();
+  if (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) {
+    const T Pt = s_bc[0], ht = s_bc[1];
+    bool bad = false;
+    for (int i = tid; i < ne; i += kBlock) {
+      const int s = e0 + i;
+      T pin = 0, hin = 0;
+      if (!A.zero_in) {
+        const int rv = A.rev[s];
+        if (MODE == kHOnly) {
+          hin = ((const T*)A.min)[rv];
+        } else {
+          const P2 m = ((const P2*)A.min)[rv];
+          pin = m.x;
+          hin = m.y;
+        }
+      }
+      if (MODE == kHOnly) {
+        const T hn = A.gcoef[s] * (ht - hin);
+        ((T*)A.mout)[s] = hn;
+        bad |= !isfinite(hn);
+      } else {
+        const T av = A.a[s];
+        const T inv = T(1) / (Pt - pin);
+        if (MODE == kFreeze) {
+          A.gcoef_out[s] = -av * inv;
+          bad |= !isfinite(inv);
+        } else {
+          P2 m;
+          m.x = -av * av * inv;
+          m.y = -av * (ht - hin) * inv;
+          ((P2*)A.mout)[s] = m;
+          bad |= !(isfinite(m.x) && isfinite(m.y));
+        }
+      }
+    }
+    if (bad) {
+      atomicOr(&A.st->error, kErrNonfinite);
+      atomicExch(&A.st->done, 1);
+    }
+  }
+  return res2;
+}
+
+template <typename T, int K, int MODE>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
+  using P2 = typename PairOf<T>::type;
+  constexpr bool kJointLike = (MODE == kJoint || MODE == kAgg || MODE == kFreeze);
+  constexpr int S = kBlock * K;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[kBlock / 64];
+  __shared__ T s_redT[kBlock / 64];
+  __shared__ T s_bc[2];
+  __shared__ int s_flag;
+
+  const int tid = threadIdx.x;
+  if (tid == 0) s_flag = __hip_atomic_load(&A.st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (s_flag) return;
+
+  const int b = xcd_remap(blockIdx.x, A.nblk);
+  const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
+  const int nrow = r1 - r0;
+  const int e0 = A.off_ptr[r0];
+  const int ne = A.off_ptr[r1] - e0;
+  double res2 = 0.0;
+
+  if (ne > S) {
+    res2 = long_row<T, MODE>(A, r0, e0, ne, s_redT, s_red, s_bc);
+  } else {
+    T* s_Pt = (T*)smem;
+    T* s_ht = s_Pt + kMaxRowsPerBlock;
+    T* s_h = s_ht + kMaxRowsPerBlock;
+    T* s_ax = s_h + S;
+    T* s_P = s_ax + S;  // joint-like modes only
+    int32_t* s_ptr = (int32_t*)(s_P + (kJointLike ? S : 0));
+    uint8_t* s_row = (uint8_t*)(s_ptr + kMaxRowsPerBlock + 4);
+
+    for (int i = tid; i <= nrow; i += kBlock) s_ptr[i] = A.off_ptr[r0 + i] - e0;
+
+    // 1. slot phase: coalesced rev/a, gather of the reverse message
+    T pin[K], hin[K], coef[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * kBlock;
+      pin[k] = 0;
+      hin[k] = 0;
+      coef[k] = 0;
+      if (i < ne) {
+        const int s = e0 + i;
+        if (MODE != kResid) {
+          if (MODE == kHOnly) coef[k] = A.gcoef[s];
+          else if (MODE != kAgg) coef[k] = A.a[s];
+          if (!A.zero_in) {
+            const int rv = A.rev[s];
+            if (MODE == kHOnly) {
+              hin[k] = ((const T*)A.min)[rv];
+            } else {
+              const P2 m = ((const P2*)A.min)[rv];
+              pin[k] = m.x;
+              hin[k] = m.y;
+            }
+          }
+          if (kJointLike) s_P[i] = pin[k];
+          s_h[i] = hin[k];
+        }
+        if (A.check) {
+          const T av = (MODE == kJoint || MODE == kFreeze) ? coef[k] : A.a[s];
+          s_ax[i] = av * A.xchk[A.off_col[s]];
+        }
+      }
+    }
+    __syncthreads();
+
+    // 2. row phase: aggregates of Alg. 2 step 2, tentative mean, residual
+    if (tid < nrow) {
+      const int r = r0 + tid;
+      const int lo = s_ptr[tid], hi = s_ptr[tid + 1];
+      if (MODE != kResid) {
+        T Pt = kJointLike ? A.diag[r] : T(0);
+        T ht = A.rhs[r];
+        for (int j = lo; j < hi; ++j) {
+          if (kJointLike) Pt += s_P[j];
+          ht += s_h[j];
+          s_row[j] = (uint8_t)tid;
+        }
+        s_ht[tid] = ht;
+        s_Pt[tid] = Pt;
+        const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
+        if (A.xout) A.xout[r] = xr;
+        if (A.ptout && kJointLike) A.ptout[r] = Pt;
+        if (MODE == kFreeze) A.inv_pt_out[r] = T(1) / Pt;
+      }
+      if (A.check) {
+        double acc = (double)A.rhs[r] - (double)A.diag[r] * (double)A.xchk[r];
+        for (int j = lo; j < hi; ++j) acc -= (double)s_ax[j];
+        res2 = acc * acc;
+      }
+    }
+    __syncthreads();
+
+    // 3. edge phase: new outgoing messages, reverse message subtracted
+    if (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) {
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < ne) {
+          const int s = e0 + i;
+          const int lr = s_row[i];
+          if (MODE == kHOnly) {
+            const T hn = coef[k] * (s_ht[lr] - hin[k]);
+            ((T*)A.mout)[s] = hn;
+            bad |= !isfinite(hn);
+          } else {
+            const T inv = T(1) / (s_Pt[lr] - pin[k]);
+            const T av = coef[k];
+            if (MODE == kFreeze) {
+              A.gcoef_out[s] = -av * inv;
+              bad |= !isfinite(inv);
+            } else {
+              P2 m;
+              m.x = -av * av * inv;
+              m.y = -av * (s_ht[lr] - hin[k]) * inv;
+              ((P2*)A.mout)[s] = m;
+              bad |= !(isfinite(m.x) && isfinite(m.y));
+            }
+          }
+        }
+      }
+      if (bad) {
+        atomicOr(&A.st->error, kErrNonfinite);
+        atomicExch(&A.st->done, 1);
+      }
+    }
+  }
+
+  if (A.check)
+    finish_check(res2, s_red, &s_flag, A.partials, A.st, A.nblk, b, A.rhs_norm, A.tol,
+                 A.round_checked, nullptr);
+}
+
+template <typename T, int K>
+static hipError_t launch_k(int mode, const SweepArgs<T>& a, hipStream_t s) {
+  const bool joint = (mode == kJoint || mode == kAgg || mode == kFreeze);
+  const size_t lds = lds_layout(K, sizeof(T), joint);
+  const dim3 grid(a.nblk), block(kBlock);
+  switch (mode) {
+    case kJoint: hipLaunchKernelGGL((k_sweep<T, K, kJoint>), grid, block, lds, s, a); break;
+    case kHOnly: hipLaunchKernelGGL((k_sweep<T, K, kHOnly>), grid, block, lds, s, a); break;
+    case kAgg: hipLaunchKernelGGL((k_sweep<T, K, kAgg>), grid, block, lds, s, a); break;
+    case kFreeze: hipLaunchKernelGGL((k_sweep<T, K, kFreeze>), grid, block, lds, s, a); break;
+    case kResid: hipLaunchKernelGGL((k_sweep<T, K, kResid>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s) {
+  if (a.nblk <= 0) return hipSuccess;
+  switch (K) {
+    case 2: return launch_k<T, 2>(mode, a, s);
+    case 4: return launch_k<T, 4>(mode, a, s);
+    case 8: return launch_k<T, 8>(mode, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_sweep<double>(int, int, const SweepArgs<double>&, hipStream_t);
+template hipError_t launch_sweep<float>(int, int, const SweepArgs<float>&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// outer correction step (FP64): x_new = x_old + d, r = b - A x_new
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
+  constexpr int S = kBlock * K;
+  __shared__ double s_ax[S];
+  __shared__ int32_t s_ptr[kMaxRowsPerBlock + 4];
+  __shared__ double s_red[kBlock / 64];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x;
+  const int b = xcd_remap(blockIdx.x, A.nblk);
+  const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
+  const int nrow = r1 - r0;
+  const int e0 = A.off_ptr[r0];
+  const int ne = A.off_ptr[r1] - e0;
+  const DevStatus* si = A.st_in;
+  const int round = (si && si->conv_round >= 0) ? si->conv_round : A.in_fallback;
+  const float* d32 = A.d32[round & 1];
+  const double* d64 = A.d64[round & 1];
+  auto xat = [&](int c) -> double {
+    double v = A.xold ? A.xold[c] : 0.0;
+    if (A.use_d) v += d64 ? d64[c] : (double)d32[c];
+    return v;
+  };
+  double res2 = 0.0;
+  if (ne > S) {  // one long row
+    double p = 0.0;
+    for (int i = tid; i < ne; i += kBlock) p += A.a[e0 + i] * xat(A.off_col[e0 + i]);
+    p = block_sum(p, s_red);
+    if (tid == 0) {
+      const double xr = xat(r0);
+      A.xnew[r0] = xr;
+      const double res = A.b[r0] - A.diag[r0] * xr - p;
+      if (A.rin32) A.rin32[r0] = (float)res;
+      if (A.rin64) A.rin64[r0] = res;
+      res2 = res * res;
+    }
+  } else {
+    for (int i = tid; i <= nrow; i += kBlock) s_ptr[i] = A.off_ptr[r0 + i] - e0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * kBlock;
+      if (i < ne) s_ax[i] = A.a[e0 + i] * xat(A.off_col[e0 + i]);
+    }
+    __syncthreads();
+    if (tid < nrow) {
+      const int r = r0 + tid;
+      const double xr = xat(r);
+      A.xnew[r] = xr;
+      double res = A.b[r] - A.diag[r] * xr;
+      for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) res -= s_ax[j];
+      if (A.rin32) A.rin32[r] = (float)res;
+      if (A.rin64) A.rin64[r] = res;
+      res2 = res * res;
+    }
+  }
+  finish_check(res2, s_red, &s_flag, A.partials, A.st, A.nblk, b, A.b_norm, A.tol, 0, A.r_norm);
+}
+
+hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
+  if (a.nblk <= 0) return hipSuccess;
+  const dim3 grid(a.nblk), block(kBlock);
+  switch (K) {
+    case 2: hipLaunchKernelGGL(k_outer<2>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_outer<4>, grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_outer<8>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_reset_status(DevStatus* st, int count) {
+  const int i = threadIdx.x;
+  if (i < count) {
+    st[i].done = 0;
+    st[i].conv_round = -1;
+    st[i].error = 0;
+    st[i].ticket = 0;
+    st[i].last_rel = -1.0;
+    st[i].last_round = -1;
+    st[i].pad = 0;
+  }
+}
+
+hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, st, count);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ||v||_2 in two deterministic stages: per-workgroup partial sums, then one
+// workgroup adding them in index order.
+__global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* v, int64_t n, double* partials) {
+  __shared__ double s_red[kBlock / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    acc += v[i] * v[i];
+  acc = block_sum(acc, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sumsq_final(const double* partials, int nparts, double* out) {
+  __shared__ double s_red[kBlock / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) acc += partials[i];
+  acc = block_sum(acc, s_red);
+  if (threadIdx.x == 0) *out = sqrt(acc);
+}
+
+hipError_t launch_norm(const double* v, int64_t n, double* partials, int nparts, double* out,
+                       DevStatus*, hipStream_t s) {
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, nparts));
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(blocks), dim3(kBlock), 0, s, v, n, partials);
+  hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(kBlock), 0, s, partials, blocks, out);
+  return hipGetLastError();
+}
+
+// Final copy of the converged round (chosen on the device, no host sync):
+// x = x_round, var = 1 / P~_round.
+__global__ void k_copy_round(const double* x0, const double* x1, const double* p0, const double* p1,
+                             const DevStatus* st, int32_t fallback, double* x, double* var, int32_t n) {
+  const int round = st->conv_round >= 0 ? st->conv_round : fallback;
+  const double* xs = (round & 1) ? x1 : x0;
+  const double* ps = (round & 1) ? p1 : p0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] = xs[i];
+    if (var) var[i] = 1.0 / ps[i];
+  }
+}
+
+hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, const DevStatus* st,
+                             int32_t fallback_round, double* x, double* var, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_copy_round, dim3(blocks), dim3(256), 0, s, x2[0], x2[1], pt2 ? pt2[0] : nullptr,
+                     pt2 ? pt2[1] : nullptr, st, fallback_round, x, var, n);
+  return hipGetLastError();
+}
+
+// dL/dA on the stored pattern of the caller's CSR (tied mirror entries).
+__global__ void k_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
+                            double* gv, int32_t n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double lr = lam[r], xr = x[r];
+  for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+    const int32_t c = col[e];
+    gv[e] = (c == r) ? -lr * xr : -(lr * x[c] + lam[c] * xr);
+  }
+}
+
+hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam, const double* x,
+                            double* gv, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_vals, dim3((n + 255) / 256), dim3(256), 0, s, row_ptr, col, lam, x, gv, n);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double v = d[i] * f;
+    if (out64) out64[i] = v;
+    if (out32) out32[i] = (float)v;
+  }
+}
+
+hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_diag, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, d, f, out64, out32, n);
+  return hipGetLastError();
+}
+
+// De-interleave the FP64 message pairs into P and h arrays.
+__global__ void k_split_pairs(const double2* m, double* P, double* h, int64_t E) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = m[i];
+    P[i] = v.x;
+    h[i] = v.y;
+  }
+}
+
+hipError_t launch_split_pairs(const void* m, double* P, double* h, int64_t E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((E + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_split_pairs, dim3(blocks), dim3(256), 0, s, (const double2*)m, P, h, E);
+  return hipGetLastError();
+}
+
+}  // namespace gabp

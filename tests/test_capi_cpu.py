@@ -1,0 +1,42 @@
+"""CPU-side checks of the C ABI library: it loads and exports every declared symbol.
+
+No compute call is made here (no GPU in this environment).
+"""
+import os
+import re
+
+import paper_0811_2518_amd as pkg
+from paper_0811_2518_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "gabp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gabp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_entry_points():
+    assert _declared() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_opts_match_header_documentation():
+    o = pkg.default_opts()
+    assert o.precision == binding.FP64 and o.check_every == 1 and o.edges_per_block == 0
+    assert o.inner_tol == 1e-5 and o.inner_max_iter == 10000 and o.max_outer == 1000
+    assert o.flags == binding.FLAG_REUSE_PRECISION and o.gamma == 0.0
+
+
+def test_struct_layouts():
+    import ctypes
+    # gabp_opts: 6 int32 then 3 doubles; gabp_info: 4 int32, 3 doubles, 2 int32
+    assert ctypes.sizeof(binding.Opts) == 6 * 4 + 3 * 8
+    assert ctypes.sizeof(binding.Info) == 4 * 4 + 3 * 8 + 2 * 4
+    assert ctypes.sizeof(binding.Props) == 8 + 8 + 4 * 4 + 8

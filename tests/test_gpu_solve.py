@@ -1,0 +1,342 @@
+"""GPU parity of the HIP GaBP path against the FP64 oracle (through the C ABI).
+
+Bar: relative 2-norm error <= 1e-10 against the oracle on the same seeded
+input after the same number of sweeps (and at convergence), bit-exact for
+integer outputs (sweep counts, status codes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import _golden
+import oracle
+import paper_0811_2518_amd as g
+import workloads
+from paper_0811_2518_amd import binding
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = 1e-10
+
+
+def rel(a, b):
+    a = a.detach().cpu().numpy() if torch.is_tensor(a) else np.asarray(a)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def solver(p, **kw):
+    return g.Solver(p.row_ptr, p.col, p.val, device=DEV, **kw)
+
+
+def oracle_T(p, T):
+    return oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=T,
+                                 return_messages=True)
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+
+
+# ---------------------------------------------------------------------------
+# the paper's worked example, round by round
+# ---------------------------------------------------------------------------
+
+def test_e1_tree_every_round_matches_printed_tables():
+    E1 = _golden.load("e1_tree.txt")
+    A = _golden.as_float(_golden.matrix(E1))
+    b = _golden.as_float(_golden.vector(E1, "b"))
+    p = workloads.from_dense(A, b)
+    s = solver(p)
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    off = rows != p.col
+    src, dst = rows[off], p.col[off]
+    for t in range(4):
+        x, info, var = s.solve(dev(b), tol=0, max_iter=t, var=True)
+        means = [float(E1[f"mean {i}"][0][t]) for i in range(3)]
+        np.testing.assert_allclose(x.cpu().numpy(), means, rtol=0, atol=1e-14)
+        P, hm = s.messages()
+        P, hm = P.cpu().numpy(), hm.cpu().numpy()
+        for e in range(len(src)):
+            pg = float(E1[f"P {src[e]} {dst[e]}"][0][t])
+            mg = float(E1[f"mu {src[e]} {dst[e]}"][0][t])
+            assert P[e] == pytest.approx(pg, abs=1e-14)
+            assert hm[e] == pytest.approx(pg * mg, abs=1e-13)  # h = P mu
+    prec = _golden.as_float(_golden.vector(E1, "prec"))
+    np.testing.assert_allclose(1.0 / var.cpu().numpy(), prec, rtol=1e-14)
+    # converged solve: exact after the tree diameter
+    x, info = s.solve(dev(b), tol=1e-14, max_iter=50)
+    assert info["converged"] == 1 and info["sweeps"] <= int(E1["diameter"][0][0])
+    np.testing.assert_allclose(x.cpu().numpy(), _golden.as_float(_golden.vector(E1, "x")), atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# per-sweep parity on seeded inputs
+# ---------------------------------------------------------------------------
+
+CASES = {
+    "grid32": workloads.config1,
+    "er_ragged": lambda: workloads.er_problem(3001, 8, 77, ratio=1.1),
+    "er_sparse_isolated": lambda: workloads.er_problem(4099, 2, 78, ratio=1.3),
+    "grid3d_10": lambda: workloads.grid3d_problem(10, 79),
+    "tree": lambda: workloads.random_tree(777, 80),
+    "star_long_row": lambda: workloads.star_problem(5000, 81),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("epb", [512, 2048])
+def test_sweep_parity_fixed_rounds(name, epb):
+    p = CASES[name]()
+    s = solver(p, edges_per_block=epb)
+    for T in (0, 1, 2, 7, 25):
+        ref = oracle_T(p, T)
+        x, info = s.solve(dev(p.b), tol=0, max_iter=T)
+        assert rel(x, ref["x"]) <= 1e-13, (name, T, rel(x, ref["x"]))
+        P, hm = s.messages()
+        # message i->j of the oracle's edge list vs slot order (both CSR order)
+        np.testing.assert_allclose(P.cpu().numpy(), ref["P"], rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(hm.cpu().numpy(), ref["P"] * ref["mu"], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_converged_solve_matches_oracle(name):
+    p = CASES[name]()
+    s = solver(p)
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000)
+    x, info = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+    assert info["converged"] == 1 and info["status"] == binding.OK
+    assert info["sweeps"] == ref["sweeps"]
+    assert rel(x, ref["x"]) <= TOL
+    assert info["rel_residual"] == pytest.approx(ref["rel_residual"], rel=1e-6)
+    # both pinned to the plain definition
+    xd = oracle.dense_solve(p.dense(), p.b) if p.n <= 5000 else None
+    if xd is not None:
+        assert rel(x, xd) <= 1e-8
+
+
+def test_check_every_matches_oracle():
+    p = workloads.config1()
+    s = solver(p, check_every=4)
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000, check_every=4)
+    x, info = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+    assert info["sweeps"] == ref["sweeps"] and info["sweeps"] % 4 == 0
+    assert rel(x, ref["x"]) <= TOL
+
+
+def test_block_size_invariance_and_determinism():
+    p = workloads.er_problem(20000, 8, 90)
+    xs = []
+    for epb in (512, 1024, 2048, 512):
+        s = solver(p, edges_per_block=epb)
+        x, info = s.solve(dev(p.b), tol=1e-12, max_iter=500)
+        xs.append((x.cpu().numpy(), info["sweeps"]))
+        s.close()
+    for x, sw in xs[1:]:
+        assert sw == xs[0][1]
+        np.testing.assert_array_equal(x, xs[0][0])  # row sums are order-identical
+
+
+def test_tree_variances_exact():
+    p = workloads.random_tree(300, 5)
+    s = solver(p)
+    x, info, var = s.solve(dev(p.b), tol=1e-14, max_iter=1000, var=True)
+    A = p.dense()
+    np.testing.assert_allclose(var.cpu().numpy(), np.diag(np.linalg.inv(A)), rtol=1e-11)
+    assert rel(x, np.linalg.solve(A, p.b)) <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_single_node_and_diagonal_only():
+    p = workloads.from_dense(np.array([[4.0]]), np.array([2.0]))
+    x, info = solver(p).solve(dev(p.b), tol=TOL, max_iter=10)
+    assert x.item() == 0.5 and info["converged"] == 1 and info["sweeps"] == 0
+    d = np.array([1.0, -2.0, 4.0, 0.5, 3.0])
+    p = workloads.from_dense(np.diag(d), np.arange(5.0))
+    x, info = solver(p).solve(dev(p.b), tol=TOL, max_iter=10)
+    np.testing.assert_array_equal(x.cpu().numpy(), np.arange(5.0) / d)
+
+
+def test_empty_system():
+    s = g.Solver(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), device=DEV)
+    x, info = s.solve(torch.zeros(0, dtype=torch.float64, device=DEV), tol=TOL, max_iter=5)
+    assert info["converged"] == 1 and x.numel() == 0
+
+
+def test_zero_rhs_converges_at_round_zero():
+    p = workloads.config1()
+    x, info = solver(p).solve(torch.zeros(p.n, dtype=torch.float64, device=DEV), tol=TOL, max_iter=10)
+    assert info["converged"] == 1 and info["sweeps"] == 0 and float(x.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# failures forced from the host with CPU-built inputs
+# ---------------------------------------------------------------------------
+
+def _status_of_create(rp, col, val, **kw):
+    st, s = g.try_create(rp, col, val, device=DEV, **kw)
+    return st
+
+
+def test_rejects_asymmetric_pattern_and_values():
+    p = workloads.config1()
+    val = p.val.copy()
+    e = p.row_ptr[5] + 1
+    val[e] += 0.5
+    assert _status_of_create(p.row_ptr, p.col, val) == binding.E_NOT_SYMMETRIC
+    A = np.array([[2.0, 1.0, 0.0], [0.0, 2.0, 0.0], [0.0, 0.0, 2.0]])
+    rp = np.array([0, 2, 3, 4], np.int32)
+    col = np.array([0, 1, 1, 2], np.int32)
+    assert _status_of_create(rp, col, A[[0, 0, 1, 2], col]) == binding.E_NOT_SYMMETRIC
+
+
+def test_rejects_zero_or_missing_diagonal():
+    p = workloads.config1()
+    val = p.val.copy()
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    val[np.nonzero((rows == 7) & (p.col == 7))[0][0]] = 0.0
+    assert _status_of_create(p.row_ptr, p.col, val) == binding.E_ZERO_DIAG
+    rp = np.array([0, 1, 2], np.int32)
+    assert _status_of_create(rp, np.array([1, 0], np.int32), np.array([1.0, 1.0])) == binding.E_ZERO_DIAG
+
+
+def test_rejects_bad_structure():
+    rp = np.array([0, 2, 4], np.int32)
+    assert _status_of_create(rp, np.array([1, 0, 0, 1], np.int32), np.ones(4)) == binding.E_ARG  # unsorted
+    assert _status_of_create(rp, np.array([0, 0, 0, 1], np.int32), np.ones(4)) == binding.E_ARG  # duplicate
+    assert _status_of_create(rp, np.array([0, 5, 0, 1], np.int32), np.ones(4)) == binding.E_ARG  # range
+    assert _status_of_create(np.array([0, 3, 2], np.int32), np.array([0, 1, 1], np.int32),
+                             np.ones(3)) == binding.E_ARG  # row pointers decrease
+    assert _status_of_create(rp, np.array([0, 1, 0, 1], np.int32),
+                             np.array([1.0, np.nan, np.nan, 1.0])) == binding.E_NONFINITE
+
+
+def test_nan_rhs_is_nonfinite():
+    p = workloads.config1()
+    b = p.b.copy()
+    b[3] = np.nan
+    x, info = solver(p).solve(dev(b), tol=TOL, max_iter=100, check=False)
+    assert info["status"] == binding.E_NONFINITE
+
+
+def test_iteration_cap_reports_not_converged():
+    p = workloads.config1()
+    ref = oracle_T(p, 1)
+    x, info = solver(p).solve(dev(p.b), tol=TOL, max_iter=1)
+    assert info["status"] == binding.NOT_CONVERGED and info["converged"] == 0 and info["sweeps"] == 1
+    assert rel(x, ref["x"]) <= 1e-14
+
+
+def test_non_walk_summable_diverges_without_loading():
+    p = workloads.config5(n=2000, rows=4000)
+    x, info = solver(p).solve(dev(p.b), tol=1e-9, max_iter=2000, check=False)
+    assert info["status"] in (binding.E_DIVERGED, binding.E_NONFINITE)
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-9, max_sweeps=2000)
+    assert not ref["converged"]
+
+
+# ---------------------------------------------------------------------------
+# FP32 messages with FP64 refinement; diagonal loading (Ch. 5)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["grid32", "er_ragged", "grid3d_10", "star_long_row"])
+def test_fp32_refine_reaches_fp64_accuracy(name):
+    p = CASES[name]()
+    s = solver(p, precision="fp32")
+    x, info = s.solve(dev(p.b), tol=TOL, max_iter=5000)
+    assert info["converged"] == 1 and info["rel_residual"] <= TOL
+    assert info["outer_iters"] >= 2
+    _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+    assert rr <= 1.05 * TOL
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-14, max_sweeps=5000)
+    assert rel(x, ref["x"]) <= 1e-9  # error vs the FP64 oracle, reported by the bench
+
+
+def test_diagonal_loading_fixes_divergent_system():
+    p = workloads.config5(n=3000, rows=6000)
+    lo, hi = oracle.walk_rho(p.n, p.row_ptr, p.col, p.val, rtol=1e-8, iters=20000)
+    gam = oracle.walk_loading(hi, 0.05)
+    for prec in ("fp64", "fp32"):
+        s = solver(p, precision=prec, gamma=gam, inner_tol=1e-3)
+        x, info = s.solve(dev(p.b), tol=1e-9, max_iter=200000)
+        assert info["converged"] == 1, info
+        xd = np.linalg.solve(p.dense(), p.b)
+        assert rel(x, xd) <= 1e-7, (prec, rel(x, xd))
+        assert info["gamma"] == pytest.approx(gam)
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+def test_backward_matches_dense_gradient_and_fd():
+    p = workloads.config4(p=8)
+    t = p.extra["target"]
+    A = p.dense()
+    s = solver(p)
+    x, info = s.solve(dev(p.b), tol=1e-13, max_iter=5000)
+    gb, gv, binfo = s.backward(x, x - dev(t), tol=1e-13, max_iter=5000)
+    xr, lam, gvals = oracle.adjoint_gradient(A, p.b, t, p.row_ptr, p.col)
+    assert rel(gb, lam) <= TOL
+    assert rel(gv, gvals) <= TOL
+    # central finite differences on a sample of entries (oracle, dense solves)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(p.col), 40, replace=False)
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    for e in idx:
+        i, j = rows[e], p.col[e]
+        h = 1e-6 * max(abs(A[i, j]), 1.0)
+        Ap, Am = A.copy(), A.copy()
+        Ap[i, j] += h
+        Am[i, j] -= h
+        if i != j:
+            Ap[j, i] += h
+            Am[j, i] -= h
+        fd = (oracle.loss(Ap, p.b, t) - oracle.loss(Am, p.b, t)) / (2 * h)
+        assert gv[e].item() == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_autograd_function():
+    p = workloads.config4(p=6)
+    t = torch.from_numpy(p.extra["target"]).to(DEV)
+    s = solver(p)
+    vals = torch.from_numpy(p.val).to(DEV).requires_grad_(True)
+    b = torch.from_numpy(p.b).to(DEV).requires_grad_(True)
+    x = g.gabp_solve(s, vals, b, tol=1e-13, max_iter=5000)
+    loss = 0.5 * ((x - t) ** 2).sum()
+    loss.backward()
+    xr, lam, gvals = oracle.adjoint_gradient(p.dense(), p.b, p.extra["target"], p.row_ptr, p.col)
+    assert rel(b.grad, lam) <= TOL
+    assert rel(vals.grad, gvals) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def er_full():
+    return workloads.config2()
+
+
+def test_full_er_first_rounds_match_oracle(er_full):
+    p = er_full
+    s = solver(p)
+    for T in (1, 3):
+        ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=T)
+        x, info = s.solve(dev(p.b), tol=0, max_iter=T)
+        assert rel(x, ref["x"]) <= 1e-12
+
+
+def test_full_er_converges_with_independent_residual(er_full):
+    p = er_full
+    for prec in ("fp64", "fp32"):
+        s = solver(p, precision=prec, reuse_precision=False)
+        x, info = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+        assert info["converged"] == 1
+        r = p.b - p.scipy() @ x.cpu().numpy()
+        assert np.linalg.norm(r) / np.linalg.norm(p.b) <= 1.05 * TOL
+        s.close()
