@@ -110,6 +110,25 @@ def cpu_baseline(p, sweeps):
     return p.num_offdiag * sweeps / dt, dt
 
 
+def probe(torch, g, workloads, args):
+    """Launches for rocprofv3 counter runs: a plain copy of known size, then solves."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
+    p = workloads.config2(args.n)
+    b = torch.from_numpy(p.b).to("cuda")
+    for prec in ("fp64", "fp32"):
+        s = g.Solver(p.row_ptr, p.col, p.val, precision=prec, reuse_precision=False)
+        for _ in range(args.steps):
+            _, info = s.solve(b, tol=TOL, max_iter=2000)
+        log(f"{prec}: {info}")
+        s.close()
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +137,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -128,6 +149,10 @@ def main():
 
     import paper_0811_2518_amd as g
     import workloads
+
+    if args.probe:
+        probe(torch, g, workloads, args)
+        return
 
     log("generating the G(n,4n) workload")
     p = workloads.config2(args.n)

@@ -184,7 +184,8 @@ def _status_of_create(rp, col, val, **kw):
 def test_rejects_asymmetric_pattern_and_values():
     p = workloads.config1()
     val = p.val.copy()
-    e = p.row_ptr[5] + 1
+    e = p.row_ptr[5]  # entry (5, 4): off the diagonal
+    assert p.col[e] == 4
     val[e] += 0.5
     assert _status_of_create(p.row_ptr, p.col, val) == binding.E_NOT_SYMMETRIC
     A = np.array([[2.0, 1.0, 0.0], [0.0, 2.0, 0.0], [0.0, 0.0, 2.0]])
