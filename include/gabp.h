@@ -80,9 +80,10 @@ typedef struct {
  * gabp_solve runs the full synchronous iteration from zero messages. */
 #define GABP_FLAG_REUSE_PRECISION 1
 
-/* Time every main-mode sweep launch that carries the fused residual check
- * with a pair of HIP events on the handle's stream; the total is returned in
- * gabp_info.sweep_ms (profiling aid, adds one event record per launch). */
+/* Profiling aid: time every main-mode sweep that carries the fused residual
+ * check with HIP events attached to the dispatch (hipExtLaunchKernel), so the
+ * interval is the kernel's own execution; totals land in gabp_info.sweep_ms /
+ * timed_sweeps (at most 2048 sweeps per call are timed). */
 #define GABP_FLAG_TIME_SWEEPS 2
 
 typedef struct {
@@ -92,8 +93,8 @@ typedef struct {
   int32_t status;        /* gabp_status of the call                                   */
   double  rel_residual;  /* ||b - A x||_2 / ||b||_2 of the returned x (||r|| if b = 0)*/
   double  gamma;         /* loading actually used (0 if none)                         */
-  double  sweep_ms;      /* GABP_FLAG_TIME_SWEEPS: summed duration of timed sweeps    */
-  int32_t timed_sweeps;  /* number of sweep launches in sweep_ms                      */
+  double  sweep_ms;      /* GABP_FLAG_TIME_SWEEPS: summed duration of the timed sweeps */
+  int32_t timed_sweeps;  /* number of sweeps in sweep_ms                              */
   int32_t sweep_mode;    /* 0: joint (P, h) sweeps were timed, 1: h-only sweeps       */
 } gabp_info;
 

@@ -121,8 +121,8 @@ struct Ctx {
   DevStatus* st_d = nullptr;              // [2]: inner / outer
   DevStatus* st_h = nullptr;              // pinned host mirror [4]
   hipEvent_t ev[2] = {nullptr, nullptr};
-  // sweep timing (GABP_FLAG_TIME_SWEEPS)
-  std::vector<hipEvent_t> tev;      // pairs: start, stop
+  // GABP_FLAG_TIME_SWEEPS: event pairs attached to main-mode checking sweeps
+  std::vector<hipEvent_t> tev;
   int tev_used = 0;
   double sweep_ms = 0.0;
   int timed_sweeps = 0;
@@ -154,7 +154,8 @@ gabp_status set_partition(Ctx* c, int K);
 
 // ---- kernels (sweep.hip) ---------------------------------------------------
 template <typename T>
-hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s);
+hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 size_t sweep_lds_bytes(int K, int elt, bool joint);
 hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
@@ -191,6 +192,9 @@ struct OuterArgs {
   int32_t n;
 };
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
+hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s);
+hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
+                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s);
 hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam,
                             const double* x, double* gv, int32_t n, hipStream_t s);
 hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n,

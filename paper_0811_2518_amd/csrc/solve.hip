@@ -91,13 +91,16 @@ gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
       if (mode == kResid && !ck) continue;
       const bool timed = (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck &&
                          c->tev_used + 2 <= (int)c->tev.size();
-      if (timed) GABP_HIP(c, hipEventRecord(c->tev[c->tev_used], s));
-      GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s));
       if (timed) {
-        GABP_HIP(c, hipEventRecord(c->tev[c->tev_used + 1], s));
+        GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s, c->tev[c->tev_used], c->tev[c->tev_used + 1]));
         c->tev_used += 2;
         c->timed_mode = cfg.honly ? 1 : 0;
+      } else {
+        GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s));
       }
+      if (ck)
+        GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, k.tol, t - 2, nullptr,
+                                        true, s));
     }
     GABP_HIP(c, hipMemcpyAsync(&c->st_h[slot], cfg.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     GABP_HIP(c, hipEventRecord(c->ev[slot], s));
@@ -112,7 +115,7 @@ gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
   return GABP_OK;
 }
 
-// Sum the recorded sweep durations (after the stream has been synchronised).
+// Sum the durations of the timed sweeps (after the stream has been synchronised).
 gabp_status collect_timing(Ctx* c) {
   for (int i = 0; i + 1 < c->tev_used; i += 2) {
     float ms = 0.f;
@@ -131,7 +134,6 @@ void reset_timing(Ctx* c) {
 }
 
 void report_timing(const Ctx* c, gabp_info* info) {
-  if (!info) return;
   info->sweep_ms = c->sweep_ms;
   info->timed_sweeps = c->timed_sweeps;
   info->sweep_mode = c->timed_mode;

@@ -18,6 +18,8 @@
 // formed once, in registers/LDS, and never written to HBM.  Optionally the same
 // launch checks the residual b - A x of the previous round's x (fused
 // convergence check, wave64 reductions, deterministic last-workgroup total).
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -63,28 +65,23 @@ __device__ __forceinline__ V block_sum(V v, V* s_red) {
   return (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
-__device__ __forceinline__ double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Residual bookkeeping shared by the sweep and outer kernels: every workgroup
+// stores its partial sum of r_i^2 with a plain store; k_check_finish, launched
+// right after, adds the partials in index order and updates the status.  No
+// fence or device-scope atomic is needed inside the sweep: the kernel boundary
+// makes the partials visible.
+__device__ __forceinline__ void store_partial(double res2, double* s_red, double* partials, int b) {
+  const double bs = block_sum(res2, s_red);
+  if (threadIdx.x == 0) partials[b] = bs;
 }
 
-// Residual bookkeeping shared by the sweep and outer kernels: every workgroup
-// stores its partial sum of r_i^2; the last to arrive adds the partials in
-// index order and updates the status.
-__device__ void finish_check(double res2, double* s_red, int* s_last, double* partials, DevStatus* st,
-                             int nblk, int b, const double* rhs_norm, double tol, int round,
-                             double* norm_out) {
-  const double bs = block_sum(res2, s_red);
-  if (threadIdx.x == 0) {
-    partials[b] = bs;
-    __threadfence();
-    const unsigned tk = atomicAdd(&st->ticket, 1u);
-    *s_last = (tk == (unsigned)nblk - 1);
-  }
-  __syncthreads();
-  if (!*s_last) return;
-  __threadfence();
+__global__ __launch_bounds__(kBlock) void k_check_finish(const double* __restrict__ partials, int nblk,
+                                                         DevStatus* st, const double* rhs_norm, double tol,
+                                                         int round, double* norm_out, int gate_on_done) {
+  __shared__ double s_red[kBlock / 64];
+  if (gate_on_done && st->done) return;
   double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kBlock) v += load_coherent(partials + i);
+  for (int i = threadIdx.x; i < nblk; i += kBlock) v += partials[i];
   const double tot = block_sum(v, s_red);
   if (threadIdx.x == 0) {
     const double nb = *rhs_norm;
@@ -100,8 +97,14 @@ __device__ void finish_check(double res2, double* s_red, int* s_last, double* pa
       st->error |= kErrDiverged;
       st->done = 1;
     }
-    st->ticket = 0;
   }
+}
+
+hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
+                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kBlock), 0, s, partials, nblk, st, rhs_norm, tol, round,
+                     norm_out, gate_on_done ? 1 : 0);
+  return hipGetLastError();
 }
 
 // LDS layout of the sweep kernel (bytes): row aggregates, staged incoming
@@ -208,12 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
   __shared__ double s_red[kBlock / 64];
   __shared__ T s_redT[kBlock / 64];
   __shared__ T s_bc[2];
-  __shared__ int s_flag;
 
   const int tid = threadIdx.x;
-  if (tid == 0) s_flag = __hip_atomic_load(&A.st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  if (s_flag) return;
+  // written by an earlier kernel: visible after the kernel boundary
+  if (A.st->done) return;
 
   const int b = xcd_remap(blockIdx.x, A.nblk);
   const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
@@ -332,39 +333,39 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     }
   }
 
-  if (A.check)
-    finish_check(res2, s_red, &s_flag, A.partials, A.st, A.nblk, b, A.rhs_norm, A.tol,
-                 A.round_checked, nullptr);
+  if (A.check) store_partial(res2, s_red, A.partials, b);
 }
 
+// ev0/ev1 (nullable): events attached to the dispatch itself, so that their
+// interval is the kernel's own execution time.
 template <typename T, int K>
-static hipError_t launch_k(int mode, const SweepArgs<T>& a, hipStream_t s) {
+static hipError_t launch_k(int mode, const SweepArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const bool joint = (mode == kJoint || mode == kAgg || mode == kFreeze);
-  const size_t lds = lds_layout(K, sizeof(T), joint);
+  const uint32_t lds = (uint32_t)lds_layout(K, sizeof(T), joint);
   const dim3 grid(a.nblk), block(kBlock);
   switch (mode) {
-    case kJoint: hipLaunchKernelGGL((k_sweep<T, K, kJoint>), grid, block, lds, s, a); break;
-    case kHOnly: hipLaunchKernelGGL((k_sweep<T, K, kHOnly>), grid, block, lds, s, a); break;
-    case kAgg: hipLaunchKernelGGL((k_sweep<T, K, kAgg>), grid, block, lds, s, a); break;
-    case kFreeze: hipLaunchKernelGGL((k_sweep<T, K, kFreeze>), grid, block, lds, s, a); break;
-    case kResid: hipLaunchKernelGGL((k_sweep<T, K, kResid>), grid, block, lds, s, a); break;
+    case kJoint: hipExtLaunchKernelGGL((k_sweep<T, K, kJoint>), grid, block, lds, s, ev0, ev1, 0, a); break;
+    case kHOnly: hipExtLaunchKernelGGL((k_sweep<T, K, kHOnly>), grid, block, lds, s, ev0, ev1, 0, a); break;
+    case kAgg: hipExtLaunchKernelGGL((k_sweep<T, K, kAgg>), grid, block, lds, s, ev0, ev1, 0, a); break;
+    case kFreeze: hipExtLaunchKernelGGL((k_sweep<T, K, kFreeze>), grid, block, lds, s, ev0, ev1, 0, a); break;
+    case kResid: hipExtLaunchKernelGGL((k_sweep<T, K, kResid>), grid, block, lds, s, ev0, ev1, 0, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s) {
+hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (a.nblk <= 0) return hipSuccess;
   switch (K) {
-    case 2: return launch_k<T, 2>(mode, a, s);
-    case 4: return launch_k<T, 4>(mode, a, s);
-    case 8: return launch_k<T, 8>(mode, a, s);
+    case 2: return launch_k<T, 2>(mode, a, s, ev0, ev1);
+    case 4: return launch_k<T, 4>(mode, a, s, ev0, ev1);
+    case 8: return launch_k<T, 8>(mode, a, s, ev0, ev1);
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_sweep<double>(int, int, const SweepArgs<double>&, hipStream_t);
-template hipError_t launch_sweep<float>(int, int, const SweepArgs<float>&, hipStream_t);
+template hipError_t launch_sweep<double>(int, int, const SweepArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_sweep<float>(int, int, const SweepArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // outer correction step (FP64): x_new = x_old + d, r = b - A x_new
@@ -376,7 +377,6 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
   __shared__ double s_ax[S];
   __shared__ int32_t s_ptr[kMaxRowsPerBlock + 4];
   __shared__ double s_red[kBlock / 64];
-  __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, A.nblk);
   const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
@@ -424,11 +424,17 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
       res2 = res * res;
     }
   }
-  finish_check(res2, s_red, &s_flag, A.partials, A.st, A.nblk, b, A.b_norm, A.tol, 0, A.r_norm);
+  store_partial(res2, s_red, A.partials, b);
 }
 
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
   if (a.nblk <= 0) return hipSuccess;
+  hipError_t e = launch_outer_only(K, a, s);
+  if (e != hipSuccess) return e;
+  return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s);
+}
+
+hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s) {
   const dim3 grid(a.nblk), block(kBlock);
   switch (K) {
     case 2: hipLaunchKernelGGL(k_outer<2>, grid, block, 0, s, a); break;

@@ -1,0 +1,97 @@
+"""Batched solves (one persistent-kernel graph launch) against per-system references."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0811_2518_amd as g
+import workloads
+from paper_0811_2518_amd import binding
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    # uneven sizes, all three topologies, 1..12 right-hand sides (several work
+    # items for k > 8)
+    return workloads.config3(num_sys=24, nmin=64, nmax=2500, kmax=12, seed=4242)
+
+
+def _solve(bt, **kw):
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV, **kw)
+    B = torch.from_numpy(bt.B).to(DEV)
+    X, infos, st = s.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=20000)
+    return s, B, X, infos, st
+
+
+def test_batched_matches_per_system_references(small_batch):
+    bt = small_batch
+    assert max(bt.nrhs) > 8 and min(bt.nrhs) >= 1
+    assert set(bt.kinds) == {"grid2d", "grid3d", "er"}
+    s, B, X, infos, st = _solve(bt)
+    assert st == binding.OK
+    Xh = X.cpu().numpy()
+    for q in range(bt.num_sys):
+        p = bt.system(q)
+        info = infos[q]
+        assert info["converged"] == 1 and info["rel_residual"] <= TOL, (q, info)
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        A = p.dense()
+        for j in range(k):
+            _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, xs[:, j], p.b[:, j])
+            assert rr <= 1.05 * TOL, (q, j, rr)
+            ref = oracle.dense_solve(A, p.b[:, j])
+            err = np.linalg.norm(xs[:, j] - ref) / np.linalg.norm(ref)
+            assert err <= 1e-8, (q, j, err)
+
+
+def test_batched_graph_replay_is_deterministic(small_batch):
+    bt = small_batch
+    s, B, X, infos, st = _solve(bt)
+    x1 = X.cpu().numpy().copy()
+    X2, infos2, st2 = s.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=20000, X=X)
+    np.testing.assert_array_equal(X2.cpu().numpy(), x1)
+    assert [i["sweeps"] for i in infos2] == [i["sweeps"] for i in infos]
+
+
+def test_batched_single_system_equals_fp32_solver_accuracy():
+    p = workloads.er_problem(3000, 8, 99, ratio=1.1)
+    bt_off = np.array([0, p.n], np.int32)
+    B = np.random.default_rng(1).standard_normal((p.n, 3))
+    s = g.BatchedSolver(bt_off, p.row_ptr, p.col, p.val, device=DEV)
+    X, infos, st = s.solve([3], [0, p.n * 3], B.ravel(), tol=TOL, max_iter=20000)
+    xs = X.cpu().numpy().reshape(p.n, 3)
+    A = p.dense()
+    for j in range(3):
+        ref = np.linalg.solve(A, B[:, j])
+        assert np.linalg.norm(xs[:, j] - ref) / np.linalg.norm(ref) <= 1e-8
+
+
+def test_batched_rejects_cross_system_entries():
+    a = workloads.grid2d_problem(4, 4, 1)
+    # two copies of the same 16-node system; then couple row 0 to row 16
+    rp = np.concatenate([a.row_ptr, a.row_ptr[1:] + a.row_ptr[-1]]).astype(np.int32)
+    col = np.concatenate([a.col, a.col + 16]).astype(np.int32)
+    val = np.concatenate([a.val, a.val])
+    ok = g.BatchedSolver([0, 16, 32], rp, col, val, device=DEV)
+    ok.close()
+    col_bad = col.copy()
+    assert list(col[:3]) == [0, 1, 4]
+    col_bad[2] = 17  # row 0 references a column of the second system (row stays sorted)
+    with pytest.raises(binding.GabpError) as e:
+        g.BatchedSolver([0, 16, 32], rp, col_bad, val, device=DEV)
+    assert e.value.status == binding.E_ARG
+
+
+def test_batched_rejects_bad_rhs_layout(small_batch):
+    bt = small_batch
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV)
+    B = torch.from_numpy(bt.B).to(DEV)
+    bad = bt.rhs_off.copy()
+    bad[1] += 1
+    X, infos, st = s.solve(bt.nrhs, bad, B, tol=TOL, check=False)
+    assert st == binding.E_ARG
