@@ -39,21 +39,19 @@ def log(msg):
 def sweep_bytes(n, E, elt, check=True, honly=False):
     """Algorithmic HBM bytes of one sweep launch (each array element touched once).
 
-    Joint sweep, per slot: rev 4 + A_ij elt + gathered reverse pair 2 elt +
-    written pair 2 elt; with the fused check also col 4 + gathered x_j elt.
-    Per node: row pointer 4 + A_ii elt + b_i elt + x_i written elt; check adds
-    x_i read elt.  h-only sweep: the pair becomes one h (and A_ij the frozen
-    coefficient), the node reads 1/P~_i instead of A_ii.
+    Joint sweep, per slot: rev 4 + A_ij elt + the gathered reverse message
+    record (P, h, sender mean x) 3 elt + the written record 3 elt.  Per node:
+    row pointer 4 + A_ii elt + b_i elt + x_i written elt, and with the fused
+    check the node's own x of the checked round, elt (the neighbours' x come
+    inside the gathered records).  h-only sweep: records (h, x) of 2 elt, the
+    frozen coefficient instead of A_ij (plus A_ij when checking) and 1/P~_i.
     """
     if honly:
-        slot = 4 + elt + elt + elt
-        node = 4 + elt + elt + elt
+        slot = 4 + elt + 2 * elt + 2 * elt + (elt if check else 0)
+        node = 4 + elt + elt + elt + (2 * elt if check else 0)
     else:
-        slot = 4 + elt + 2 * elt + 2 * elt
-        node = 4 + elt + elt + elt
-    if check:
-        slot += 4 + elt
-        node += elt
+        slot = 4 + elt + 3 * elt + 3 * elt
+        node = 4 + elt + elt + elt + (elt if check else 0)
     return slot * E + node * n
 
 
@@ -77,9 +75,8 @@ def measured_traffic(kernel_tag):
     return ent.get("bytes_per_launch")
 
 
-def run_solves(torch, g, p, b, precision, steps, warmup, time_sweeps):
-    s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False,
-                 time_sweeps=time_sweeps)
+def run_solves(torch, g, p, b, precision, steps, warmup):
+    s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         s.solve(b, tol=TOL, max_iter=2000, x=x)
@@ -99,6 +96,29 @@ def run_solves(torch, g, p, b, precision, steps, warmup, time_sweeps):
     xs = x.detach().cpu().numpy()
     s.close()
     return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs}
+
+
+def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3):
+    """Per-sweep time of the checked FP64 joint sweep: slope between two
+    fixed-length runs (tolerance below reach, so every sweep carries the fused
+    check and nothing stops early), each timed with events around the whole
+    call.  Includes the one-workgroup finish kernel and the dispatch gaps."""
+    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    s.solve(b, tol=1e-300, max_iter=n1, x=x)
+    best = {}
+    for n_sw in (n1, n2):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.solve(b, tol=1e-300, max_iter=n_sw, x=x)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        best[n_sw] = min(ts)
+    s.close()
+    return (best[n2] - best[n1]) / (n2 - n1)
 
 
 def cpu_baseline(p, sweeps):
@@ -160,9 +180,11 @@ def main():
     b = torch.from_numpy(p.b).to("cuda")
 
     log("FP64 solves")
-    r64 = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, time_sweeps=True)
+    r64 = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup)
     log("FP32 + FP64 refinement solves")
-    r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup, time_sweeps=False)
+    r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup)
+    log("sweep period (fixed-length runs)")
+    per_launch_ms = sweep_period(torch, g, p, b)
 
     i64 = r64["infos"][-1]
     sweeps64 = i64["sweeps"]
@@ -172,7 +194,6 @@ def main():
     ms_step32 = r32["event_ms"] / args.steps
 
     # roofline of the dominant kernel: the FP64 joint sweep with the fused check
-    per_launch_ms = sum(i["sweep_ms"] for i in r64["infos"]) / max(1, sum(i["timed_sweeps"] for i in r64["infos"]))
     alg = sweep_bytes(n, E, 8, check=True)
     achieved = alg / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_sweep_fp64_joint_check")
@@ -212,7 +233,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep<double,K,joint> with fused residual check",
-                     "alg_bytes_per_launch": alg, "avg_launch_ms": per_launch_ms},
+                     "alg_bytes_per_launch": alg, "avg_launch_ms": per_launch_ms,
+                     "timing": "slope of fixed-length checked runs; includes the finish kernel "
+                               "and dispatch gaps of each sweep"},
         "cpu_baseline": cpu,
         "fp64": {"time_to_tol_ms": ms_step, "sweeps": sweeps64, "rel_residual": res64,
                  "wall_ms_per_step": 1e3 * r64["wall_s"] / args.steps},

@@ -61,11 +61,11 @@ gabp_status common_setup(Ctx* c) {
 gabp_status alloc_solver(Ctx* c) {
   const int64_t n = c->n, E = c->E;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
-  const size_t pair = fp32 ? 2 * sizeof(float) : 2 * sizeof(double);
   const size_t elt = fp32 ? sizeof(float) : sizeof(double);
+  const size_t rec = msg_bytes((int)elt, true);  // (P, h, x) record; (h, x) records fit in it
   for (int i = 0; i < 2; ++i) {
-    TRY(dev_alloc(c, &c->msg_d[i], pair * E));
-    c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the pair buffers
+    TRY(dev_alloc(c, &c->msg_d[i], rec * E));
+    c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the message buffers
     TRY(dev_alloc(c, (void**)&c->x64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->pt64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->xo_d[i], sizeof(double) * n));

@@ -101,7 +101,7 @@ struct Ctx {
   std::vector<int32_t> off_ptr_h;
 
   // message buffers (double-buffered), frozen precisions
-  void* msg_d[2] = {nullptr, nullptr};  // double2 / float2 pairs [E]
+  void* msg_d[2] = {nullptr, nullptr};  // message records [E] (P, h, x) or (h, x)
   void* hmsg_d[2] = {nullptr, nullptr}; // h only [E]
   void* gcoef_d = nullptr;              // [E]
   void* inv_pt_d = nullptr;             // [n]
@@ -157,6 +157,7 @@ template <typename T>
 hipError_t launch_sweep(int mode, int K, const SweepArgs<T>& a, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 size_t sweep_lds_bytes(int K, int elt, bool joint);
+size_t msg_bytes(int elt, bool joint);  // bytes of one message record
 hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_norm(const double* v, int64_t n, double* partials, int nparts, double* out,

@@ -16,8 +16,9 @@
 //      P_ij), coalesced in slot order.
 // Steps 2 and 3 of the paper's round are thus fused: the aggregate of node i is
 // formed once, in registers/LDS, and never written to HBM.  Optionally the same
-// launch checks the residual b - A x of the previous round's x (fused
-// convergence check, wave64 reductions, deterministic last-workgroup total).
+// launch checks the residual b - A x of an earlier round (fused convergence
+// check: wave64 reductions into one partial per workgroup, added in a fixed
+// order by a one-workgroup finish kernel).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -27,15 +28,18 @@
 
 namespace gabp {
 
+// Message records.  A joint message i -> j carries (P_ij, h_ij) and, beside
+// them, the sender's tentative mean x_i of the round its aggregate was formed
+// in; with frozen precisions only (h_ij, x_i) remain.  The residual check of
+// row j needs x_i of every neighbour: it arrives in the same cache line as the
+// gathered reverse message instead of costing a second random access.
 template <typename T>
-struct PairOf;
-template <>
-struct PairOf<double> {
-  using type = double2;
+struct MsgJ {
+  T P, h, x;
 };
-template <>
-struct PairOf<float> {
-  using type = float2;
+template <typename T>
+struct MsgH {
+  T h, x;
 };
 
 // Workgroups are dealt round-robin over the 8 XCDs of the chip.  Give each
@@ -75,15 +79,27 @@ __device__ __forceinline__ void store_partial(double res2, double* s_red, double
   if (threadIdx.x == 0) partials[b] = bs;
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_finish(const double* __restrict__ partials, int nblk,
-                                                         DevStatus* st, const double* rhs_norm, double tol,
-                                                         int round, double* norm_out, int gate_on_done) {
-  __shared__ double s_red[kBlock / 64];
+constexpr int kFinishBlock = 1024;
+
+__global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __restrict__ partials, int nblk,
+                                                               DevStatus* st, const double* rhs_norm,
+                                                               double tol, int round, double* norm_out,
+                                                               int gate_on_done) {
+  __shared__ double s_red[kFinishBlock / 64];
   if (gate_on_done && st->done) return;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kBlock) v += partials[i];
-  const double tot = block_sum(v, s_red);
+  double v0 = 0.0, v1 = 0.0;
+  int i = threadIdx.x;
+  for (; i + kFinishBlock < nblk; i += 2 * kFinishBlock) {
+    v0 += partials[i];
+    v1 += partials[i + kFinishBlock];
+  }
+  if (i < nblk) v0 += partials[i];
+  double v = wave_sum(v0 + v1);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kFinishBlock / 64; ++w) tot += s_red[w];
     const double nb = *rhs_norm;
     const double rn = sqrt(tot);
     const double rel = nb > 0.0 ? rn / nb : rn;
@@ -102,51 +118,69 @@ __global__ __launch_bounds__(kBlock) void k_check_finish(const double* __restric
 
 hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
                                double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kBlock), 0, s, partials, nblk, st, rhs_norm, tol, round,
-                     norm_out, gate_on_done ? 1 : 0);
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nblk, st, rhs_norm, tol,
+                     round, norm_out, gate_on_done ? 1 : 0);
   return hipGetLastError();
 }
 
-// LDS layout of the sweep kernel (bytes): row aggregates, staged incoming
-// messages, staged a_ij x_j products, row pointers, local row of each slot.
+size_t msg_bytes(int elt, bool joint) { return (size_t)elt * (joint ? 3 : 2); }
+
+// LDS layout of the sweep kernel (bytes): row aggregates and means, staged
+// incoming messages, staged a_ij x_j products, row pointers, local row of
+// each slot.
 __host__ __device__ constexpr size_t lds_layout(int K, int elt, bool joint) {
-  return (size_t)elt * (2 * kMaxRowsPerBlock + (size_t)kBlock * K * (joint ? 3 : 2)) +
+  return (size_t)elt * (3 * kMaxRowsPerBlock + (size_t)kBlock * K * (joint ? 3 : 2)) +
          sizeof(int32_t) * (kMaxRowsPerBlock + 4) + (size_t)kBlock * K;
 }
 
 size_t sweep_lds_bytes(int K, int elt, bool joint) { return lds_layout(K, elt, joint); }
 
+// Gather of the reverse message (and the sender's mean) of slot s.
+template <typename T, int MODE>
+__device__ __forceinline__ void gather(const SweepArgs<T>& A, int s, T& pin, T& hin, T& xin) {
+  const int rv = A.rev[s];
+  if (MODE == kHOnly) {
+    const MsgH<T> m = ((const MsgH<T>*)A.min)[rv];
+    hin = m.h;
+    xin = m.x;
+  } else {
+    const MsgJ<T> m = ((const MsgJ<T>*)A.min)[rv];
+    pin = m.P;
+    hin = m.h;
+    xin = m.x;
+  }
+}
+
+// A row longer than the workgroup's slot capacity: block-wide reductions,
+// then a second pass over the row for the outgoing messages.
 template <typename T, int MODE>
 __device__ double long_row(const SweepArgs<T>& A, int r, int e0, int ne, T* s_redT, double* s_red,
                            T* s_bc) {
-  using P2 = typename PairOf<T>::type;
   constexpr bool kJointLike = (MODE == kJoint || MODE == kAgg || MODE == kFreeze);
   const int tid = threadIdx.x;
   T pP = 0, ph = 0;
   double pax = 0.0;
   for (int i = tid; i < ne; i += kBlock) {
     const int s = e0 + i;
-    if (MODE != kResid && !A.zero_in) {
-      const int rv = A.rev[s];
-      if (MODE == kHOnly) {
-        ph += ((const T*)A.min)[rv];
-      } else {
-        const P2 m = ((const P2*)A.min)[rv];
-        pP += m.x;
-        ph += m.y;
-      }
+    T pin = 0, hin = 0, xin = 0;
+    if (MODE != kResid && !A.zero_in) gather<T, MODE>(A, s, pin, hin, xin);
+    pP += pin;
+    ph += hin;
+    if (A.check) {
+      const T xc = (MODE == kResid) ? A.xchk[A.off_col[s]] : xin;
+      pax += (double)(A.a[s] * xc);
     }
-    if (A.check) pax += (double)(A.a[s] * A.xchk[A.off_col[s]]);
   }
   pP = block_sum(pP, s_redT);
   ph = block_sum(ph, s_redT);
   pax = block_sum(pax, s_red);
   double res2 = 0.0;
   if (tid == 0) {
-    T Pt = kJointLike ? A.diag[r] + pP : T(0);
+    const T Pt = kJointLike ? A.diag[r] + pP : T(0);
     const T ht = A.rhs[r] + ph;
+    T xr = 0;
     if (MODE != kResid) {
-      const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
+      xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
       if (A.xout) A.xout[r] = xr;
       if (A.ptout && kJointLike) A.ptout[r] = Pt;
       if (MODE == kFreeze) A.inv_pt_out[r] = T(1) / Pt;
@@ -157,28 +191,22 @@ __device__ double long_row(const SweepArgs<T>& A, int r, int e0, int ne, T* s_re
     }
     s_bc[0] = Pt;
     s_bc[1] = ht;
+    s_bc[2] = xr;
   }
   __syncthreads();
   if (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) {
-    const T Pt = s_bc[0], ht = s_bc[1];
+    const T Pt = s_bc[0], ht = s_bc[1], xr = s_bc[2];
     bool bad = false;
     for (int i = tid; i < ne; i += kBlock) {
       const int s = e0 + i;
-      T pin = 0, hin = 0;
-      if (!A.zero_in) {
-        const int rv = A.rev[s];
-        if (MODE == kHOnly) {
-          hin = ((const T*)A.min)[rv];
-        } else {
-          const P2 m = ((const P2*)A.min)[rv];
-          pin = m.x;
-          hin = m.y;
-        }
-      }
+      T pin = 0, hin = 0, xin = 0;
+      if (!A.zero_in) gather<T, MODE>(A, s, pin, hin, xin);
       if (MODE == kHOnly) {
-        const T hn = A.gcoef[s] * (ht - hin);
-        ((T*)A.mout)[s] = hn;
-        bad |= !isfinite(hn);
+        MsgH<T> m;
+        m.h = A.gcoef[s] * (ht - hin);
+        m.x = xr;
+        ((MsgH<T>*)A.mout)[s] = m;
+        bad |= !isfinite(m.h);
       } else {
         const T av = A.a[s];
         const T inv = T(1) / (Pt - pin);
@@ -186,11 +214,12 @@ __device__ double long_row(const SweepArgs<T>& A, int r, int e0, int ne, T* s_re
           A.gcoef_out[s] = -av * inv;
           bad |= !isfinite(inv);
         } else {
-          P2 m;
-          m.x = -av * av * inv;
-          m.y = -av * (ht - hin) * inv;
-          ((P2*)A.mout)[s] = m;
-          bad |= !(isfinite(m.x) && isfinite(m.y));
+          MsgJ<T> m;
+          m.P = -av * av * inv;
+          m.h = -av * (ht - hin) * inv;
+          m.x = xr;
+          ((MsgJ<T>*)A.mout)[s] = m;
+          bad |= !(isfinite(m.P) && isfinite(m.h));
         }
       }
     }
@@ -204,13 +233,12 @@ __device__ double long_row(const SweepArgs<T>& A, int r, int e0, int ne, T* s_re
 
 template <typename T, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
-  using P2 = typename PairOf<T>::type;
   constexpr bool kJointLike = (MODE == kJoint || MODE == kAgg || MODE == kFreeze);
   constexpr int S = kBlock * K;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[kBlock / 64];
   __shared__ T s_redT[kBlock / 64];
-  __shared__ T s_bc[2];
+  __shared__ T s_bc[3];
 
   const int tid = threadIdx.x;
   // written by an earlier kernel: visible after the kernel boundary
@@ -228,7 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
   } else {
     T* s_Pt = (T*)smem;
     T* s_ht = s_Pt + kMaxRowsPerBlock;
-    T* s_h = s_ht + kMaxRowsPerBlock;
+    T* s_x = s_ht + kMaxRowsPerBlock;
+    T* s_h = s_x + kMaxRowsPerBlock;
     T* s_ax = s_h + S;
     T* s_P = s_ax + S;  // joint-like modes only
     int32_t* s_ptr = (int32_t*)(s_P + (kJointLike ? S : 0));
@@ -246,25 +275,18 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
       coef[k] = 0;
       if (i < ne) {
         const int s = e0 + i;
+        T xin = 0;
         if (MODE != kResid) {
           if (MODE == kHOnly) coef[k] = A.gcoef[s];
           else if (MODE != kAgg) coef[k] = A.a[s];
-          if (!A.zero_in) {
-            const int rv = A.rev[s];
-            if (MODE == kHOnly) {
-              hin[k] = ((const T*)A.min)[rv];
-            } else {
-              const P2 m = ((const P2*)A.min)[rv];
-              pin[k] = m.x;
-              hin[k] = m.y;
-            }
-          }
+          if (!A.zero_in) gather<T, MODE>(A, s, pin[k], hin[k], xin);
           if (kJointLike) s_P[i] = pin[k];
           s_h[i] = hin[k];
         }
         if (A.check) {
           const T av = (MODE == kJoint || MODE == kFreeze) ? coef[k] : A.a[s];
-          s_ax[i] = av * A.xchk[A.off_col[s]];
+          const T xc = (MODE == kResid) ? A.xchk[A.off_col[s]] : xin;
+          s_ax[i] = av * xc;
         }
       }
     }
@@ -282,9 +304,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
           ht += s_h[j];
           s_row[j] = (uint8_t)tid;
         }
+        const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
         s_ht[tid] = ht;
         s_Pt[tid] = Pt;
-        const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
+        s_x[tid] = xr;
         if (A.xout) A.xout[r] = xr;
         if (A.ptout && kJointLike) A.ptout[r] = Pt;
         if (MODE == kFreeze) A.inv_pt_out[r] = T(1) / Pt;
@@ -307,9 +330,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
           const int s = e0 + i;
           const int lr = s_row[i];
           if (MODE == kHOnly) {
-            const T hn = coef[k] * (s_ht[lr] - hin[k]);
-            ((T*)A.mout)[s] = hn;
-            bad |= !isfinite(hn);
+            MsgH<T> m;
+            m.h = coef[k] * (s_ht[lr] - hin[k]);
+            m.x = s_x[lr];
+            ((MsgH<T>*)A.mout)[s] = m;
+            bad |= !isfinite(m.h);
           } else {
             const T inv = T(1) / (s_Pt[lr] - pin[k]);
             const T av = coef[k];
@@ -317,11 +342,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
               A.gcoef_out[s] = -av * inv;
               bad |= !isfinite(inv);
             } else {
-              P2 m;
-              m.x = -av * av * inv;
-              m.y = -av * (s_ht[lr] - hin[k]) * inv;
-              ((P2*)A.mout)[s] = m;
-              bad |= !(isfinite(m.x) && isfinite(m.y));
+              MsgJ<T> m;
+              m.P = -av * av * inv;
+              m.h = -av * (s_ht[lr] - hin[k]) * inv;
+              m.x = s_x[lr];
+              ((MsgJ<T>*)A.mout)[s] = m;
+              bad |= !(isfinite(m.P) && isfinite(m.h));
             }
           }
         }
@@ -561,19 +587,19 @@ hipError_t launch_scale_diag(const double* d, double f, double* out64, float* ou
   return hipGetLastError();
 }
 
-// De-interleave the FP64 message pairs into P and h arrays.
-__global__ void k_split_pairs(const double2* m, double* P, double* h, int64_t E) {
+// Copy P and h out of the FP64 joint message records.
+__global__ void k_split_msgs(const MsgJ<double>* m, double* P, double* h, int64_t E) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 v = m[i];
-    P[i] = v.x;
-    h[i] = v.y;
+    const MsgJ<double> v = m[i];
+    P[i] = v.P;
+    h[i] = v.h;
   }
 }
 
 hipError_t launch_split_pairs(const void* m, double* P, double* h, int64_t E, hipStream_t s) {
   if (E <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>((E + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_split_pairs, dim3(blocks), dim3(256), 0, s, (const double2*)m, P, h, E);
+  hipLaunchKernelGGL(k_split_msgs, dim3(blocks), dim3(256), 0, s, (const MsgJ<double>*)m, P, h, E);
   return hipGetLastError();
 }
 
