@@ -67,6 +67,10 @@ typedef struct {
   int32_t inner_max_iter;   /* cap on inner sweeps per outer step                   */
   int32_t max_outer;        /* cap on outer steps (refinement / loading loop)       */
   int32_t flags;            /* GABP_FLAG_* bits                                     */
+  int32_t layout;           /* message layout of the sweep kernels: 0 = pick by     */
+                            /* timing at create, 1 = outgoing records + reverse-    */
+                            /* slot index, 2 = node broadcast (edge pairs in place) */
+  int32_t reserved;         /* must be 0                                            */
   double  gamma;            /* diagonal loading of Ch. 5: the inner solves use      */
                             /* A + gamma * diag(A); 0 = none; < 0 = chosen from an  */
                             /* estimate of rho(|R|) (walk-summability, Ch. 5.2)     */
@@ -103,14 +107,17 @@ typedef struct {
   int64_t n;                /* unknowns                                   */
   int64_t num_offdiag;      /* directed message slots E = nnz - n         */
   int32_t edges_per_block;  /* slots per workgroup in the sweep kernel    */
+  int32_t layout;           /* 1 = reverse-slot index, 2 = node broadcast */
+  int32_t pad;
   int32_t num_blocks;       /* workgroups per sweep launch                */
   int32_t max_degree;       /* largest off-diagonal row length            */
   int32_t precision;        /* gabp_precision                             */
   int64_t device_bytes;     /* device memory owned by the handle          */
 } gabp_props;
 
-/* Default options: FP64, check every sweep, autotuned block size, no loading,
- * inner_tol 1e-5, inner_max_iter 10000, max_outer 1000, reuse flag on. */
+/* Default options: FP64, check every sweep, autotuned block size and layout,
+ * no loading, inner_tol 1e-5, inner_max_iter 10000, max_outer 1000, reuse
+ * flag on. */
 void gabp_default_opts(gabp_opts *opts);
 
 /*

@@ -34,6 +34,7 @@ EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "g
 class Opts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("check_every", c_i32), ("edges_per_block", c_i32),
                 ("inner_max_iter", c_i32), ("max_outer", c_i32), ("flags", c_i32),
+                ("layout", c_i32), ("reserved", c_i32),
                 ("gamma", c_f64), ("loading_delta", c_f64), ("inner_tol", c_f64)]
 
 
@@ -48,6 +49,7 @@ class Info(ctypes.Structure):
 
 class Props(ctypes.Structure):
     _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("num_blocks", c_i32),
+                ("layout", c_i32), ("pad", c_i32),
                 ("max_degree", c_i32), ("precision", c_i32), ("device_bytes", c_i64)]
 
 
@@ -139,7 +141,7 @@ class Solver:
 
     def __init__(self, row_ptr, col, val, *, precision="fp64", check_every=1, edges_per_block=0,
                  gamma=0.0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
-                 reuse_precision=True, time_sweeps=False, device="cuda", stream=None):
+                 reuse_precision=True, time_sweeps=False, layout="auto", device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
         self.stream, sh = _stream_handle(stream)
@@ -151,7 +153,7 @@ class Solver:
             precision={"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}[precision],
             check_every=check_every, edges_per_block=edges_per_block, gamma=gamma,
             loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
-            max_outer=max_outer,
+            max_outer=max_outer, layout={"auto": 0, "edge": 1, "node": 2}[layout],
             flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0))
         h = ctypes.c_void_p()
         st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),

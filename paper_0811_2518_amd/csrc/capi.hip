@@ -39,6 +39,7 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
       o.edges_per_block != 2048)
     return fail(c, GABP_E_ARG, "edges_per_block must be 0, 512, 1024 or 2048");
   if (o.inner_max_iter < 0 || o.max_outer < 0) return fail(c, GABP_E_ARG, "negative iteration cap");
+  if (o.layout < 0 || o.layout > kLayoutNode || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
   if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
     return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
   return GABP_OK;
@@ -57,21 +58,26 @@ gabp_status common_setup(Ctx* c) {
   return GABP_OK;
 }
 
-// Buffers of the solve loops, sized for the handle's precision.
+// Buffers of the solve loops, sized for the handle's precision, for every
+// layout the autotuner may pick (the unused layout's are released after it).
 gabp_status alloc_solver(Ctx* c) {
   const int64_t n = c->n, E = c->E;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
   const size_t elt = fp32 ? sizeof(float) : sizeof(double);
-  const size_t rec = msg_bytes((int)elt, true);  // (P, h, x) record; (h, x) records fit in it
+  const bool edge = c->opts.layout != kLayoutNode, node = c->opts.layout != kLayoutEdge;
   for (int i = 0; i < 2; ++i) {
-    TRY(dev_alloc(c, &c->msg_d[i], rec * E));
-    c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the message buffers
+    if (edge) {
+      TRY(dev_alloc(c, &c->msg_d[i], msg_bytes((int)elt, true) * E));
+      c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the message buffers
+    }
+    if (node) TRY(dev_alloc(c, &c->agg_d[i], 2 * elt * n));
     TRY(dev_alloc(c, (void**)&c->x64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->pt64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->xo_d[i], sizeof(double) * n));
     if (fp32) TRY(dev_alloc(c, (void**)&c->x32_d[i], sizeof(float) * n));
   }
-  TRY(dev_alloc(c, &c->gcoef_d, elt * E));
+  if (node) TRY(dev_alloc(c, &c->bstate_d, bcast_state_bytes((int)elt) * E));
+  TRY(dev_alloc(c, &c->gcoef_d, 2 * elt * E));
   TRY(dev_alloc(c, &c->inv_pt_d, elt * n));
   if (fp32) TRY(dev_alloc(c, (void**)&c->rin32_d, sizeof(float) * n));
   TRY(dev_alloc(c, (void**)&c->rin64_d, sizeof(double) * n));
@@ -88,6 +94,22 @@ gabp_status alloc_solver(Ctx* c) {
     GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0, nullptr, c->din32_d, c->n, c->stream));
   }
   return GABP_OK;
+}
+
+void release_unused_layout(Ctx* c) {
+  if (c->layout == kLayoutNode) {
+    for (int i = 0; i < 2; ++i) {
+      dev_free(c, c->msg_d[i]);
+      c->msg_d[i] = c->hmsg_d[i] = nullptr;
+    }
+  } else {
+    dev_free(c, c->bstate_d);
+    c->bstate_d = nullptr;
+    for (int i = 0; i < 2; ++i) {
+      dev_free(c, c->agg_d[i]);
+      c->agg_d[i] = nullptr;
+    }
+  }
 }
 
 bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->opts.gamma == 0.0; }
@@ -126,6 +148,7 @@ gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_id
   if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, nullptr, 0);
   if (r == GABP_OK && n > 0) r = alloc_solver(c);
   if (r == GABP_OK && n > 0) r = autotune(c);
+  if (r == GABP_OK && n > 0) release_unused_layout(c);
   if (r == GABP_OK) {
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) r = hip_fail(c, e, "hipStreamSynchronize");
@@ -168,6 +191,8 @@ gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
   if (c->last_msg_round == 0) {  // round 0: every message is zero (Alg. 2 step 1)
     GABP_HIP(c, launch_fill(P, c->E, 0.0, c->stream));
     GABP_HIP(c, launch_fill(hm, c->E, 0.0, c->stream));
+  } else if (c->layout == kLayoutNode) {
+    GABP_HIP(c, launch_split_out(c->bstate_d, P, hm, c->E, c->stream));
   } else {
     GABP_HIP(c, launch_split_pairs(c->msg_d[c->last_msg_round & 1], P, hm, c->E, c->stream));
   }
@@ -255,6 +280,8 @@ gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
   p->num_offdiag = c->E;
   p->edges_per_block = c->K * kBlock;
   p->num_blocks = c->nblk;
+  p->layout = c->layout;
+  p->pad = 0;
   p->max_degree = c->max_degree;
   p->precision = c->opts.precision;
   p->device_bytes = c->device_bytes;

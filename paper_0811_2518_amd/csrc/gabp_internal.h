@@ -67,6 +67,38 @@ struct SweepArgs {
   int32_t check;           // compute the residual of xchk
 };
 
+// Arguments of one node-broadcast sweep launch (bcast.hip).
+template <typename T>
+struct BcastArgs {
+  const int32_t* blk_row;
+  const int32_t* off_ptr;
+  const int32_t* col;      // [E] neighbour of each slot
+  const T* a;              // [E] A_ji of slot (j, i)
+  const T* diag;           // [n] P_ii (possibly loaded)
+  const T* rhs;            // [n]
+  void* state;             // [E] per-slot message pairs, updated in place
+  const void* aold;        // [n] aggregates of round t-1 ({P~, h~}, or h~ with frozen precisions)
+  void* anew;              // [n] aggregates of round t
+  const T* xold;           // [n] means of round t-1 (frozen precisions / residual-only launches)
+  const void* coef;        // [E] frozen {g_in, g_out}
+  void* coef_out;          // freeze output
+  const T* inv_pt;         // [n] frozen 1 / P~
+  T* inv_pt_out;           // freeze output
+  T* xout;                 // [n] means of round t
+  T* xout_prev;            // [n] first sweep only: means of round 0
+  T* ptout;                // [n] P~ of round t (nullable)
+  T* ptout_prev;           // [n] first sweep only: P~ of round 0 (nullable)
+  double* partials;
+  DevStatus* st;
+  int32_t nblk;
+  int32_t zero_in;
+  int32_t check;
+  int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
+};
+
+constexpr int kLayoutEdge = 1;  // outgoing message records + reverse-slot index
+constexpr int kLayoutNode = 2;  // node broadcast: aggregates published, edge pairs kept in place
+
 // Everything a handle owns.  Device arrays are suffixed _d.
 struct Ctx {
   int32_t n = 0;
@@ -77,6 +109,7 @@ struct Ctx {
   int32_t max_degree = 0;
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
+  std::vector<int64_t> alloc_sizes;
 
   // caller's full CSR (kept for the gradient assembly)
   int32_t* row_ptr_d = nullptr;
@@ -108,6 +141,9 @@ struct Ctx {
   bool frozen_valid = false;
   int32_t frozen_prec = -1;
   int last_msg_round = -1;              // round held by msg_d[last_msg_round & 1] (tol <= 0 solves)
+  int layout = kLayoutEdge;
+  void* bstate_d = nullptr;             // node layout: per-slot message pairs [E]
+  void* agg_d[2] = {nullptr, nullptr};  // node layout: published aggregates by round parity [n]
 
   // node vectors
   double* x64_d[2] = {nullptr, nullptr};  // x of rounds (plain) / inner FP64 iterates
@@ -201,6 +237,13 @@ hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const do
 hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n,
                              hipStream_t s);
 hipError_t launch_split_pairs(const void* m, double* P, double* h, int64_t E, hipStream_t s);
+template <typename T>
+hipError_t launch_bcast(int mode, int K, const BcastArgs<T>& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+hipError_t launch_split_out(const void* state, double* P, double* h, int64_t E, hipStream_t s);
+size_t bcast_state_bytes(int elt);
+size_t bcast_lds_bytes(int K, int elt);
+void dev_free(Ctx* c, void* p);
 
 // ---- drivers (solve.hip) ---------------------------------------------------
 gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double tol,

@@ -137,8 +137,21 @@ gabp_status dev_alloc(Ctx* c, void** p, size_t bytes) {
     return fail(c, GABP_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   c->allocs.push_back(*p);
+  c->alloc_sizes.push_back((int64_t)bytes);
   c->device_bytes += (int64_t)bytes;
   return GABP_OK;
+}
+
+void dev_free(Ctx* c, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i] == p) {
+      (void)hipFree(p);
+      c->device_bytes -= c->alloc_sizes[i];
+      c->allocs.erase(c->allocs.begin() + i);
+      c->alloc_sizes.erase(c->alloc_sizes.begin() + i);
+      return;
+    }
 }
 
 #define GABP_TRY(x)                   \

@@ -34,14 +34,47 @@ const T* coef_array(const Ctx* c) {
   else return (const T*)c->a32_d;
 }
 
-// Enqueue the sweeps of one solve: rounds 1..max_iter of Alg. 2 (mode joint
-// or h-only), then the aggregates of round max_iter and a last residual check.
-// Sweep t produces the messages of round t and the means x of round t-1; it
-// checks x of round t-2.  The host polls the device status once per chunk of
-// sweeps while the next chunk runs; sweeps enqueued after convergence return
-// immediately.  Does not wait for the last chunk.
+// Host-side polling of the device status: after each chunk of sweeps the
+// status is copied to pinned memory; the host waits for the copy of the
+// previous chunk while the current one runs.  Returns true once the device
+// reported convergence or failure.
+struct Poller {
+  int pending = -1, slot = 0;
+  gabp_status err = GABP_OK;
+  bool step(Ctx* c, const DevStatus* st) {
+    hipError_t e = hipMemcpyAsync(&c->st_h[slot], st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], c->stream);
+    bool done = false;
+    if (e == hipSuccess && pending >= 0) {
+      e = hipEventSynchronize(c->ev[pending]);
+      if (e == hipSuccess && c->st_h[pending].done) done = true;
+    }
+    if (e != hipSuccess) {
+      err = hip_fail(c, e, "status poll");
+      return true;
+    }
+    pending = slot;
+    slot ^= 1;
+    return done;
+  }
+};
+
 template <typename T>
-gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+void start_timed(Ctx* c, bool timed, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (timed && c->tev_used + 2 <= (int)c->tev.size()) {
+    *e0 = c->tev[c->tev_used];
+    *e1 = c->tev[c->tev_used + 1];
+    c->tev_used += 2;
+  }
+}
+
+// Reverse-index layout.  Sweep t produces the messages of round t and the
+// means x of round t-1, and checks x of round t-2 (its neighbours' means
+// arrive inside the gathered records); rounds 1..M, then the aggregates of
+// round M and a residual-only launch for round M.
+template <typename T>
+gabp_status run_edge(Ctx* c, const RunCfg& cfg) {
   hipStream_t s = c->stream;
   const bool exact = cfg.tol <= 0.0;
   const int M = cfg.max_iter;
@@ -67,7 +100,8 @@ gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
 
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   const int last = M + 2;
-  int t = 1, chunk = 2, pending = -1, slot = 0;
+  int t = 1, chunk = 2;
+  Poller poll;
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -89,30 +123,100 @@ gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
       k.xchk = (const T*)cfg.x2[(t - 2) & 1];
       k.round_checked = t - 2;
       if (mode == kResid && !ck) continue;
-      const bool timed = (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck &&
-                         c->tev_used + 2 <= (int)c->tev.size();
-      if (timed) {
-        GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s, c->tev[c->tev_used], c->tev[c->tev_used + 1]));
-        c->tev_used += 2;
-        c->timed_mode = cfg.honly ? 1 : 0;
-      } else {
-        GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s));
-      }
+      hipEvent_t e0, e1;
+      start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck, &e0, &e1);
+      if (e0) c->timed_mode = cfg.honly ? 1 : 0;
+      GABP_HIP(c, launch_sweep<T>(mode, c->K, k, s, e0, e1));
       if (ck)
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, k.tol, t - 2, nullptr,
                                         true, s));
     }
-    GABP_HIP(c, hipMemcpyAsync(&c->st_h[slot], cfg.st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    GABP_HIP(c, hipEventRecord(c->ev[slot], s));
-    if (pending >= 0) {
-      GABP_HIP(c, hipEventSynchronize(c->ev[pending]));
-      if (c->st_h[pending].done) stop = true;
-    }
-    pending = slot;
-    slot ^= 1;
+    stop = poll.step(c, cfg.st);
     chunk = std::min(chunk * 2, 16);
   }
-  return GABP_OK;
+  return poll.err;
+}
+
+// Node-broadcast layout.  Sweep t publishes the aggregates of round t (and
+// the means x of round t) and checks round t-1, whose neighbour means come
+// with the gathered aggregates; rounds 1..M, then a residual-only launch for
+// round M.
+template <typename T>
+gabp_status run_node(Ctx* c, const RunCfg& cfg) {
+  hipStream_t s = c->stream;
+  const bool exact = cfg.tol <= 0.0;
+  const int M = cfg.max_iter;
+  const int ce = std::max(1, cfg.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+
+  BcastArgs<T> a{};
+  a.blk_row = c->blk_row_d;
+  a.off_ptr = c->off_ptr_d;
+  a.col = c->off_col_d;
+  a.a = coef_array<T>(c);
+  a.diag = (const T*)cfg.diag;
+  a.rhs = (const T*)cfg.rhs;
+  a.state = c->bstate_d;
+  a.coef = c->gcoef_d;
+  a.inv_pt = (const T*)c->inv_pt_d;
+  a.partials = c->partials_d;
+  a.st = cfg.st;
+  a.nblk = c->nblk;
+  a.honly_nodes = cfg.honly ? 1 : 0;
+  const double tol = exact ? -1.0 : cfg.tol;
+  GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
+
+  const int main_mode = cfg.honly ? kHOnly : kJoint;
+  const int last = M + 1;
+  int t = 1, chunk = 2;
+  Poller poll;
+  bool stop = false;
+  while (t <= last && !stop) {
+    const int tend = std::min(last, t + chunk - 1);
+    for (; t <= tend; ++t) {
+      const int mode = (t <= M) ? main_mode : kResid;
+      BcastArgs<T> k = a;
+      k.zero_in = (t == 1);
+      k.aold = c->agg_d[(t - 1) & 1];
+      k.anew = c->agg_d[t & 1];
+      k.xold = (const T*)cfg.x2[(t - 1) & 1];
+      if (mode != kResid) {
+        const bool wx = cfg.honly || (exact ? t == M : in_set(t));
+        k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
+        k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
+      }
+      if (t == 1 && (exact ? M == 0 : in_set(0))) {
+        k.xout_prev = (T*)cfg.x2[0];
+        k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
+      }
+      const bool ck = exact ? (t == M + 1) : in_set(t - 1);
+      k.check = ck ? 1 : 0;
+      if (mode == kResid && !ck) continue;
+      hipEvent_t e0, e1;
+      start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck, &e0, &e1);
+      if (e0) c->timed_mode = cfg.honly ? 1 : 0;
+      GABP_HIP(c, launch_bcast<T>(mode, c->K, k, s, e0, e1));
+      if (ck)
+        GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
+                                        true, s));
+    }
+    stop = poll.step(c, cfg.st);
+    chunk = std::min(chunk * 2, 16);
+  }
+  return poll.err;
+}
+
+template <typename T>
+gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+  return c->layout == kLayoutNode ? run_node<T>(c, cfg) : run_edge<T>(c, cfg);
+}
+
+// Latest round whose messages are held after a solve stopped at round
+// `conv` (or ran out at max_iter): sweeps past convergence return at once, so
+// the edge layout (lagged by two) holds round conv+2, the node layout conv+1.
+int held_round(const Ctx* c, int conv, int M) {
+  if (conv < 0) return M;
+  return std::min(conv + (c->layout == kLayoutNode ? 1 : 2), M);
 }
 
 // Sum the durations of the timed sweeps (after the stream has been synchronised).
@@ -146,28 +250,49 @@ gabp_status read_status(Ctx* c, const DevStatus* st_d, DevStatus* out) {
   return collect_timing(c);
 }
 
-// Freeze the precisions of the messages of round `round`: coefficient
-// g_s = -A_ij / (P~_i - P_ji) per slot and 1 / P~_i per node, so that later
-// sweeps update the h messages only (the P update has no b term).
+// Freeze the precisions of the messages of round `round`: the h update
+// coefficient -A_ij / (P~_i - P_ji) of every message and 1 / P~_i of every
+// node, so that later sweeps update the h messages only (the P update has no
+// b term).
 template <typename T>
 gabp_status freeze(Ctx* c, int round, const void* diag, const void* rhs, int prec) {
-  SweepArgs<T> k{};
-  k.blk_row = c->blk_row_d;
-  k.off_ptr = c->off_ptr_d;
-  k.off_col = c->off_col_d;
-  k.rev = c->rev_d;
-  k.a = coef_array<T>(c);
-  k.diag = (const T*)diag;
-  k.rhs = (const T*)rhs;
-  k.min = c->msg_d[round & 1];
-  k.zero_in = (round == 0);
-  k.gcoef_out = (T*)c->gcoef_d;
-  k.inv_pt_out = (T*)c->inv_pt_d;
-  k.partials = c->partials_d;
-  k.st = c->st_d + 1;  // fresh status: the freeze must not be skipped
-  k.nblk = c->nblk;
-  GABP_HIP(c, launch_reset_status(k.st, 1, c->stream));
-  GABP_HIP(c, launch_sweep<T>(kFreeze, c->K, k, c->stream));
+  DevStatus* st = c->st_d + 1;  // fresh status: the freeze must not be skipped
+  GABP_HIP(c, launch_reset_status(st, 1, c->stream));
+  if (c->layout == kLayoutNode) {
+    BcastArgs<T> k{};
+    k.blk_row = c->blk_row_d;
+    k.off_ptr = c->off_ptr_d;
+    k.col = c->off_col_d;
+    k.a = coef_array<T>(c);
+    k.diag = (const T*)diag;
+    k.rhs = (const T*)rhs;
+    k.state = c->bstate_d;
+    k.aold = c->agg_d[round & 1];
+    k.zero_in = (round == 0);
+    k.coef_out = c->gcoef_d;
+    k.inv_pt_out = (T*)c->inv_pt_d;
+    k.partials = c->partials_d;
+    k.st = st;
+    k.nblk = c->nblk;
+    GABP_HIP(c, launch_bcast<T>(kFreeze, c->K, k, c->stream));
+  } else {
+    SweepArgs<T> k{};
+    k.blk_row = c->blk_row_d;
+    k.off_ptr = c->off_ptr_d;
+    k.off_col = c->off_col_d;
+    k.rev = c->rev_d;
+    k.a = coef_array<T>(c);
+    k.diag = (const T*)diag;
+    k.rhs = (const T*)rhs;
+    k.min = c->msg_d[round & 1];
+    k.zero_in = (round == 0);
+    k.gcoef_out = (T*)c->gcoef_d;
+    k.inv_pt_out = (T*)c->inv_pt_d;
+    k.partials = c->partials_d;
+    k.st = st;
+    k.nblk = c->nblk;
+    GABP_HIP(c, launch_sweep<T>(kFreeze, c->K, k, c->stream));
+  }
   c->frozen_valid = true;
   c->frozen_prec = prec;
   return GABP_OK;
@@ -227,9 +352,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   }
   c->last_msg_round = (exact && !honly && r == GABP_OK) ? max_iter : -1;
   if (r == GABP_OK && !exact && !honly && (c->opts.flags & GABP_FLAG_REUSE_PRECISION)) {
-    // latest round whose messages were written: sweeps stop two rounds after
-    // the converged one (lagged check) or at max_iter
-    const int last = std::min(st.conv_round + 2, max_iter);
+    const int last = held_round(c, st.conv_round, max_iter);
     gabp_status fr = freeze<double>(c, last, c->din64_d, b, GABP_FP64);
     if (fr != GABP_OK) return fr;
     GABP_HIP(c, hipStreamSynchronize(s));
@@ -313,7 +436,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     const int used = si.conv_round >= 0 ? si.conv_round : budget;
     total += used;
     if (!cfg.honly && si.conv_round >= 0) {
-      const int last = std::min(si.conv_round + 2, budget);
+      const int last = held_round(c, si.conv_round, budget);
       r = fp32 ? freeze<float>(c, last, cfg.diag, cfg.rhs, prec) : freeze<double>(c, last, cfg.diag, cfg.rhs, prec);
       if (r != GABP_OK) return r;
     }
@@ -344,7 +467,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: slots per workgroup
+// autotuner: message layout and slots per workgroup
 // ---------------------------------------------------------------------------
 
 namespace {
@@ -353,42 +476,53 @@ std::string tune_key(const Ctx* c) {
   int nb = 0;
   while ((1LL << (nb + 1)) <= (long long)std::max(1, c->n)) ++nb;
   const double avg = c->n ? (double)c->E / c->n : 0.0;
-  char buf[128];
-  std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d", c->opts.precision == GABP_FP32_REFINE ? 32 : 64, nb,
-                (int)std::lround(avg), c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256));
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d-L%d-epb%d",
+                c->opts.precision == GABP_FP32_REFINE ? 32 : 64, nb, (int)std::lround(avg),
+                c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256), c->opts.layout,
+                c->opts.edges_per_block);
   return buf;
 }
 
-int cache_lookup(const std::string& path, const std::string& key) {
+bool cache_lookup(const std::string& path, const std::string& key, int* layout, int* K) {
   std::ifstream f(path);
   std::string line;
-  int best = 0;
+  bool found = false;
   while (std::getline(f, line)) {
-    const std::string pat = "\"key\": \"" + key + "\"";
-    if (line.find(pat) == std::string::npos) continue;
-    const auto p = line.find("\"K\": ");
-    if (p != std::string::npos) best = std::atoi(line.c_str() + p + 5);
+    if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+    const auto pk = line.find("\"K\": ");
+    const auto pl = line.find("\"layout\": ");
+    if (pk == std::string::npos || pl == std::string::npos) continue;
+    const int k = std::atoi(line.c_str() + pk + 5), l = std::atoi(line.c_str() + pl + 10);
+    if ((k == 2 || k == 4 || k == 8) && (l == kLayoutEdge || l == kLayoutNode)) {
+      *K = k;
+      *layout = l;
+      found = true;
+    }
   }
-  return (best == 2 || best == 4 || best == 8) ? best : 0;
+  return found;
 }
 
-void cache_store(const std::string& path, const std::string& key, int K, const double* ms) {
+void cache_store(const std::string& path, const std::string& key, int layout, int K, const std::string& detail) {
   std::ofstream f(path, std::ios::app);
   if (!f) return;
-  f << "{\"key\": \"" << key << "\", \"K\": " << K << ", \"ms_per_sweep\": {\"2\": " << ms[0]
-    << ", \"4\": " << ms[1] << ", \"8\": " << ms[2] << "}}\n";
+  f << "{\"key\": \"" << key << "\", \"layout\": " << layout << ", \"K\": " << K << ", \"ms_per_sweep\": {"
+    << detail << "}}\n";
 }
 
+// Time a few checking sweeps of the handle's main precision, from zero
+// messages, with events around the whole run.
 template <typename T>
-gabp_status time_candidate(Ctx* c, int K, const void* ones, const void* diag, float* ms_out) {
+gabp_status time_candidate(Ctx* c, int layout, int K, const void* rhs, const void* diag, float* ms_out) {
+  c->layout = layout;
   gabp_status r = set_partition(c, K);
   if (r != GABP_OK) return r;
   RunCfg cfg;
-  cfg.rhs = ones;
+  cfg.rhs = rhs;
   cfg.diag = diag;
   cfg.rhs_norm = c->norms_d;
-  cfg.tol = 0.0;
-  cfg.max_iter = 6;
+  cfg.tol = 1e-300;  // never reached: every sweep carries the check
+  cfg.max_iter = 8;
   cfg.x2[0] = sizeof(T) == 8 ? (void*)c->x64_d[0] : (void*)c->x32_d[0];
   cfg.x2[1] = sizeof(T) == 8 ? (void*)c->x64_d[1] : (void*)c->x32_d[1];
   cfg.st = c->st_d;
@@ -402,7 +536,7 @@ gabp_status time_candidate(Ctx* c, int K, const void* ones, const void* diag, fl
     GABP_HIP(c, hipEventRecord(e1, c->stream));
     GABP_HIP(c, hipEventSynchronize(e1));
     GABP_HIP(c, hipEventElapsedTime(ms_out, e0, e1));
-    *ms_out /= (cfg.max_iter + 2);
+    *ms_out /= cfg.max_iter;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -413,35 +547,44 @@ gabp_status time_candidate(Ctx* c, int K, const void* ones, const void* diag, fl
 
 gabp_status autotune(Ctx* c) {
   const int epb = c->opts.edges_per_block;
-  if (epb != 0) return set_partition(c, epb / kBlock);
-  if (c->E < 200000) return set_partition(c, 4);
-  const std::string key = tune_key(c);
-  const char* path = std::getenv("GABP_AUTOTUNE_CACHE");
-  if (path && *path) {
-    const int K = cache_lookup(path, key);
-    if (K) return set_partition(c, K);
-  }
-  const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
-  // right-hand side: the diagonal itself (any finite vector will do)
-  const void* rhs = fp32 ? (const void*)c->din32_d : (const void*)c->din64_d;
-  GABP_HIP(c, launch_fill(c->norms_d, 1, 1.0, c->stream));
-  const int Ks[3] = {2, 4, 8};
-  double ms[3] = {0, 0, 0};
-  int best = 4;
-  float best_ms = 1e30f;
-  for (int i = 0; i < 3; ++i) {
-    float t = 0.f;
-    gabp_status r = fp32 ? time_candidate<float>(c, Ks[i], rhs, rhs, &t)
-                         : time_candidate<double>(c, Ks[i], rhs, rhs, &t);
-    if (r != GABP_OK) return r;
-    ms[i] = t;
-    if (t < best_ms) {
-      best_ms = t;
-      best = Ks[i];
+  std::vector<int> layouts, Ks;
+  if (c->opts.layout) layouts.push_back(c->opts.layout);
+  else layouts = {kLayoutEdge, kLayoutNode};
+  if (epb) Ks.push_back(epb / kBlock);
+  else Ks = {2, 4, 8};
+  int best_l = layouts.back(), best_k = epb ? epb / kBlock : 4;
+  if (c->E >= 200000 && layouts.size() * Ks.size() > 1) {
+    const std::string key = tune_key(c);
+    const char* path = std::getenv("GABP_AUTOTUNE_CACHE");
+    if (path && *path && cache_lookup(path, key, &best_l, &best_k)) {
+      c->layout = best_l;
+      return set_partition(c, best_k);
     }
+    const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
+    // right-hand side: the diagonal itself (any finite vector will do)
+    const void* rhs = fp32 ? (const void*)c->din32_d : (const void*)c->din64_d;
+    GABP_HIP(c, launch_fill(c->norms_d, 1, 1.0, c->stream));
+    float best_ms = 1e30f;
+    std::string detail;
+    for (int l : layouts)
+      for (int K : Ks) {
+        float t = 0.f;
+        gabp_status r = fp32 ? time_candidate<float>(c, l, K, rhs, rhs, &t)
+                             : time_candidate<double>(c, l, K, rhs, rhs, &t);
+        if (r != GABP_OK) return r;
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), "%s\"L%d-K%d\": %.4f", detail.empty() ? "" : ", ", l, K, t);
+        detail += buf;
+        if (t < best_ms) {
+          best_ms = t;
+          best_l = l;
+          best_k = K;
+        }
+      }
+    if (path && *path) cache_store(path, key, best_l, best_k, detail);
   }
-  if (path && *path) cache_store(path, key, best, ms);
-  return set_partition(c, best);
+  c->layout = best_l;
+  return set_partition(c, best_k);
 }
 
 }  // namespace gabp
