@@ -48,9 +48,9 @@ class Info(ctypes.Structure):
 
 
 class Props(ctypes.Structure):
-    _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("num_blocks", c_i32),
-                ("layout", c_i32), ("pad", c_i32),
-                ("max_degree", c_i32), ("precision", c_i32), ("device_bytes", c_i64)]
+    _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("layout", c_i32),
+                ("pad", c_i32), ("num_blocks", c_i32), ("max_degree", c_i32), ("precision", c_i32),
+                ("device_bytes", c_i64)]
 
 
 class GabpError(RuntimeError):

@@ -40,8 +40,8 @@ struct Agg {  // published node aggregate
   T P, h;
 };
 template <typename T>
-struct Coef {  // frozen h-update coefficients of a slot
-  T gin, gout;
+struct Coef {  // frozen h-update coefficients of a slot, and 1 / P~ of its neighbour
+  T gin, gout, ipn;
 };
 
 __device__ __forceinline__ int xcd_remap_b(int b, int nb) {
@@ -105,6 +105,7 @@ __device__ __forceinline__ void slot_update(const BcastArgs<T>& A, int s, T AoP,
       Coef<T> cf;
       cf.gin = -av * inv_in;
       cf.gout = -av * inv_out;
+      cf.ipn = T(1) / Pi;
       ((Coef<T>*)A.coef_out)[s] = cf;
       Pn = inv_in;  // only checked for finiteness
       hn = inv_out;
@@ -134,7 +135,8 @@ __device__ __forceinline__ void slot_update(const BcastArgs<T>& A, int s, T AoP,
     ns.hout = cf.gout * (Aoh - st.hin);
     ((PairH<T>*)A.state)[s] = ns;
     hn = ns.hin;
-    if (A.check) ax = av * (A.zero_in ? hi * A.inv_pt[c] : A.xold[c]);
+    // the neighbour's mean from its published h~ and its frozen 1/P~
+    if (A.check) ax = av * (hi * cf.ipn);
   } else {  // kResid: neighbours' means of the published round
     T xc;
     if (A.zero_in) xc = A.honly_nodes ? A.rhs[c] * A.inv_pt[c] : A.rhs[c] / A.diag[c];
@@ -182,6 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
     }
   };
   auto own_x = [&](int r, T P, T h) -> T {
+    if (MODE == kHOnly) return h * A.inv_pt[r];
     if (!joint_nodes) return A.zero_in ? A.rhs[r] * A.inv_pt[r] : A.xold[r];
     return h / P;
   };
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
       } else if (MODE == kHOnly) {
         const T ht = A.rhs[r] + ph;
         ((T*)A.anew)[r] = ht;
-        A.xout[r] = ht * A.inv_pt[r];
+        if (A.xout) A.xout[r] = ht * A.inv_pt[r];
       } else if (MODE == kFreeze) {
         A.inv_pt_out[r] = T(1) / AoP;
       }
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
         T ht = A.rhs[r];
         for (int j = lo; j < hi; ++j) ht += s_hn[j];
         ((T*)A.anew)[r] = ht;
-        A.xout[r] = ht * A.inv_pt[r];
+        if (A.xout) A.xout[r] = ht * A.inv_pt[r];
       } else if (MODE == kFreeze) {
         A.inv_pt_out[r] = T(1) / s_AoP[tid];
       }
@@ -328,6 +331,7 @@ __global__ void k_split_out(const PairJ<double>* st, double* P, double* h, int64
 }  // namespace
 
 size_t bcast_state_bytes(int elt) { return 4 * (size_t)elt; }
+size_t bcast_coef_bytes(int elt) { return 3 * (size_t)elt; }
 size_t bcast_lds_bytes(int K, int elt) { return bc_lds(K, elt); }
 
 template <typename T>

@@ -1,4 +1,5 @@
 // extern "C" entry points of libgabp (declared in include/gabp.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -77,7 +78,7 @@ gabp_status alloc_solver(Ctx* c) {
     if (fp32) TRY(dev_alloc(c, (void**)&c->x32_d[i], sizeof(float) * n));
   }
   if (node) TRY(dev_alloc(c, &c->bstate_d, bcast_state_bytes((int)elt) * E));
-  TRY(dev_alloc(c, &c->gcoef_d, 2 * elt * E));
+  TRY(dev_alloc(c, &c->gcoef_d, std::max(bcast_coef_bytes((int)elt), elt) * E));
   TRY(dev_alloc(c, &c->inv_pt_d, elt * n));
   if (fp32) TRY(dev_alloc(c, (void**)&c->rin32_d, sizeof(float) * n));
   TRY(dev_alloc(c, (void**)&c->rin64_d, sizeof(double) * n));

@@ -242,6 +242,7 @@ hipError_t launch_bcast(int mode, int K, const BcastArgs<T>& a, hipStream_t s, h
                         hipEvent_t ev1 = nullptr);
 hipError_t launch_split_out(const void* state, double* P, double* h, int64_t E, hipStream_t s);
 size_t bcast_state_bytes(int elt);
+size_t bcast_coef_bytes(int elt);
 size_t bcast_lds_bytes(int K, int elt);
 void dev_free(Ctx* c, void* p);
 

@@ -181,7 +181,7 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
       k.anew = c->agg_d[t & 1];
       k.xold = (const T*)cfg.x2[(t - 1) & 1];
       if (mode != kResid) {
-        const bool wx = cfg.honly || (exact ? t == M : in_set(t));
+        const bool wx = exact ? t == M : in_set(t);
         k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
         k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
       }
@@ -365,6 +365,8 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
   const int prec = c->opts.precision;
   reset_timing(c);
+  // frozen precisions of an earlier call are used only when asked for
+  if (!(c->opts.flags & GABP_FLAG_REUSE_PRECISION)) c->frozen_valid = false;
   GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
   DevStatus* st_out = c->st_d + 1;
   DevStatus* st_in = c->st_d;

@@ -397,6 +397,22 @@ template hipError_t launch_sweep<float>(int, int, const SweepArgs<float>&, hipSt
 // outer correction step (FP64): x_new = x_old + d, r = b - A x_new
 // ---------------------------------------------------------------------------
 
+// x_new = x_old + d, the correction d taken from the inner solve's round that
+// met the inner tolerance (chosen on the device by the inner status).
+__global__ void k_update(OuterArgs A) {
+  const DevStatus* si = A.st_in;
+  const int round = (si && si->conv_round >= 0) ? si->conv_round : A.in_fallback;
+  const float* d32 = A.d32[round & 1];
+  const double* d64 = A.d64[round & 1];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
+    double v = A.xold ? A.xold[i] : 0.0;
+    if (A.use_d) v += d64 ? d64[i] : (double)d32[i];
+    A.xnew[i] = v;
+  }
+}
+
+// r = b - A x_new in FP64 (one gather of x per slot), the inner right-hand
+// side in the inner precision, and the partial sums of r^2.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
   constexpr int S = kBlock * K;
@@ -409,24 +425,14 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
   const int nrow = r1 - r0;
   const int e0 = A.off_ptr[r0];
   const int ne = A.off_ptr[r1] - e0;
-  const DevStatus* si = A.st_in;
-  const int round = (si && si->conv_round >= 0) ? si->conv_round : A.in_fallback;
-  const float* d32 = A.d32[round & 1];
-  const double* d64 = A.d64[round & 1];
-  auto xat = [&](int c) -> double {
-    double v = A.xold ? A.xold[c] : 0.0;
-    if (A.use_d) v += d64 ? d64[c] : (double)d32[c];
-    return v;
-  };
+  const double* x = A.xnew;
   double res2 = 0.0;
   if (ne > S) {  // one long row
     double p = 0.0;
-    for (int i = tid; i < ne; i += kBlock) p += A.a[e0 + i] * xat(A.off_col[e0 + i]);
+    for (int i = tid; i < ne; i += kBlock) p += A.a[e0 + i] * x[A.off_col[e0 + i]];
     p = block_sum(p, s_red);
     if (tid == 0) {
-      const double xr = xat(r0);
-      A.xnew[r0] = xr;
-      const double res = A.b[r0] - A.diag[r0] * xr - p;
+      const double res = A.b[r0] - A.diag[r0] * x[r0] - p;
       if (A.rin32) A.rin32[r0] = (float)res;
       if (A.rin64) A.rin64[r0] = res;
       res2 = res * res;
@@ -436,14 +442,12 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * kBlock;
-      if (i < ne) s_ax[i] = A.a[e0 + i] * xat(A.off_col[e0 + i]);
+      if (i < ne) s_ax[i] = A.a[e0 + i] * x[A.off_col[e0 + i]];
     }
     __syncthreads();
     if (tid < nrow) {
       const int r = r0 + tid;
-      const double xr = xat(r);
-      A.xnew[r] = xr;
-      double res = A.b[r] - A.diag[r] * xr;
+      double res = A.b[r] - A.diag[r] * x[r];
       for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) res -= s_ax[j];
       if (A.rin32) A.rin32[r] = (float)res;
       if (A.rin64) A.rin64[r] = res;
@@ -455,7 +459,10 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
 
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
   if (a.nblk <= 0) return hipSuccess;
-  hipError_t e = launch_outer_only(K, a, s);
+  hipLaunchKernelGGL(k_update, dim3(std::min((a.n + 255) / 256, 4096)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_outer_only(K, a, s);
   if (e != hipSuccess) return e;
   return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s);
 }
