@@ -130,6 +130,127 @@ def cpu_baseline(p, sweeps):
     return p.num_offdiag * sweeps / dt, dt
 
 
+def timed(torch, fn, reps=1):
+    """Best wall time of fn() over reps, the GPU synchronised around each call."""
+    best, out = float("inf"), None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best, out
+
+
+def suite_grid(torch, g, workloads):
+    p = workloads.config1()
+    b = torch.from_numpy(p.b).to("cuda")
+    s = g.Solver(p.row_ptr, p.col, p.val, reuse_precision=False)
+    s.solve(b, tol=TOL, max_iter=2000)
+    dt, (x, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=2000), reps=5)
+    res = float(np.linalg.norm(p.b - p.scipy() @ x.cpu().numpy()) / np.linalg.norm(p.b))
+    out = {"workload": "32x32 grid, A_ii = 1.2 sum|A_ij|", "n": p.n, "E": p.num_offdiag,
+           "time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "rel_residual": res,
+           "edge_updates_per_s": p.num_offdiag * info["sweeps"] / dt, "layout": s.props()["layout"]}
+    s.close()
+    return out
+
+
+def suite_adjoint(torch, g, workloads):
+    p = workloads.config4()
+    b = torch.from_numpy(p.b).to("cuda")
+    t = torch.from_numpy(p.extra["target"]).to("cuda")
+    s = g.Solver(p.row_ptr, p.col, p.val)  # adjoint reuses the forward precisions
+    s.solve(b, tol=TOL, max_iter=5000)
+    s.backward(s.solve(b, tol=TOL, max_iter=5000)[0], torch.zeros_like(b) + 1.0, tol=TOL)
+    dtf, (x, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=5000))
+    dtb, (gb, gv, binfo) = timed(torch, lambda: s.backward(x, x - t, tol=TOL, max_iter=5000))
+    A = p.scipy()
+    lam = gb.cpu().numpy()
+    gx = (x - t).cpu().numpy()
+    out = {"workload": "64^3 7-point grid, L = 0.5 ||x - t||^2", "n": p.n, "E": p.num_offdiag,
+           "forward_ms": 1e3 * dtf, "forward_sweeps": info["sweeps"],
+           "backward_ms": 1e3 * dtb, "backward_sweeps": binfo["sweeps"],
+           "adjoint_rel_residual": float(np.linalg.norm(gx - A @ lam) / np.linalg.norm(gx)),
+           "backward_edge_updates_per_s": p.num_offdiag * binfo["sweeps"] / dtb}
+    s.close()
+    return out
+
+
+def suite_convfix(torch, g, workloads, inner_tol=1e-2):
+    p = workloads.config5()
+    b = torch.from_numpy(p.b).to("cuda")
+    t0 = time.perf_counter()
+    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp32", gamma=-1.0, inner_tol=inner_tol,
+                 reuse_precision=False, inner_max_iter=2000, max_outer=5000)
+    create_s = time.perf_counter() - t0
+    pr = s.props()
+    dt, (x, info) = timed(torch, lambda: s.solve(b, tol=1e-9, max_iter=1000000, check=False))
+    res = float(np.linalg.norm(p.b - p.scipy() @ x.cpu().numpy()) / np.linalg.norm(p.b))
+    out = {"workload": "A = B^T B + 0.1 I, B 2^21 x 2^20 with 4 N(0,1) per row",
+           "n": p.n, "E": p.num_offdiag, "rho_bounds": [pr["rho_lo"], pr["rho_hi"]], "gamma": pr["gamma"],
+           "create_s": create_s, "time_to_tol_ms": 1e3 * dt, "outer_iters": info["outer_iters"],
+           "inner_sweeps": info["sweeps"], "status": info["status"], "rel_residual": res,
+           "inner_tol": inner_tol, "edge_updates_per_s": p.num_offdiag * info["sweeps"] / dt}
+    s.close()
+    return out
+
+
+def suite_batched(torch, g, workloads, sample=48):
+    t0 = time.perf_counter()
+    bt = workloads.config3()
+    gen_s = time.perf_counter() - t0
+    log(f"batch generated in {gen_s:.0f} s")
+    B = torch.from_numpy(bt.B).to("cuda")
+    bs = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val)
+    X = torch.empty_like(B)
+    dt, (X, infos, st) = timed(torch, lambda: bs.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=100000, X=X,
+                                                       check=False))
+    E_s = np.diff(bt.row_ptr[bt.sys_row_off]) - np.diff(bt.sys_row_off)
+    slot_rhs = float(np.sum(E_s.astype(np.float64) * bt.nrhs * np.array([i["sweeps"] for i in infos])))
+    nconv = sum(i["converged"] for i in infos)
+    worst = max(i["rel_residual"] for i in infos)
+    bs.close()
+    del X
+    # per-system loop on a seeded sample: single-system FP32 + refinement handles,
+    # one solve per right-hand side, against the batched launch on the same systems
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(bt.num_sys, size=min(sample, bt.num_sys), replace=False))
+    systems = [bt.system(int(q)) for q in pick]
+    handles = [g.Solver(q.row_ptr, q.col, q.val, precision="fp32", reuse_precision=True) for q in systems]
+    rhs = [torch.from_numpy(np.ascontiguousarray(q.b.T)).to("cuda") for q in systems]
+
+    def loop():
+        for h, r in zip(handles, rhs):
+            for j in range(r.shape[0]):
+                h.solve(r[j], tol=TOL, max_iter=100000)
+    loop_s, _ = timed(torch, loop)
+    for h in handles:
+        h.close()
+    # the same sample through one batched launch
+    sub_off = np.concatenate([[0], np.cumsum([q.n for q in systems])]).astype(np.int32)
+    nnz_off = np.concatenate([[0], np.cumsum([q.nnz for q in systems])])
+    rp = np.concatenate([[0]] + [q.row_ptr[1:] + nnz_off[i] for i, q in enumerate(systems)]).astype(np.int32)
+    col = np.concatenate([q.col + sub_off[i] for i, q in enumerate(systems)]).astype(np.int32)
+    val = np.concatenate([q.val for q in systems])
+    kk = np.array([q.b.shape[1] for q in systems], np.int32)
+    roff = np.concatenate([[0], np.cumsum([q.n * q.b.shape[1] for q in systems])]).astype(np.int64)
+    Bs = torch.from_numpy(np.concatenate([q.b.ravel() for q in systems])).to("cuda")
+    sb = g.BatchedSolver(sub_off, rp, col, val)
+    sb.solve(kk, roff, Bs, tol=TOL, max_iter=100000)
+    sub_s, _ = timed(torch, lambda: sb.solve(kk, roff, Bs, tol=TOL, max_iter=100000))
+    sb.close()
+    return {"workload": "4096 systems: 2-D/3-D grids and random graphs, n log-uniform in [64, 65536], "
+                        "1..32 right-hand sides, dominance 1.05..1.5",
+            "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
+            "E": int(E_s.sum()), "generate_s": gen_s, "time_to_tol_ms": 1e3 * dt, "status": st,
+            "converged_systems": nconv, "worst_rel_residual": worst,
+            "slot_rhs_updates_per_s": slot_rhs / dt,
+            "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
+                                "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
+                                "speedup": loop_s / sub_s}}
+
+
 def probe(torch, g, workloads, args):
     """Launches for rocprofv3 counter runs: a plain copy of known size, then solves."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -157,6 +278,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-suite", action="store_true",
+                    help="skip the other workloads (grid, adjoint, convergence fix, batched)")
     ap.add_argument("--probe", action="store_true",
                     help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
     args = ap.parse_args()
@@ -213,6 +336,19 @@ def main():
                "sample": f"{args.cpu_sweeps} sweeps of the FP64 NumPy broadcast oracle on the same "
                          f"n={n} workload ({dt:.1f} s, single thread)"}
 
+    suite = {}
+    if not args.no_suite:
+        for name, fn in (("grid32_fp64", lambda: suite_grid(torch, g, workloads)),
+                         ("adjoint_grid3d_64", lambda: suite_adjoint(torch, g, workloads)),
+                         ("convfix_btb", lambda: suite_convfix(torch, g, workloads)),
+                         ("batched_4096", lambda: suite_batched(torch, g, workloads))):
+            log(f"suite: {name}")
+            try:
+                suite[name] = fn()
+            except Exception as e:  # keep the headline line even if a part fails
+                suite[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+
     out = {
         "metric": "GaBP edge-updates/s + time-to-1e-10 residual (FP64 vs FP32+refine), % HBM peak",
         "value": value,
@@ -245,6 +381,7 @@ def main():
                         "edge_updates_per_s": E * i32["sweeps"] / (ms_step32 * 1e-3),
                         "speedup_vs_fp64": ms_step / ms_step32},
         "kernel_hash": source_hash(),
+        "suite": suite,
     }
     print(json.dumps(out), flush=True)
 

@@ -113,6 +113,9 @@ typedef struct {
   int32_t max_degree;       /* largest off-diagonal row length            */
   int32_t precision;        /* gabp_precision                             */
   int64_t device_bytes;     /* device memory owned by the handle          */
+  double  rho_lo, rho_hi;   /* bounds on rho(|R|) (walk-summability) when */
+                            /* the loading was chosen automatically       */
+  double  gamma;            /* loading applied to the inner solves        */
 } gabp_props;
 
 /* Default options: FP64, check every sweep, autotuned block size and layout,

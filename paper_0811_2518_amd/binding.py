@@ -50,7 +50,7 @@ class Info(ctypes.Structure):
 class Props(ctypes.Structure):
     _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("layout", c_i32),
                 ("pad", c_i32), ("num_blocks", c_i32), ("max_degree", c_i32), ("precision", c_i32),
-                ("device_bytes", c_i64)]
+                ("device_bytes", c_i64), ("rho_lo", c_f64), ("rho_hi", c_f64), ("gamma", c_f64)]
 
 
 class GabpError(RuntimeError):

@@ -85,7 +85,11 @@ gabp_status alloc_solver(Ctx* c) {
   TRY(dev_alloc(c, (void**)&c->din32_d, sizeof(float) * n));
   // diagonal of the inner matrix A + gamma diag(A)
   double gamma = c->opts.gamma;
-  if (gamma < 0.0) return fail(c, GABP_E_ARG, "automatic loading (gamma < 0) needs gabp_estimate_loading");
+  if (gamma < 0.0) {
+    // automatic loading: gamma = (1 + delta) rho(|R|) - 1 from an upper bound on rho
+    TRY(estimate_walk_rho(c, &c->rho_lo, &c->rho_hi, 4000, 1e-4));
+    gamma = c->rho_hi >= 1.0 ? (1.0 + c->opts.loading_delta) * c->rho_hi - 1.0 : 0.0;
+  }
   c->gamma_used = gamma;
   if (gamma > 0.0) {
     TRY(dev_alloc(c, (void**)&c->din64_d, sizeof(double) * n));
@@ -113,7 +117,7 @@ void release_unused_layout(Ctx* c) {
   }
 }
 
-bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->opts.gamma == 0.0; }
+bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->gamma_used == 0.0 && c->opts.gamma == 0.0; }
 
 }  // namespace
 
@@ -283,6 +287,9 @@ gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
   p->num_blocks = c->nblk;
   p->layout = c->layout;
   p->pad = 0;
+  p->rho_lo = c->rho_lo;
+  p->rho_hi = c->rho_hi;
+  p->gamma = c->gamma_used;
   p->max_degree = c->max_degree;
   p->precision = c->opts.precision;
   p->device_bytes = c->device_bytes;

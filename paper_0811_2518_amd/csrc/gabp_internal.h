@@ -124,6 +124,7 @@ struct Ctx {
   float* din32_d = nullptr;    // inner diagonal in FP32 (loaded)
   double* din64_d = nullptr;   // inner diagonal in FP64 (loaded; == d64 when gamma = 0)
   double gamma_used = 0.0;
+  double rho_lo = 0.0, rho_hi = 0.0;  // bounds on rho(|R|) when loading was chosen automatically
 
   // workgroup partition of the rows
   int32_t K = 0;               // slots per lane
@@ -252,6 +253,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
 gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter,
                         gabp_info* info);
 gabp_status autotune(Ctx* c);
+gabp_status estimate_walk_rho(Ctx* c, double* lo, double* hi, int max_iter, double rtol);
 
 // ---- batched (batched.hip) -------------------------------------------------
 gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off);

@@ -39,4 +39,4 @@ def test_struct_layouts():
     # gabp_opts: 8 int32 then 3 doubles; gabp_info: 4 int32, 3 doubles, 2 int32
     assert ctypes.sizeof(binding.Opts) == 8 * 4 + 3 * 8
     assert ctypes.sizeof(binding.Info) == 4 * 4 + 3 * 8 + 2 * 4
-    assert ctypes.sizeof(binding.Props) == 8 + 8 + 6 * 4 + 8
+    assert ctypes.sizeof(binding.Props) == 8 + 8 + 6 * 4 + 8 + 3 * 8

@@ -382,3 +382,26 @@ def test_layouts_agree_bitwise_on_means_after_fixed_rounds():
     xe, _ = solver(p, layout="edge").solve(dev(p.b), tol=0, max_iter=12)
     xn, _ = solver(p, layout="node").solve(dev(p.b), tol=0, max_iter=12)
     assert rel(xe, xn.cpu().numpy()) <= 1e-14
+
+
+def test_automatic_loading_brackets_walk_radius_and_solves():
+    p = workloads.config5(n=3000, rows=6000)
+    rho = oracle.walk_rho_dense(p.dense())
+    assert rho > 1.0
+    s = solver(p, precision="fp32", gamma=-1.0, inner_tol=1e-3)
+    pr = s.props()
+    assert pr["rho_lo"] - 1e-6 <= rho <= pr["rho_hi"] + 1e-6
+    assert pr["rho_hi"] - pr["rho_lo"] <= 1e-3 * pr["rho_hi"]
+    assert pr["gamma"] == pytest.approx(1.05 * pr["rho_hi"] - 1.0)
+    x, info = s.solve(dev(p.b), tol=1e-9, max_iter=200000)
+    assert info["converged"] == 1
+    assert rel(x, np.linalg.solve(p.dense(), p.b)) <= 1e-7
+
+
+def test_automatic_loading_is_zero_for_walk_summable():
+    p = workloads.config1()
+    s = solver(p, precision="fp32", gamma=-1.0)
+    pr = s.props()
+    assert pr["rho_hi"] < 1.0 and pr["gamma"] == 0.0
+    x, info = s.solve(dev(p.b), tol=TOL, max_iter=5000)
+    assert info["converged"] == 1 and info["gamma"] == 0.0

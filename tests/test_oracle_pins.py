@@ -376,3 +376,11 @@ def test_generators_reproducible_and_shaped():
         np.testing.assert_array_equal(Q, Q.T)
         assert oracle.is_strictly_dd(Q)
         assert q.b.shape == (q.n, int(bt.nrhs[s]))
+
+
+def test_batch_generation_independent_of_workers():
+    a = workloads.config3(num_sys=12, nmin=64, nmax=800, kmax=4, workers=1)
+    b = workloads.config3(num_sys=12, nmin=64, nmax=800, kmax=4, workers=3)
+    for f in ("sys_row_off", "row_ptr", "col", "val", "nrhs", "rhs_off", "B"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+    assert a.kinds == b.kinds

@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 import scipy.sparse as sp
@@ -255,47 +256,69 @@ def config5(n=1 << 20, rows=None, per_row=4, shift=0.1):
 BATCH_KINDS = ("grid2d", "grid3d", "er")
 
 
-def config3(num_sys=4096, nmin=64, nmax=65536, kmax=32, seed=SEED_BASE + 3):
+def _batch_system(seq, nmin, nmax, kmax):
+    """One system of the uneven batch, drawn from its own child seed."""
+    rng = np.random.default_rng(seq)
+    kind = BATCH_KINDS[int(rng.integers(0, 3))]
+    nt = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    ratio = float(rng.uniform(1.05, 1.5))
+    k = int(rng.integers(1, kmax + 1))
+    if kind == "grid2d":
+        side = max(2, int(round(math.sqrt(nt))))
+        n = side * side
+        pairs = grid2d_pairs(side, side)
+        w = rng.uniform(-1.0, 0.0, len(pairs))
+    elif kind == "grid3d":
+        side = max(2, int(round(nt ** (1.0 / 3.0))))
+        n = side ** 3
+        pairs = grid3d_pairs(side)
+        w = rng.uniform(-1.0, 0.0, len(pairs))
+    else:
+        n = nt
+        d = int(rng.integers(4, 13))
+        pairs = er_pairs(n, (d * n) // 2, rng)
+        w = rng.standard_normal(len(pairs))
+    rp, col, val = sym_csr_from_pairs(n, pairs[:, 0], pairs[:, 1], w, ratio)
+    B = rng.standard_normal((n, k))
+    return rp, col, val, B.ravel(), n, k, kind, ratio
+
+
+def _batch_chunk(args):
+    seqs, nmin, nmax, kmax = args
+    return [_batch_system(q, nmin, nmax, kmax) for q in seqs]
+
+
+def config3(num_sys=4096, nmin=64, nmax=65536, kmax=32, seed=SEED_BASE + 3, workers=None):
     """Uneven batch: 2-D / 3-D grids and G(n, dn/2) graphs, n log-uniform, 1..kmax RHS.
 
-    Per system (own child seed): kind uniform over BATCH_KINDS, n_t =
-    round(exp U(ln nmin, ln nmax)), dominance ratio U(1.05, 1.5), RHS count
-    uniform in 1..kmax, then the matrix and B ~ N(0,1).  Grids use U(-1,0)
-    off-diagonals with side round(sqrt n_t) or round(cbrt n_t); random graphs
-    use N(0,1) with degree d uniform in 4..12.
+    Per system (own child seed of SeedSequence(seed)): kind uniform over
+    BATCH_KINDS, n_t = round(exp U(ln nmin, ln nmax)), dominance ratio
+    U(1.05, 1.5), RHS count uniform in 1..kmax, then the matrix and B ~ N(0,1).
+    Grids use U(-1,0) off-diagonals with side round(sqrt n_t) or round(cbrt
+    n_t); random graphs use N(0,1) with degree d uniform in 4..12.  Systems are
+    drawn in parallel worker processes when ``workers`` > 1; the result does not
+    depend on the number of workers.
     """
     seqs = np.random.SeedSequence(seed).spawn(num_sys)
-    rps, cols, vals, Bs = [], [], [], []
-    sizes, nrhs, kinds, ratios = [], [], [], []
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if num_sys >= 256 else 1
+    if workers > 1:
+        import concurrent.futures
+        step = max(1, num_sys // (workers * 4))
+        chunks = [(seqs[i:i + step], nmin, nmax, kmax) for i in range(0, num_sys, step)]
+        with concurrent.futures.ProcessPoolExecutor(max_workers=workers) as ex:
+            systems = [sy for part in ex.map(_batch_chunk, chunks) for sy in part]
+    else:
+        systems = _batch_chunk((seqs, nmin, nmax, kmax))
+    rps, cols, Bs, sizes, nrhs, kinds, ratios = [], [], [], [], [], [], []
+    vals = []
     row0 = 0
     nnz0 = 0
-    for s in range(num_sys):
-        rng = np.random.default_rng(seqs[s])
-        kind = BATCH_KINDS[int(rng.integers(0, 3))]
-        nt = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        ratio = float(rng.uniform(1.05, 1.5))
-        k = int(rng.integers(1, kmax + 1))
-        if kind == "grid2d":
-            side = max(2, int(round(math.sqrt(nt))))
-            n = side * side
-            pairs = grid2d_pairs(side, side)
-            w = rng.uniform(-1.0, 0.0, len(pairs))
-        elif kind == "grid3d":
-            side = max(2, int(round(nt ** (1.0 / 3.0))))
-            n = side ** 3
-            pairs = grid3d_pairs(side)
-            w = rng.uniform(-1.0, 0.0, len(pairs))
-        else:
-            n = nt
-            d = int(rng.integers(4, 13))
-            pairs = er_pairs(n, (d * n) // 2, rng)
-            w = rng.standard_normal(len(pairs))
-        rp, col, val = sym_csr_from_pairs(n, pairs[:, 0], pairs[:, 1], w, ratio)
-        B = rng.standard_normal((n, k))
+    for rp, col, val, B, n, k, kind, ratio in systems:
         rps.append(rp[1:].astype(np.int64) + nnz0)
         cols.append(col.astype(np.int64) + row0)
         vals.append(val)
-        Bs.append(B.ravel())
+        Bs.append(B)
         sizes.append(n)
         nrhs.append(k)
         kinds.append(kind)
