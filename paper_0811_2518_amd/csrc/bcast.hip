@@ -67,9 +67,49 @@ __device__ __forceinline__ V bsum(V v, V* s_red) {
   return (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
+// Streamed data (slot pairs, coefficients, columns, A_ij) is read and written
+// once per sweep: non-temporal accesses keep it from displacing the gathered
+// neighbour aggregates in L2.
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
   return __builtin_nontemporal_load(p);
+}
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ PairJ<T> ld_pairj(const void* base, int s) {
+  const vec2<T>* q = (const vec2<T>*)base + 2 * (size_t)s;
+  const vec2<T> a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1);
+  return PairJ<T>{a.x, a.y, b.x, b.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_pairj(void* base, int s, const PairJ<T>& v) {
+  vec2<T>* q = (vec2<T>*)base + 2 * (size_t)s;
+  vec2<T> a, b;
+  a.x = v.Pin;
+  a.y = v.hin;
+  b.x = v.Pout;
+  b.y = v.hout;
+  __builtin_nontemporal_store(a, q);
+  __builtin_nontemporal_store(b, q + 1);
+}
+template <typename T>
+__device__ __forceinline__ PairH<T> ld_pairh(const void* base, int s) {
+  const vec2<T> a = __builtin_nontemporal_load((const vec2<T>*)base + s);
+  return PairH<T>{a.x, a.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_pairh(void* base, int s, const PairH<T>& v) {
+  vec2<T> a;
+  a.x = v.hin;
+  a.y = v.hout;
+  __builtin_nontemporal_store(a, (vec2<T>*)base + s);
+}
+template <typename T>
+__device__ __forceinline__ Coef<T> ld_coef(const void* base, int s) {
+  const T* q = (const T*)base + 3 * (size_t)s;
+  return Coef<T>{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1), __builtin_nontemporal_load(q + 2)};
 }
 
 __host__ __device__ constexpr size_t bc_lds(int K, int elt) {
@@ -94,7 +134,7 @@ __device__ __forceinline__ void slot_update(const BcastArgs<T>& A, int s, T AoP,
       Pi = A.diag[c];
       hi = A.rhs[c];
     } else {
-      st = ((const PairJ<T>*)A.state)[s];
+      st = ld_pairj<T>(A.state, s);
       const Agg<T> ag = ((const Agg<T>*)A.aold)[c];
       Pi = ag.P;
       hi = ag.h;
@@ -115,25 +155,25 @@ __device__ __forceinline__ void slot_update(const BcastArgs<T>& A, int s, T AoP,
       ns.hin = -av * (hi - st.hout) * inv_in;
       ns.Pout = -av * av * inv_out;
       ns.hout = -av * (Aoh - st.hin) * inv_out;
-      ((PairJ<T>*)A.state)[s] = ns;
+      st_pairj<T>(A.state, s, ns);
       Pn = ns.Pin;
       hn = ns.hin;
     }
     if (A.check) ax = av * (hi / Pi);
   } else if (MODE == kHOnly) {
-    const Coef<T> cf = ((const Coef<T>*)A.coef)[s];
+    const Coef<T> cf = ld_coef<T>(A.coef, s);
     PairH<T> st{0, 0};
     T hi;
     if (A.zero_in) {
       hi = A.rhs[c];
     } else {
-      st = ((const PairH<T>*)A.state)[s];
+      st = ld_pairh<T>(A.state, s);
       hi = ((const T*)A.aold)[c];
     }
     PairH<T> ns;
     ns.hin = cf.gin * (hi - st.hout);
     ns.hout = cf.gout * (Aoh - st.hin);
-    ((PairH<T>*)A.state)[s] = ns;
+    st_pairh<T>(A.state, s, ns);
     hn = ns.hin;
     // the neighbour's mean from its published h~ and its frozen 1/P~
     if (A.check) ax = av * (hi * cf.ipn);
