@@ -228,6 +228,7 @@ def suite_batched(torch, g, workloads, sample=48):
     slot_rhs = float(np.sum(E_s.astype(np.float64) * bt.nrhs * np.array([i["sweeps"] for i in infos])))
     nconv = sum(i["converged"] for i in infos)
     worst = max(i["rel_residual"] for i in infos)
+    prof = bs.profile()
     bs.close()
     del X
     # per-system loop on a seeded sample: single-system FP32 + refinement handles,
@@ -263,7 +264,7 @@ def suite_batched(torch, g, workloads, sample=48):
             "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
             "E": int(E_s.sum()), "generate_s": gen_s, "time_to_tol_ms": 1e3 * dt, "status": st,
             "converged_systems": nconv, "worst_rel_residual": worst,
-            "slot_rhs_updates_per_s": slot_rhs / dt,
+            "slot_rhs_updates_per_s": slot_rhs / dt, "load_balance": prof,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
                                 "speedup": loop_s / sub_s}}

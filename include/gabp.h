@@ -227,6 +227,20 @@ gabp_status gabp_solve_batched(gabp_handle h, const int32_t *nrhs, const int64_t
                                const double *B, double *X, double tol, int32_t max_iter,
                                gabp_info *infos);
 
+/* Load balance of the last gabp_solve_batched launch (host struct). */
+typedef struct {
+  int32_t num_items;        /* work items: (system, group of right-hand sides)   */
+  int32_t workgroups;       /* persistent workgroups launched                    */
+  double  makespan_ms;      /* first item start to last item end (device clock)  */
+  double  busy_ms;          /* sum of the item durations                         */
+  double  longest_item_ms;  /* duration of the longest item                      */
+  int64_t precision_sweeps; /* precision-phase sweeps summed over items          */
+  int64_t inner_sweeps;     /* right-hand-side sweeps summed over items          */
+} gabp_batch_profile;
+
+/* gabp_get_batch_profile -- load-balance figures of the last batched solve. */
+gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile *out);
+
 /* gabp_props -- static properties of a handle (host output). */
 gabp_status gabp_get_props(gabp_handle h, gabp_props *props);
 

@@ -27,8 +27,8 @@ FLAG_TIME_SWEEPS = 2
 
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
-           "gabp_create_batched", "gabp_solve_batched", "gabp_get_props", "gabp_destroy",
-           "gabp_last_error")
+           "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_props",
+           "gabp_destroy", "gabp_last_error")
 
 
 class Opts(ctypes.Structure):
@@ -51,6 +51,11 @@ class Props(ctypes.Structure):
     _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("layout", c_i32),
                 ("pad", c_i32), ("num_blocks", c_i32), ("max_degree", c_i32), ("precision", c_i32),
                 ("device_bytes", c_i64), ("rho_lo", c_f64), ("rho_hi", c_f64), ("gamma", c_f64)]
+
+
+class BatchProfile(ctypes.Structure):
+    _fields_ = [("num_items", c_i32), ("workgroups", c_i32), ("makespan_ms", c_f64), ("busy_ms", c_f64),
+                ("longest_item_ms", c_f64), ("precision_sweeps", c_i64), ("inner_sweeps", c_i64)]
 
 
 class GabpError(RuntimeError):
@@ -87,6 +92,8 @@ def lib():
     L.gabp_solve_batched.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32,
                                      c_void_p]
     L.gabp_solve_batched.restype = c_i32
+    L.gabp_get_batch_profile.argtypes = [c_void_p, P(BatchProfile)]
+    L.gabp_get_batch_profile.restype = c_i32
     L.gabp_get_props.argtypes = [c_void_p, P(Props)]
     L.gabp_get_props.restype = c_i32
     L.gabp_destroy.argtypes = [c_void_p]
@@ -275,6 +282,13 @@ class BatchedSolver:
         if check and st < 0:
             raise _err(self._h, st, "gabp_solve_batched")
         return X, [i.as_dict() for i in infos], st
+
+    def profile(self) -> dict:
+        pf = BatchProfile()
+        st = lib().gabp_get_batch_profile(self._h, ctypes.byref(pf))
+        if st != OK:
+            raise _err(self._h, st, "gabp_get_batch_profile")
+        return {f: getattr(pf, f) for f, _ in pf._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

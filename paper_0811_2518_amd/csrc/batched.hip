@@ -44,6 +44,7 @@ struct ItemInfo {
   int32_t sweeps, outer, converged, status;
   double rel;
   int32_t psweeps, pad;
+  uint64_t t0, t1;  // device wall clock at the item's start and end
 };
 
 struct BatchArgs {
@@ -115,6 +116,7 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* 
   const double* B = A.B + I.rhs_off;
   double* X = A.X + I.rhs_off;
   int status = 0;
+  const uint64_t t_start = wall_clock64();
 
   // ---- 1. precision phase --------------------------------------------------
   int tp = 1;
@@ -261,6 +263,8 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* 
     inf.status = status ? status : (converged ? GABP_OK : GABP_NOT_CONVERGED);
     inf.rel = relmax;
     inf.psweeps = tp;
+    inf.t0 = t_start;
+    inf.t1 = wall_clock64();
     inf.pad = 0;
     A.infos[it] = inf;
   }
@@ -307,7 +311,10 @@ struct BatchState {
   float* kbuf = nullptr;
   int64_t ecap = 0, ncap = 0, hcap = 0, kcap = 0;
   int grid = 0;
+  int launched_grid = 0;
   hipStream_t gs = nullptr;
+  double clock_khz = 0.0;
+  gabp_batch_profile prof{};
   // cached graph of the last solve
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -355,6 +362,9 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off) 
   GABP_HIP(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   GABP_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBT, 0));
   bs->grid = std::max(1, ncu * std::max(1, per_cu));
+  int khz = 0;
+  GABP_HIP(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  bs->clock_khz = khz;
   // the graph is captured and replayed on a stream of the handle's own, ordered
   // after the caller's stream by synchronisation (capture needs a non-null stream)
   GABP_HIP(c, hipStreamCreateWithFlags(&bs->gs, hipStreamNonBlocking));
@@ -475,6 +485,7 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     GABP_HIP(c, hipStreamBeginCapture(bs->gs, hipStreamCaptureModeThreadLocal));
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, bs->gs, bs->queue_d);
     const int grid = std::max(1, std::min<int>(bs->grid, (int)items.size()));
+    bs->launched_grid = grid;
     hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, bs->gs, a);
     hipError_t e = hipStreamEndCapture(bs->gs, &bs->graph);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
@@ -493,6 +504,27 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
   GABP_HIP(c, hipMemcpyAsync(ii.data(), bs->infos_d, sizeof(ItemInfo) * ii.size(), hipMemcpyDeviceToHost,
                              bs->gs));
   GABP_HIP(c, hipStreamSynchronize(bs->gs));
+  // load-balance profile of the launch
+  {
+    gabp_batch_profile& pf = bs->prof;
+    pf = gabp_batch_profile{};
+    pf.num_items = (int32_t)ii.size();
+    pf.workgroups = bs->launched_grid;
+    uint64_t lo = ~0ull, hi = 0;
+    double busy = 0.0, longest = 0.0;
+    for (const ItemInfo& q : ii) {
+      lo = std::min(lo, q.t0);
+      hi = std::max(hi, q.t1);
+      const double ms = (double)(q.t1 - q.t0) / bs->clock_khz;
+      busy += ms;
+      longest = std::max(longest, ms);
+      pf.precision_sweeps += q.psweeps;
+      pf.inner_sweeps += q.sweeps;
+    }
+    pf.makespan_ms = ii.empty() ? 0.0 : (double)(hi - lo) / bs->clock_khz;
+    pf.busy_ms = busy;
+    pf.longest_item_ms = longest;
+  }
   // per-system info: worst over the system's items
   std::vector<gabp_info> out(S);
   for (int s = 0; s < S; ++s) {
@@ -518,6 +550,13 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     for (int s = 0; s < S; ++s) infos[s] = out[s];
   if (worst < 0) fail(c, worst, "a batched system failed (see per-system infos)");
   return worst;
+}
+
+gabp_status batched_profile(Ctx* c, gabp_batch_profile* out) {
+  auto* bs = (BatchState*)c->batch;
+  if (!bs) return fail(c, GABP_E_ARG, "not a batched handle");
+  *out = bs->prof;
+  return GABP_OK;
 }
 
 void batched_destroy(Ctx* c) {

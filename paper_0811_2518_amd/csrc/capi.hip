@@ -278,6 +278,13 @@ gabp_status gabp_solve_batched(gabp_handle h, const int32_t* nrhs, const int64_t
   return batched_solve(c, nrhs, rhs_off, B, X, tol, max_iter, infos);
 }
 
+gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile* out) {
+  if (!h || !out) return fail(h, GABP_E_ARG, "NULL argument");
+  Ctx* c = h;
+  if (!c->batched) return fail(c, GABP_E_ARG, "not a batched handle");
+  return batched_profile(c, out);
+}
+
 gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
   if (!h || !p) return fail(h, GABP_E_ARG, "NULL argument");
   Ctx* c = h;

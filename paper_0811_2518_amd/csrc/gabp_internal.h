@@ -260,6 +260,7 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off);
 gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, const double* B,
                           double* X, double tol, int32_t max_iter, gabp_info* infos);
 void batched_destroy(Ctx* c);
+gabp_status batched_profile(Ctx* c, gabp_batch_profile* out);
 
 }  // namespace gabp
 
