@@ -396,7 +396,15 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
                     bs->key_nrhs == std::vector<int32_t>(nrhs, nrhs + S) &&
                     bs->key_off == std::vector<int64_t>(rhs_off, rhs_off + S + 1);
   if (!same) {
-    // work items, largest first (estimated traffic per sweep)
+    // Work items, largest first.  The work of a right-hand side per sweep is
+    // taken as E_s + n_s; a system's right-hand sides are grouped so that no
+    // item exceeds half of an even share of the whole batch per workgroup,
+    // which keeps the longest item below the average workgroup load.
+    double total = 0.0;
+    for (int s = 0; s < S; ++s)
+      total += (double)(bs->sys_slot_off[s + 1] - bs->sys_slot_off[s] + bs->sys_row_off[s + 1] -
+                        bs->sys_row_off[s]) * nrhs[s];
+    const double cap = std::max(1.0, total / (2.0 * std::max(1, bs->grid)));
     std::vector<Item> items;
     int64_t oe = 0, on = 0, ohe = 0, onk = 0;
     for (int s = 0; s < S; ++s) {
@@ -404,11 +412,12 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
       if (r1 == r0) continue;
       const int64_t E = bs->sys_slot_off[s + 1] - bs->sys_slot_off[s];
       const int32_t k = nrhs[s];
-      for (int32_t j0 = 0; j0 < k; j0 += kMaxGroup) {
+      const int32_t group = (int32_t)std::max(1.0, std::min((double)kMaxGroup, std::floor(cap / (double)(E + r1 - r0))));
+      for (int32_t j0 = 0; j0 < k; j0 += group) {
         Item it{};
         it.sys = s;
         it.j0 = j0;
-        it.kg = std::min(kMaxGroup, k - j0);
+        it.kg = std::min(group, k - j0);
         it.k = k;
         it.r0 = r0;
         it.r1 = r1;
