@@ -64,8 +64,8 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def survey_bytes(n, E, elt):
-    """Algorithmic bytes of one synchronous sweep in the survey's per-unit model:
+def alg_sweep_bytes(n, E, elt):
+    """Algorithmic bytes of one synchronous sweep (per-unit model):
     per slot A_ij + column + reverse index + the gathered reverse message pair
     + the written pair (elt + 4 + 4 + 4 elt), per node row pointer + A_ii + b_i
     + the aggregate pair written and read (4 + 6 elt)."""
@@ -337,9 +337,9 @@ def main():
     ms_step32 = r32["event_ms"] / args.steps
 
     # roofline of the dominant kernel: the FP64 joint sweep with the fused check,
-    # algorithmic bytes in the survey's per-unit model
+    # algorithmic bytes, per-unit model
     layout = r64["props"]["layout"]
-    alg = survey_bytes(n, E, 8)
+    alg = alg_sweep_bytes(n, E, 8)
     kernel_bytes = node_layout_bytes(n, E, 8) if layout == 2 else sweep_bytes(n, E, 8, check=True)
     achieved = alg / (per_launch_ms * 1e-3) / 1e9
     ktag = "k_bcast_fp64_joint" if layout == 2 else "k_sweep_fp64_joint"
@@ -396,7 +396,7 @@ def main():
                      "kernel": ("k_bcast<double,K,joint>" if layout == 2 else "k_sweep<double,K,joint>")
                      + " with fused residual check",
                      "alg_bytes_per_launch": alg,
-                     "alg_model": "48 B/slot + 52 B/node (FP64 sweep, per-unit model of the survey)",
+                     "alg_model": "48 B/slot + 52 B/node (FP64 sweep, per-unit algorithmic model)",
                      "kernel_bytes_per_launch": kernel_bytes,
                      "kernel_frac": kernel_bytes / (per_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "avg_launch_ms": per_launch_ms,

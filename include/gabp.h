@@ -79,7 +79,7 @@ typedef struct {
 } gabp_opts;
 
 /* Reuse precision messages frozen by an earlier solve on the same handle: the
- * P messages depend on A only (Alg. 2 step 2 has no b term), so later solves
+ * P messages depend on A only (the precision update of Alg. 2 has no b term), so later solves
  * and the adjoint solve run mean-only sweeps.  Without the flag every
  * gabp_solve runs the full synchronous iteration from zero messages. */
 #define GABP_FLAG_REUSE_PRECISION 1
@@ -124,8 +124,8 @@ typedef struct {
 void gabp_default_opts(gabp_opts *opts);
 
 /*
- * gabp_create -- ingest A and prepare the solver (Alg. 2 step 1: "set the
- * neighbourhood", the priors P_ii = A_ii).
+ * gabp_create -- ingest A and prepare the solver (Alg. 2: the
+ * neighbourhoods N(i) and the priors P_ii = A_ii).
  *   n          number of unknowns (>= 0)
  *   row_ptr    device int32 [n+1]
  *   col_idx    device int32 [nnz]

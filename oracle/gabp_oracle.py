@@ -5,7 +5,7 @@ benchmark's CPU baseline; never by the solver.  Plain NumPy, FP64, written
 from Bickson, "Gaussian Belief Propagation: Theory and Application".
 
 Notation follows the paper: node i has the prior P_ii = A_ii and mu_ii =
-b_i / A_ii (Alg. 1 step 1, from the self potential of Ch. 2 Sec. 2.3); every
+b_i / A_ii (the prior of Alg. 1, from the self potential of Ch. 2 Sec. 2.3); every
 directed edge i -> j (A_ij != 0, i != j) carries a precision P_ij and a mean
 mu_ij.  A sweep is synchronous: every message of round t is computed from the
 messages of round t-1 only (parallel scheduling, Ch. 2 Sec. 2.3).  Round 0 has
@@ -121,7 +121,7 @@ def naive_gabp(A, b, sweeps):
     ``A`` is a list of rows and ``b`` a list; entries may be floats or
     ``fractions.Fraction``.  Returns one record per round t = 0..sweeps with
     the messages ``P[(i, j)]``, ``mu[(i, j)]`` (message i -> j), the tentative
-    means ``mean[i]`` and the marginal precisions ``prec[i]`` (Alg. 1 step 4).
+    means ``mean[i]`` and the marginal precisions ``prec[i]`` (the marginals of Alg. 1).
     """
     n = len(A)
     zero = b[0] * 0

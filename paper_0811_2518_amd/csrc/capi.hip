@@ -193,7 +193,7 @@ gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
     return fail(c, GABP_E_ARG, "no FP64 messages from a fixed-sweep solve (tol <= 0) are held");
   if (c->E == 0) return GABP_OK;
   if (!P || !hm) return fail(c, GABP_E_ARG, "NULL output");
-  if (c->last_msg_round == 0) {  // round 0: every message is zero (Alg. 2 step 1)
+  if (c->last_msg_round == 0) {  // round 0: every message is zero (initial state of Alg. 2)
     GABP_HIP(c, launch_fill(P, c->E, 0.0, c->stream));
     GABP_HIP(c, launch_fill(hm, c->E, 0.0, c->stream));
   } else if (c->layout == kLayoutNode) {

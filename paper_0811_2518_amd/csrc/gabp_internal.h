@@ -31,7 +31,7 @@ constexpr int32_t kErrNonfinite = 1;
 constexpr int32_t kErrDiverged = 2;
 
 enum SweepMode : int {
-  kJoint = 0,   // P and h messages (Alg. 2 step 2)
+  kJoint = 0,   // P and h messages (Alg. 2 message update)
   kHOnly = 1,   // h messages with frozen precisions (coefficient per slot)
   kAgg = 2,     // node aggregates only: x (and P~) of the current messages
   kFreeze = 3,  // aggregates + freeze: g_s = -a_s / (P~_i - P_ji), 1 / P~_i

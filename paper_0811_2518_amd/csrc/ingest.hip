@@ -1,6 +1,6 @@
 // CSR ingest: validation, diagonal split, reverse-slot index, workgroup partition.
 //
-// Alg. 2 step 1 sets the neighbourhood N(i) (the nonzeros of row i, diagonal
+// Alg. 2 starts from the neighbourhood N(i) (the nonzeros of row i, diagonal
 // excluded) and the priors P_ii = A_ii.  Here that becomes an off-diagonal CSR
 // whose slot s = (i, j) holds the message i -> j, plus rev[s] = the slot of
 // (j, i), which the broadcast update subtracts (Alg. 2, P_ij = -A_ij^2 /

@@ -7,7 +7,7 @@
 // rows,
 //   1. gathers the reverse message j -> i = msg[rev[s]] (the only irregular
 //      access), coalesced reads of rev[] and a[] in slot order,
-//   2. forms the node aggregates of Alg. 2 step 2, P~_i = A_ii + sum_k P_ki and
+//   2. forms the node aggregates of Alg. 2, P~_i = A_ii + sum_k P_ki and
 //      h~_i = b_i + sum_k h_ki, with one lane per row over the row segment
 //      staged in LDS; x_i = h~_i / P~_i is the tentative mean of the round,
 //   3. writes the new outgoing messages, subtracting the reverse message
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
     }
     __syncthreads();
 
-    // 2. row phase: aggregates of Alg. 2 step 2, tentative mean, residual
+    // 2. row phase: node aggregates of Alg. 2, tentative mean, residual
     if (tid < nrow) {
       const int r = r0 + tid;
       const int lo = s_ptr[tid], hi = s_ptr[tid + 1];
