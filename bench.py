@@ -58,7 +58,7 @@ def sweep_bytes(n, E, elt, check=True, honly=False):
 def source_hash():
     """Hash of the sweep kernel sources (traffic counters are valid for these only)."""
     h = hashlib.sha256()
-    for f in ("sweep.hip", "bcast.hip"):
+    for f in ("sweep.hip", "bcast.hip", "compact.hip"):
         with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,6 +78,28 @@ def node_layout_bytes(n, E, elt, check=True):
     neighbour aggregate 2 elt; per node row pointer 4 + A_ii, b_i + own
     aggregate read and new aggregate written 4 elt + x written elt."""
     return (4 + 11 * elt) * E + (4 + 7 * elt) * n
+
+
+def compact_layout_bytes(n, E, elt):
+    """Bytes the compact node-broadcast sweep moves, each element once: per
+    slot column 4 + A_ij elt + the incoming message read and written 4 elt +
+    the gathered neighbour aggregate 2 elt; per node row pointer 4 + A_ii, b_i
+    + own aggregates of the two previous rounds read and the new one written
+    6 elt + x written elt."""
+    return (4 + 7 * elt) * E + (4 + 9 * elt) * n
+
+
+LAYOUT_NAMES = {1: "reverse-slot index", 2: "node broadcast", 3: "compact node broadcast"}
+LAYOUT_KERNELS = {1: ("k_sweep", "k_sweep_fp64_joint"), 2: ("k_bcast", "k_bcast_fp64_joint"),
+                  3: ("k_cnode", "k_cnode_fp64_joint")}
+
+
+def kernel_bytes_of(layout, n, E, elt):
+    if layout == 3:
+        return compact_layout_bytes(n, E, elt)
+    if layout == 2:
+        return node_layout_bytes(n, E, elt)
+    return sweep_bytes(n, E, elt, check=True)
 
 
 def measured_traffic(kernel_tag):
@@ -280,7 +302,7 @@ def probe(torch, g, workloads, args):
     log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
     p = workloads.config2(args.n)
     b = torch.from_numpy(p.b).to("cuda")
-    for prec, layout in (("fp64", "node"), ("fp64", "edge"), ("fp32", "node")):
+    for prec, layout in (("fp64", "compact"), ("fp64", "node"), ("fp64", "edge"), ("fp32", "compact")):
         s = g.Solver(p.row_ptr, p.col, p.val, precision=prec, reuse_precision=False, layout=layout,
                      edges_per_block=512)
         for _ in range(args.steps):
@@ -340,9 +362,9 @@ def main():
     # algorithmic bytes, per-unit model
     layout = r64["props"]["layout"]
     alg = alg_sweep_bytes(n, E, 8)
-    kernel_bytes = node_layout_bytes(n, E, 8) if layout == 2 else sweep_bytes(n, E, 8, check=True)
+    kernel_bytes = kernel_bytes_of(layout, n, E, 8)
     achieved = alg / (per_launch_ms * 1e-3) / 1e9
-    ktag = "k_bcast_fp64_joint" if layout == 2 else "k_sweep_fp64_joint"
+    kname, ktag = LAYOUT_KERNELS[layout]
     traffic = measured_traffic(ktag)
 
     # errors against the FP64 reference x (the FP64 GPU solve is itself checked
@@ -390,11 +412,11 @@ def main():
                                f"A_ii=1.1*sum|A_ij|, b~N(0,1), solve to rel. residual 1e-10",
                    "n": n, "num_offdiag": E, "tol": TOL,
                    "edges_per_block": r64["props"]["edges_per_block"],
-                   "layout": {1: "reverse-slot index", 2: "node broadcast"}[layout]},
+                   "layout": LAYOUT_NAMES[layout]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("k_bcast<double,K,joint>" if layout == 2 else "k_sweep<double,K,joint>")
-                     + " with fused residual check",
+                     "kernel": f"{kname}<double,{r64['props']['edges_per_block'] // 256},joint>"
+                               " with fused residual check",
                      "alg_bytes_per_launch": alg,
                      "alg_model": "48 B/slot + 52 B/node (FP64 sweep, per-unit algorithmic model)",
                      "kernel_bytes_per_launch": kernel_bytes,

@@ -69,7 +69,9 @@ typedef struct {
   int32_t flags;            /* GABP_FLAG_* bits                                     */
   int32_t layout;           /* message layout of the sweep kernels: 0 = pick by     */
                             /* timing at create, 1 = outgoing records + reverse-    */
-                            /* slot index, 2 = node broadcast (edge pairs in place) */
+                            /* slot index, 2 = node broadcast (edge pairs in place),*/
+                            /* 3 = compact node broadcast (one incoming message per */
+                            /* slot, the outgoing one recomputed by its sender)     */
   int32_t reserved;         /* must be 0                                            */
   double  gamma;            /* diagonal loading of Ch. 5: the inner solves use      */
                             /* A + gamma * diag(A); 0 = none; < 0 = chosen from an  */
@@ -107,7 +109,8 @@ typedef struct {
   int64_t n;                /* unknowns                                   */
   int64_t num_offdiag;      /* directed message slots E = nnz - n         */
   int32_t edges_per_block;  /* slots per workgroup in the sweep kernel    */
-  int32_t layout;           /* 1 = reverse-slot index, 2 = node broadcast */
+  int32_t layout;           /* 1 = reverse-slot index, 2 = node broadcast,*/
+                            /* 3 = compact node broadcast                 */
   int32_t pad;
   int32_t num_blocks;       /* workgroups per sweep launch                */
   int32_t max_degree;       /* largest off-diagonal row length            */

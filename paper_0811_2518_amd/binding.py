@@ -160,7 +160,7 @@ class Solver:
             precision={"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}[precision],
             check_every=check_every, edges_per_block=edges_per_block, gamma=gamma,
             loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
-            max_outer=max_outer, layout={"auto": 0, "edge": 1, "node": 2}[layout],
+            max_outer=max_outer, layout={"auto": 0, "edge": 1, "node": 2, "compact": 3}[layout],
             flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0))
         h = ctypes.c_void_p()
         st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),

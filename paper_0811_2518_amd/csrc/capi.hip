@@ -40,7 +40,7 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
       o.edges_per_block != 2048)
     return fail(c, GABP_E_ARG, "edges_per_block must be 0, 512, 1024 or 2048");
   if (o.inner_max_iter < 0 || o.max_outer < 0) return fail(c, GABP_E_ARG, "negative iteration cap");
-  if (o.layout < 0 || o.layout > kLayoutNode || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
+  if (o.layout < 0 || o.layout > kLayoutCompact || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
   if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
     return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
   return GABP_OK;
@@ -65,13 +65,14 @@ gabp_status alloc_solver(Ctx* c) {
   const int64_t n = c->n, E = c->E;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
   const size_t elt = fp32 ? sizeof(float) : sizeof(double);
-  const bool edge = c->opts.layout != kLayoutNode, node = c->opts.layout != kLayoutEdge;
+  const bool edge = !node_family(c->opts.layout), node = c->opts.layout != kLayoutEdge;
+  if (node)
+    for (int i = 0; i < 3; ++i) TRY(dev_alloc(c, &c->agg_d[i], 2 * elt * n));
   for (int i = 0; i < 2; ++i) {
     if (edge) {
       TRY(dev_alloc(c, &c->msg_d[i], msg_bytes((int)elt, true) * E));
       c->hmsg_d[i] = c->msg_d[i];  // h-only sweeps reuse the message buffers
     }
-    if (node) TRY(dev_alloc(c, &c->agg_d[i], 2 * elt * n));
     TRY(dev_alloc(c, (void**)&c->x64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->pt64_d[i], sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->xo_d[i], sizeof(double) * n));
@@ -102,15 +103,19 @@ gabp_status alloc_solver(Ctx* c) {
 }
 
 void release_unused_layout(Ctx* c) {
-  if (c->layout == kLayoutNode) {
+  if (node_family(c->layout)) {
     for (int i = 0; i < 2; ++i) {
       dev_free(c, c->msg_d[i]);
       c->msg_d[i] = c->hmsg_d[i] = nullptr;
     }
+    if (c->layout == kLayoutNode) {  // two aggregate generations suffice
+      dev_free(c, c->agg_d[2]);
+      c->agg_d[2] = nullptr;
+    }
   } else {
     dev_free(c, c->bstate_d);
     c->bstate_d = nullptr;
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 3; ++i) {
       dev_free(c, c->agg_d[i]);
       c->agg_d[i] = nullptr;
     }
@@ -196,6 +201,12 @@ gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
   if (c->last_msg_round == 0) {  // round 0: every message is zero (initial state of Alg. 2)
     GABP_HIP(c, launch_fill(P, c->E, 0.0, c->stream));
     GABP_HIP(c, launch_fill(hm, c->E, 0.0, c->stream));
+  } else if (c->layout == kLayoutCompact) {
+    // out^(T) recomputed from in^(T-1) and the aggregates of round T-1
+    const int T = c->last_msg_round;
+    const void* in_prev = (char*)c->bstate_d + ((T - 1) & 1) * 2 * sizeof(double) * (size_t)c->E;
+    GABP_HIP(c, launch_cnode_out(c->n, c->off_ptr_d, c->a64_d, in_prev, c->agg_d[(T - 1) % 3], T == 1, P, hm,
+                                 c->stream));
   } else if (c->layout == kLayoutNode) {
     GABP_HIP(c, launch_split_out(c->bstate_d, P, hm, c->E, c->stream));
   } else {

@@ -96,8 +96,43 @@ struct BcastArgs {
   int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
 };
 
-constexpr int kLayoutEdge = 1;  // outgoing message records + reverse-slot index
-constexpr int kLayoutNode = 2;  // node broadcast: aggregates published, edge pairs kept in place
+// Arguments of one compact node-broadcast sweep launch (compact.hip).
+template <typename T>
+struct CnodeArgs {
+  const int32_t* blk_row;
+  const int32_t* blk_e0;   // [nblk+1] first slot of each workgroup
+  const int32_t* off_ptr;
+  const int32_t* col;      // [E] neighbour of each slot
+  const T* a;              // [E] A_ji of slot (j, i)
+  const T* diag;           // [n] P_ii (possibly loaded)
+  const T* rhs;            // [n]
+  void* cin;               // [E] incoming messages: round t-2 on entry, round t on exit (freeze: round T)
+  const void* cin_old;     // [E] freeze only: incoming messages of round T-1
+  const void* agg2;        // [n] aggregates of round t-2 (freeze: T-1)
+  const void* agg1;        // [n] aggregates of round t-1 (freeze: T)
+  void* anew;              // [n] aggregates of round t
+  void* a0out;             // [n] first joint sweep only: the prior written as round-0 aggregates
+  const void* coef;        // [E] frozen {g_in, g_out}
+  void* coef_out;          // freeze output
+  const T* inv_pt;         // [n] frozen 1 / P~
+  T* inv_pt_out;           // freeze output
+  T* xout;                 // [n] means of round t
+  T* xout_prev;            // [n] first sweep only: means of round 0
+  T* ptout;                // [n] P~ of round t (nullable)
+  T* ptout_prev;           // [n] first sweep only: P~ of round 0 (nullable)
+  double* partials;
+  DevStatus* st;
+  int32_t nblk;
+  int32_t first;           // t == 1 (freeze: T == 0): round t-1 is the prior, no outgoing message yet
+  int32_t second;          // t == 2 (freeze: T == 1): round t-2 is the prior, its messages are zero
+  int32_t check;
+  int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
+};
+
+constexpr int kLayoutEdge = 1;     // outgoing message records + reverse-slot index
+constexpr int kLayoutNode = 2;     // node broadcast: aggregates published, edge pairs kept in place
+constexpr int kLayoutCompact = 3;  // node broadcast, one incoming message per slot, outgoing recomputed
+inline bool node_family(int layout) { return layout == kLayoutNode || layout == kLayoutCompact; }
 
 // Everything a handle owns.  Device arrays are suffixed _d.
 struct Ctx {
@@ -130,6 +165,7 @@ struct Ctx {
   int32_t K = 0;               // slots per lane
   int32_t nblk = 0;
   int32_t* blk_row_d = nullptr;
+  int32_t* blk_e0_d = nullptr;  // first slot of each workgroup (same allocation as blk_row_d)
   int32_t nblk_capacity = 0;
   int32_t partials_capacity = 0;
   std::vector<int32_t> off_ptr_h;
@@ -144,7 +180,9 @@ struct Ctx {
   int last_msg_round = -1;              // round held by msg_d[last_msg_round & 1] (tol <= 0 solves)
   int layout = kLayoutEdge;
   void* bstate_d = nullptr;             // node layout: per-slot message pairs [E]
-  void* agg_d[2] = {nullptr, nullptr};  // node layout: published aggregates by round parity [n]
+                                        // (compact layout: the two incoming-message buffers)
+  void* agg_d[3] = {nullptr, nullptr, nullptr};  // published aggregates [n]: by round parity (node
+                                                 // layout), by round mod 3 (compact layout)
 
   // node vectors
   double* x64_d[2] = {nullptr, nullptr};  // x of rounds (plain) / inner FP64 iterates
@@ -242,6 +280,12 @@ template <typename T>
 hipError_t launch_bcast(int mode, int K, const BcastArgs<T>& a, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 hipError_t launch_split_out(const void* state, double* P, double* h, int64_t E, hipStream_t s);
+template <typename T>
+hipError_t launch_cnode(int mode, int K, const CnodeArgs<T>& a, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+hipError_t launch_cnode_out(int32_t n, const int32_t* off_ptr, const double* a, const void* in_prev,
+                            const void* agg_prev, bool zero_in, double* P, double* h, hipStream_t s);
+size_t cnode_lds_bytes(int K, int elt);
 size_t bcast_state_bytes(int elt);
 size_t bcast_coef_bytes(int elt);
 size_t bcast_lds_bytes(int K, int elt);

@@ -265,13 +265,16 @@ gabp_status set_partition(Ctx* c, int K) {
   std::vector<int32_t> br;
   build_partition(c, K, br);
   const int32_t nb = (int32_t)br.size() - 1;
+  // first rows, then first slots, of the workgroups: [2 (nb + 1)]
+  for (int32_t i = 0; i <= nb; ++i) br.push_back(c->off_ptr_h[br[i]]);
   if (c->blk_row_d == nullptr || nb > c->nblk_capacity) {
     void* p = nullptr;
-    GABP_TRY(dev_alloc(c, &p, sizeof(int32_t) * (nb + 1)));
+    GABP_TRY(dev_alloc(c, &p, sizeof(int32_t) * 2 * (nb + 1)));
     c->blk_row_d = (int32_t*)p;
     c->nblk_capacity = nb;
   }
-  GABP_HIP(c, hipMemcpyAsync(c->blk_row_d, br.data(), sizeof(int32_t) * (nb + 1),
+  c->blk_e0_d = c->blk_row_d + (nb + 1);
+  GABP_HIP(c, hipMemcpyAsync(c->blk_row_d, br.data(), sizeof(int32_t) * 2 * (nb + 1),
                              hipMemcpyHostToDevice, c->stream));
   GABP_HIP(c, hipStreamSynchronize(c->stream));
   c->K = K;

@@ -206,17 +206,96 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
   return poll.err;
 }
 
+// Compact layout: the incoming messages of even and odd rounds live in the
+// two halves of the slot-state buffer (in^(t) overwrites in^(t-2) in place);
+// the aggregates rotate through three buffers by round mod 3.
+template <typename T>
+void* cin_buf(const Ctx* c, int parity) {
+  return (char*)c->bstate_d + (parity & 1) * 2 * sizeof(T) * (size_t)c->E;
+}
+
+// Compact node layout: like run_node, sweep t publishes round t and checks
+// round t-1; rounds 1..M, then a residual-only launch for round M.
+template <typename T>
+gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
+  hipStream_t s = c->stream;
+  const bool exact = cfg.tol <= 0.0;
+  const int M = cfg.max_iter;
+  const int ce = std::max(1, cfg.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+
+  CnodeArgs<T> a{};
+  a.blk_row = c->blk_row_d;
+  a.blk_e0 = c->blk_e0_d;
+  a.off_ptr = c->off_ptr_d;
+  a.col = c->off_col_d;
+  a.a = coef_array<T>(c);
+  a.diag = (const T*)cfg.diag;
+  a.rhs = (const T*)cfg.rhs;
+  a.coef = c->gcoef_d;
+  a.inv_pt = (const T*)c->inv_pt_d;
+  a.partials = c->partials_d;
+  a.st = cfg.st;
+  a.nblk = c->nblk;
+  a.honly_nodes = cfg.honly ? 1 : 0;
+  const double tol = exact ? -1.0 : cfg.tol;
+  GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
+
+  const int main_mode = cfg.honly ? kHOnly : kJoint;
+  const int last = M + 1;
+  int t = 1, chunk = 2;
+  Poller poll;
+  bool stop = false;
+  while (t <= last && !stop) {
+    const int tend = std::min(last, t + chunk - 1);
+    for (; t <= tend; ++t) {
+      const int mode = (t <= M) ? main_mode : kResid;
+      CnodeArgs<T> k = a;
+      k.first = (t == 1);
+      k.second = (t == 2);
+      k.cin = cin_buf<T>(c, t);
+      k.agg1 = c->agg_d[(t - 1) % 3];
+      k.agg2 = c->agg_d[(t + 1) % 3];  // round t-2
+      k.anew = c->agg_d[t % 3];
+      if (mode == kJoint && t == 1) k.a0out = c->agg_d[0];
+      if (mode != kResid) {
+        const bool wx = exact ? t == M : in_set(t);
+        k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
+        k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
+      }
+      if (t == 1 && (exact ? M == 0 : in_set(0))) {
+        k.xout_prev = (T*)cfg.x2[0];
+        k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
+      }
+      const bool ck = exact ? (t == M + 1) : in_set(t - 1);
+      k.check = ck ? 1 : 0;
+      if (mode == kResid && !ck) continue;
+      hipEvent_t e0, e1;
+      start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck, &e0, &e1);
+      if (e0) c->timed_mode = cfg.honly ? 1 : 0;
+      GABP_HIP(c, launch_cnode<T>(mode, c->K, k, s, e0, e1));
+      if (ck)
+        GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
+                                        true, s));
+    }
+    stop = poll.step(c, cfg.st);
+    chunk = std::min(chunk * 2, 16);
+  }
+  return poll.err;
+}
+
 template <typename T>
 gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+  if (c->layout == kLayoutCompact) return run_cnode<T>(c, cfg);
   return c->layout == kLayoutNode ? run_node<T>(c, cfg) : run_edge<T>(c, cfg);
 }
 
 // Latest round whose messages are held after a solve stopped at round
 // `conv` (or ran out at max_iter): sweeps past convergence return at once, so
-// the edge layout (lagged by two) holds round conv+2, the node layout conv+1.
+// the edge layout (lagged by two) holds round conv+2, the node layouts conv+1.
 int held_round(const Ctx* c, int conv, int M) {
   if (conv < 0) return M;
-  return std::min(conv + (c->layout == kLayoutNode ? 1 : 2), M);
+  return std::min(conv + (node_family(c->layout) ? 1 : 2), M);
 }
 
 // Sum the durations of the timed sweeps (after the stream has been synchronised).
@@ -258,7 +337,28 @@ template <typename T>
 gabp_status freeze(Ctx* c, int round, const void* diag, const void* rhs, int prec) {
   DevStatus* st = c->st_d + 1;  // fresh status: the freeze must not be skipped
   GABP_HIP(c, launch_reset_status(st, 1, c->stream));
-  if (c->layout == kLayoutNode) {
+  if (c->layout == kLayoutCompact) {
+    CnodeArgs<T> k{};
+    k.blk_row = c->blk_row_d;
+    k.blk_e0 = c->blk_e0_d;
+    k.off_ptr = c->off_ptr_d;
+    k.col = c->off_col_d;
+    k.a = coef_array<T>(c);
+    k.diag = (const T*)diag;
+    k.rhs = (const T*)rhs;
+    k.cin = cin_buf<T>(c, round);
+    k.cin_old = cin_buf<T>(c, round + 1);  // round - 1
+    k.agg1 = c->agg_d[round % 3];
+    k.agg2 = c->agg_d[(round + 2) % 3];  // round - 1
+    k.first = (round == 0);
+    k.second = (round == 1);
+    k.coef_out = c->gcoef_d;
+    k.inv_pt_out = (T*)c->inv_pt_d;
+    k.partials = c->partials_d;
+    k.st = st;
+    k.nblk = c->nblk;
+    GABP_HIP(c, launch_cnode<T>(kFreeze, c->K, k, c->stream));
+  } else if (c->layout == kLayoutNode) {
     BcastArgs<T> k{};
     k.blk_row = c->blk_row_d;
     k.off_ptr = c->off_ptr_d;
@@ -496,7 +596,7 @@ bool cache_lookup(const std::string& path, const std::string& key, int* layout, 
     const auto pl = line.find("\"layout\": ");
     if (pk == std::string::npos || pl == std::string::npos) continue;
     const int k = std::atoi(line.c_str() + pk + 5), l = std::atoi(line.c_str() + pl + 10);
-    if ((k == 2 || k == 4 || k == 8) && (l == kLayoutEdge || l == kLayoutNode)) {
+    if ((k == 2 || k == 4 || k == 8) && (l == kLayoutEdge || node_family(l))) {
       *K = k;
       *layout = l;
       found = true;
@@ -551,10 +651,10 @@ gabp_status autotune(Ctx* c) {
   const int epb = c->opts.edges_per_block;
   std::vector<int> layouts, Ks;
   if (c->opts.layout) layouts.push_back(c->opts.layout);
-  else layouts = {kLayoutEdge, kLayoutNode};
+  else layouts = {kLayoutEdge, kLayoutNode, kLayoutCompact};
   if (epb) Ks.push_back(epb / kBlock);
   else Ks = {2, 4, 8};
-  int best_l = layouts.back(), best_k = epb ? epb / kBlock : 4;
+  int best_l = c->opts.layout ? c->opts.layout : kLayoutNode, best_k = epb ? epb / kBlock : 4;
   if (c->E >= 200000 && layouts.size() * Ks.size() > 1) {
     const std::string key = tune_key(c);
     const char* path = std::getenv("GABP_AUTOTUNE_CACHE");

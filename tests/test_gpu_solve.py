@@ -42,7 +42,7 @@ def dev(v):
 # the paper's worked example, round by round
 # ---------------------------------------------------------------------------
 
-LAYOUTS = ["edge", "node"]
+LAYOUTS = ["edge", "node", "compact"]
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -366,7 +366,7 @@ def test_reuse_precision_second_solve_and_layout_property(layout):
     # frozen precisions and must still reach the oracle's solution
     p = workloads.er_problem(5000, 8, 91, ratio=1.1)
     s = solver(p, layout=layout)
-    assert s.props()["layout"] == {"edge": 1, "node": 2}[layout]
+    assert s.props()["layout"] == {"edge": 1, "node": 2, "compact": 3}[layout]
     x1, i1 = s.solve(dev(p.b), tol=1e-12, max_iter=2000)
     b2 = np.random.default_rng(3).standard_normal(p.n)
     x2, i2 = s.solve(dev(b2), tol=1e-12, max_iter=2000)
@@ -376,12 +376,39 @@ def test_reuse_precision_second_solve_and_layout_property(layout):
 
 
 def test_layouts_agree_bitwise_on_means_after_fixed_rounds():
-    # both layouts compute the same synchronous rounds; only rounding of the
+    # all layouts compute the same synchronous rounds; only rounding of the
     # message records differs in storage, not in arithmetic order of a row sum
     p = workloads.er_problem(4000, 8, 92)
     xe, _ = solver(p, layout="edge").solve(dev(p.b), tol=0, max_iter=12)
     xn, _ = solver(p, layout="node").solve(dev(p.b), tol=0, max_iter=12)
     assert rel(xe, xn.cpu().numpy()) <= 1e-14
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 12])
+def test_compact_layout_is_the_node_iteration_operation_for_operation(T):
+    # the compact layout recomputes each outgoing message from the sender's
+    # own aggregate instead of storing it: same operations, same rounding
+    p = workloads.er_problem(4000, 8, 93)
+    sn, sc = solver(p, layout="node"), solver(p, layout="compact")
+    xn, _ = sn.solve(dev(p.b), tol=0, max_iter=T)
+    xc, _ = sc.solve(dev(p.b), tol=0, max_iter=T)
+    np.testing.assert_array_equal(xc.cpu().numpy(), xn.cpu().numpy())
+    Pn, hn = sn.messages()
+    Pc, hc = sc.messages()
+    np.testing.assert_array_equal(Pc.cpu().numpy(), Pn.cpu().numpy())
+    np.testing.assert_array_equal(hc.cpu().numpy(), hn.cpu().numpy())
+
+
+def test_compact_layout_frozen_precision_sweeps_match_node_layout():
+    # FP32 inner sweeps: precision phase, freeze, h-only sweeps, FP64 outer loop
+    p = workloads.er_problem(6000, 8, 94, ratio=1.1)
+    out = {}
+    for layout in ("node", "compact"):
+        s = solver(p, precision="fp32", layout=layout, edges_per_block=1024)
+        x, info = s.solve(dev(p.b), tol=TOL, max_iter=5000)
+        out[layout] = (x.cpu().numpy(), info["sweeps"], info["outer_iters"])
+    assert out["compact"][1:] == out["node"][1:]
+    np.testing.assert_array_equal(out["compact"][0], out["node"][0])
 
 
 def test_automatic_loading_brackets_walk_radius_and_solves():
