@@ -239,6 +239,11 @@ typedef struct {
   double  longest_item_ms;  /* duration of the longest item                      */
   int64_t precision_sweeps; /* precision-phase sweeps summed over items          */
   int64_t inner_sweeps;     /* right-hand-side sweeps summed over items          */
+  int32_t longest_sys;      /* system of the longest item                        */
+  int32_t longest_nrhs;     /* right-hand sides in that item                     */
+  int32_t longest_sweeps;   /* its inner sweeps                                  */
+  int32_t longest_psweeps;  /* its precision-phase sweeps                        */
+  double  longest_start_ms; /* its start after the first item's start            */
 } gabp_batch_profile;
 
 /* gabp_get_batch_profile -- load-balance figures of the last batched solve. */

@@ -8,12 +8,14 @@
 //   1. precision phase (FP32): synchronous P-only sweeps of Alg. 2 -- the P
 //      update has no b term, so the precisions are shared by all right-hand
 //      sides of the item -- until the node precisions P~_i stop changing; then
-//      freeze g_s = -A_ij / (P~_i - P_ji) and 1 / P~_i;
+//      freeze g_in = -A_ij / (P~_i - P_ji), g_out and 1 / P~_i;
 //   2. FP64 iterative refinement: r = b - A x in FP64; the correction A d = r
 //      by h-only FP32 sweeps on all right-hand sides of the group at once
-//      (messages stored [slot][rhs], so the reverse-message gather reads
-//      kg contiguous words), x += d in FP64; until every right-hand side
-//      reaches the relative residual tolerance.
+//      (messages and aggregates stored [slot][rhs] / [node][rhs], so a
+//      neighbour gather reads kg contiguous words), x += d in FP64; until
+//      every right-hand side reaches the relative residual tolerance.
+// Every sweep walks the item's rows in tiles with slot-parallel tasks (see
+// tile_pass); messages follow the compact one-message-per-slot form.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -25,18 +27,29 @@ namespace gabp {
 
 namespace {
 
-constexpr int kBT = 512;       // lanes per batched workgroup
-constexpr int kMaxGroup = 8;   // right-hand sides per work item
-constexpr float kPrecTol = 4e-7f;
+constexpr int kBT = 512;                // lanes per batched workgroup
+constexpr int kKT = 4;                  // tasks per lane per chunk (FP32 passes)
+constexpr int kMaxGroup = 8;            // right-hand sides per work item
+constexpr float kPrecTol = 4e-7f;    // precision phase: relative change of P~ to stop at
+constexpr float kPrecStall = 2e-5f;  // ... or below this, once it stops halving (FP32 rounding floor)
+constexpr int kPrecStallSweeps = 8;
+
+// Sweep kinds of the tile loop.
+enum TileKind : int {
+  kTP = 0,      // precision-only message sweep
+  kTFreeze = 1, // frozen h-update coefficients from the precisions of a round
+  kTH = 2,      // h-only message sweep, all right-hand sides of the item
+  kTSpmv = 3    // FP64 residual r = b - A x
+};
 
 struct Item {
   int32_t sys, j0, kg, k;  // right-hand sides j0 .. j0+kg-1 of k
   int32_t r0, r1;          // global rows of the system
   int64_t s0, s1;          // global off-diagonal slots of the system
-  int64_t off_e;           // item scratch: per-slot arrays (3 E floats)
-  int64_t off_n;           // per-node arrays (2 n floats)
+  int64_t off_e;           // item scratch: per-slot arrays (4 E floats)
+  int64_t off_n;           // per-node arrays (4 n floats)
   int64_t off_he;          // h messages (2 E kg floats)
-  int64_t off_nk;          // d and r (2 n kg floats)
+  int64_t off_nk;          // h aggregates and inner right-hand side (4 n kg floats)
   int64_t rhs_off;         // B / X offset of the system
 };
 
@@ -50,7 +63,6 @@ struct ItemInfo {
 struct BatchArgs {
   const int32_t* off_ptr;
   const int32_t* off_col;
-  const int32_t* rev;
   const float* a32;
   const double* a64;
   const float* d32;
@@ -72,108 +84,365 @@ struct BatchArgs {
   int32_t max_iter;
 };
 
+using f2 = float __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void lds_max(unsigned* slot, float v) {
   // nonnegative floats order like their bit patterns; NaN maps above +inf
   atomicMax(slot, isnan(v) ? 0x7f800001u : __float_as_uint(v));
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Views of one item's scratch.  The message recursion is the compact form of
+// Alg. 2: slot (j, i) keeps the incoming message i -> j of the even and of the
+// odd rounds; the outgoing message j -> i of the previous round is recomputed
+// from row j's own aggregate two rounds back,
+//     out^(t-1) = F(A_j^(t-2), in^(t-2)),   in^(t) = F(A_i^(t-1), out^(t-1)),
+// and the node aggregates rotate through three buffers (round mod 3).
+struct ItemView {
+  int n, kg, k, j0, r0;
+  int64_t s0, E;
+  f2* coef;        // [E] frozen {g_in, g_out}
+  float* P0;       // [2][E] incoming precisions by round parity
+  float* Pagg0;    // [3][n] P~ by round mod 3
+  float* invPt;    // [n] frozen 1 / P~
+  float* H0;       // [2][E kg] incoming h messages by round parity, [slot][rhs]
+  float* hagg0;    // [3][n kg] h~ by round mod 3, [node][rhs]
+  float* r32;      // [n kg] right-hand side of the correction system
+  const double* B; // [n][k] of the system
+  double* X;       // [n][k] of the system
+  // buffers of a round (pointer arithmetic keeps the view in registers)
+  __device__ float* P(int t) const { return P0 + (t & 1) * E; }
+  __device__ float* Pagg(int t) const { return Pagg0 + (t % 3) * (int64_t)n; }
+  __device__ float* H(int t) const { return H0 + (t & 1) * E * kg; }
+  __device__ float* hagg(int t) const { return hagg0 + (t % 3) * (int64_t)n * kg; }
+};
+
+constexpr int kWave = 64;
+constexpr int kWaves = kBT / kWave;
+constexpr int kWChunk = kWave * kKT;  // tasks per wave chunk (FP32 passes)
+
+// LDS of one wave (every wave walks its own tiles).
+struct WaveShared {
+  unsigned char* stage;  // kWChunk results (float; double for the residual, half as many)
+  uint16_t* row;         // tile-local row of each slot of the chunk
+  int32_t* ptr;          // tile-local slot offsets of the rows [kWave + 1]
+  float* own;            // [kWave] own values per (row, rhs): round t-2 (freeze: T-1)
+  float* own1;           // [kWave] own values per (row, rhs): round t-1 (freeze: T)
+};
+
+// Per-(row, right-hand side) results handed back by a tile sweep.
+struct RowOut {
+  float dmax, xmax;  // h sweep: change of d and size of d; P sweep: relative change of P~
+  double r2;         // residual: sum of squares of this lane's rows
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per right-hand-side sums: lane t < Tq always owns column t % kg, so the
-// partial sums of one column are combined in a fixed order.
-__device__ void column_sums(double v, int kg, int Tq, double* s_part, double* out) {
+// One pass of the given kind over all rows of an item.  The rows are cut into
+// tiles of R = 64 / kgE consecutive rows, and each wave of the workgroup
+// walks its own tiles (tile w, w + 8, ...) with wave-level synchronisation
+// only, so the waves' memory latencies overlap.  A tile's (slot, rhs) tasks
+// are processed in chunks of up to kWChunk, up to kKT per lane with every load
+// issued before the first is used; per-task results are staged in the wave's
+// LDS and summed per (row, rhs) in slot order by the lane that owns the pair.
+// The caller synchronises the workgroup after the pass.
+// Reciprocal for the FP32 inner passes (about 1 ulp; the FP64 outer loop
+// corrects whatever the inner solves leave).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int KIND>
+__device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const WaveShared& sh, RowOut& ro) {
+  const int lane = threadIdx.x & (kWave - 1);
+  // uniform within the wave: the tile loop runs on scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int kgE = (KIND == kTH || KIND == kTSpmv) ? V.kg : 1;
+  const int R = kWave / kgE;    // rows per tile; also slots per k-step of a chunk
+  constexpr int KT = (KIND == kTSpmv) ? kKT / 2 : kKT;  // FP64 tasks hold twice the registers
+  const int CHS = R * KT;       // slots per chunk
+  const bool first = (t == 1), second = (t == 2);  // sweeps (freeze: T == 0, T == 1)
+  // lane -> (slot offset, right-hand side); lanes R * kgE .. 63 idle when kgE
+  // does not divide 64
+  const bool tl = lane < R * kgE;
+  const int ls = lane / kgE, jj = lane % kgE;
+  const int kg = V.kg;
+  // item-local bases (uniform), so that every per-task address is a 32-bit
+  // offset from a scalar base
+  const int* off_ptr = A.off_ptr + V.r0;
+  const int* colp = A.off_col + V.s0;
+  const float* a32p = A.a32 + V.s0;
+  const double* a64p = A.a64 + V.s0;
+  const float* d32p = A.d32 + V.r0;
+  float* Pt_ = V.P(t);                                      // P: in^(t-2) -> in^(t); freeze: in^(T)
+  const float* Pold_ = V.P(t + 1);                          // freeze: in^(T-1)
+  const float* Pg_ = V.Pagg(KIND == kTFreeze ? t : t + 2);  // gathered P~ of round t-1 (T)
+  float* Ht_ = V.H(t);
+  const float* hg_ = V.hagg(t + 2);                         // gathered h~ of round t-1
+  const float* r32_ = V.r32;
+  const double* Xs = V.X + V.j0;
+  float* stagef = (float*)sh.stage;
+  double* staged = (double*)sh.stage;
+  const int ntiles = (V.n + R - 1) / R;
+
+  for (int tile = wave; tile < ntiles; tile += kWaves) {
+    const int tr0 = tile * R;
+    const int nr = min(R, V.n - tr0);
+    const int e0 = off_ptr[tr0] - (int)V.s0;  // item-local slot of the tile's first row
+    const int ne = off_ptr[tr0 + nr] - (int)V.s0 - e0;
+    const bool rl = tl && ls < nr;  // lane owns the (row ls, rhs jj) pair
+    const int i = tr0 + ls;         // item-local row of that pair
+
+    // per-task registers of one chunk
+    int tc[KT];
+    float ta[KT], tm[KT], tg[KT];
+    f2 tcf[KT];
+    double tad[KT], txd[KT];
+    auto load_chunk = [&](int cs0) {
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const int sl = cs0 + ls + k * R;  // tile-local slot
+        if (tl && sl < ne) {
+          const int e = e0 + sl;
+          const int c = colp[e] - V.r0;
+          tc[k] = c;
+          if (KIND == kTP || KIND == kTFreeze) {
+            ta[k] = a32p[e];
+            tm[k] = 0.f;
+            tcf[k] = f2{0.f, 0.f};
+            if (KIND == kTP && !first && !second) tm[k] = Pt_[e];  // in^(t-2)
+            if (KIND == kTFreeze && !first) {
+              tm[k] = Pt_[e];                                      // in^(T)
+              if (!second) tcf[k].x = Pold_[e];                    // in^(T-1)
+            }
+          } else if (KIND == kTH) {
+            tcf[k] = V.coef[e];
+            tm[k] = (!first && !second) ? Ht_[e * kg + jj] : 0.f;  // h_in^(t-2)
+          } else {
+            tad[k] = a64p[e];
+          }
+        }
+      }
+      // the gathers: neighbour aggregates of round t-1 (freeze: T), or x
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const int sl = cs0 + ls + k * R;
+        if (tl && sl < ne) {
+          const int c = tc[k];
+          if (KIND == kTP || KIND == kTFreeze) tg[k] = first ? d32p[c] : Pg_[c];
+          else if (KIND == kTH) tg[k] = (first ? r32_ : hg_)[c * kg + jj];
+          else txd[k] = Xs[c * V.k + jj];
+        }
+      }
+    };
+    load_chunk(0);
+
+    // row side: slot offsets and own values of round t-2 (freeze: T-1) and
+    // t-1 (T); what the epilogue needs besides is loaded here as well
+    int rp = 0;
+    float er = 0.f, eip = 0.f;  // epilogue: prior / inner right-hand side, 1 / P~
+    if (rl) {
+      rp = off_ptr[i] - (int)V.s0 - e0;
+      float o1 = 0.f, o2 = 0.f;
+      if (KIND == kTP) {
+        o1 = first ? d32p[i] : V.Pagg(t + 2)[i];
+        o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 1)[i]);
+        er = d32p[i];
+      } else if (KIND == kTFreeze) {
+        o1 = first ? d32p[i] : V.Pagg(t)[i];
+        o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 2)[i]);
+      } else if (KIND == kTH) {
+        const int q = i * kg + jj;
+        er = r32_[q];
+        eip = V.invPt[i];
+        o1 = first ? er : V.hagg(t + 2)[q];
+        o2 = second ? er : (first ? 0.f : V.hagg(t + 1)[q]);
+      }
+      sh.own[lane] = o2;
+      sh.own1[lane] = o1;
+    }
+    if (rl && jj == 0) sh.ptr[ls] = rp;
+    if (lane == 0) sh.ptr[nr] = ne;
+    wave_sync();
+    const int lo = rl ? sh.ptr[ls] : 0, hi = rl ? sh.ptr[ls + 1] : 0;
+
+    float accf = 0.f;
+    double accd = 0.0;
+    for (int cs0 = 0; cs0 < ne; cs0 += CHS) {
+      if (cs0 > 0) load_chunk(cs0);
+      const int cs1 = min(ne, cs0 + CHS);  // slots of this chunk
+      if (rl && jj == 0)
+        for (int e = max(lo, cs0); e < min(hi, cs1); ++e) sh.row[e - cs0] = (uint16_t)ls;
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const int sl = cs0 + ls + k * R;
+        if (tl && sl < ne) {
+          const int e = e0 + sl;
+          const int st = (sl - cs0) * kgE + jj;  // stage slot of the task
+          const int lr = sh.row[sl - cs0];
+          if (KIND == kTP) {
+            const float av2 = -ta[k] * ta[k];
+            float Pout = 0.f;
+            if (!first) Pout = av2 * rcp(sh.own[lr] - tm[k]);  // out^(t-1)
+            const float Pin = av2 * rcp(tg[k] - Pout);         // in^(t)
+            Pt_[e] = Pin;
+            stagef[st] = Pin;
+          } else if (KIND == kTFreeze) {
+            const float av = ta[k];
+            float Pout = 0.f;
+            if (!first) Pout = -av * av * rcp(sh.own[lr] - tcf[k].x);  // out^(T)
+            f2 cf;
+            cf.x = -av * rcp(tg[k] - Pout);          // g_in  = -a / (P~_i - P_ji)
+            cf.y = -av * rcp(sh.own1[lr] - tm[k]);   // g_out = -a / (P~_j - P_ij)
+            V.coef[e] = cf;
+            stagef[st] = cf.x + cf.y;  // finiteness only
+          } else if (KIND == kTH) {
+            float hout = 0.f;
+            if (!first) hout = tcf[k].y * (sh.own[lr * kgE + jj] - tm[k]);  // h_out^(t-1)
+            const float hin = tcf[k].x * (tg[k] - hout);                     // h_in^(t)
+            Ht_[e * kg + jj] = hin;
+            stagef[st] = hin;
+          } else {
+            staged[st] = tad[k] * txd[k];
+          }
+        }
+      }
+      wave_sync();
+      if (rl)
+        for (int e = max(lo, cs0); e < min(hi, cs1); ++e) {
+          const int st = (e - cs0) * kgE + jj;
+          if (KIND == kTSpmv) accd += staged[st];
+          else accf += stagef[st];
+        }
+      wave_sync();
+    }
+
+    // row epilogue
+    if (rl) {
+      const float o1 = sh.own1[lane];
+      if (KIND == kTP) {
+        const float Pt = er + accf;
+        V.Pagg(t)[i] = Pt;
+        ro.dmax = fmaxf(ro.dmax, fabsf(Pt - o1) / fabsf(Pt));
+      } else if (KIND == kTFreeze) {
+        const float ip = rcp(o1);
+        V.invPt[i] = ip;
+        if (!isfinite(accf) || !isfinite(ip)) ro.dmax = __int_as_float(0x7fc00000);
+      } else if (KIND == kTH) {
+        const float ht = er + accf;
+        V.hagg(t)[i * kg + jj] = ht;
+        const float dn = ht * eip;
+        const float dold = first ? 0.f : o1 * eip;
+        ro.dmax = fmaxf(ro.dmax, fabsf(dn - dold));
+        ro.xmax = fmaxf(ro.xmax, fabsf(dn));
+      } else {
+        const int q = i * V.k + V.j0 + jj;
+        const double r = V.B[q] - A.d64[V.r0 + i] * V.X[q] - accd;
+        V.r32[i * kg + jj] = (float)r;
+        ro.r2 += r * r;
+      }
+    }
+    wave_sync();  // the next tile rewrites the wave's LDS row structure
+  }
+}
+
+// Column of the (row, rhs) pairs a thread owns in the tile passes (threads
+// that own none contribute zeros under any column).
+__device__ __forceinline__ int tile_col(int kg) { return (threadIdx.x & (kWave - 1)) % kg; }
+
+// Per right-hand-side sums of one value per thread, column `col`, combined in
+// thread order (deterministic).
+__device__ void col_sums(double v, int col, int kg, double* s_part, int* s_cidx, double* out) {
   const int tid = threadIdx.x;
-  s_part[tid] = (tid < Tq) ? v : 0.0;
+  s_part[tid] = v;
+  s_cidx[tid] = col;
   __syncthreads();
   if (tid < kg) {
     double acc = 0.0;
-    for (int t = tid; t < Tq; t += kg) acc += s_part[t];
+    for (int t = 0; t < kBT; ++t)
+      if (s_cidx[t] == tid) acc += s_part[t];
     out[tid] = acc;
   }
   __syncthreads();
 }
 
-__device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* s_max, double* s_part,
-                           double* s_col, double* s_bn, int* s_flag) {
+__device__ void solve_item(const BatchArgs& A, const Item& I, int it, const WaveShared& sh, unsigned* s_max,
+                           double* s_part, int* s_cidx, double* s_col, double* s_bn, int* s_flag) {
   const int tid = threadIdx.x;
-  const int n = I.r1 - I.r0;
-  const int64_t E = I.s1 - I.s0;
-  const int kg = I.kg, k = I.k;
-  const int Tq = (kBT / kg) * kg;  // lanes used for (row, rhs) items
-  float* P0 = A.ebuf + 3 * I.off_e;
-  float* P1 = P0 + E;
-  float* g = P1 + E;
-  float* Ptprev = A.nbuf + 2 * I.off_n;
-  float* invPt = Ptprev + n;
-  float* h0 = A.hbuf + 2 * I.off_he;
-  float* h1 = h0 + E * kg;
-  float* d = A.kbuf + 2 * I.off_nk;
-  float* r32 = d + (int64_t)n * kg;
-  const double* B = A.B + I.rhs_off;
-  double* X = A.X + I.rhs_off;
+  ItemView V;
+  V.n = I.r1 - I.r0;
+  V.kg = I.kg;
+  V.k = I.k;
+  V.j0 = I.j0;
+  V.r0 = I.r0;
+  V.s0 = I.s0;
+  V.E = I.s1 - I.s0;
+  float* eb = A.ebuf + 4 * I.off_e;
+  V.coef = (f2*)eb;
+  V.P0 = eb + 2 * V.E;
+  float* nb = A.nbuf + 4 * I.off_n;
+  V.Pagg0 = nb;
+  V.invPt = nb + 3 * (int64_t)V.n;
+  V.H0 = A.hbuf + 2 * I.off_he;
+  float* kb = A.kbuf + 4 * I.off_nk;
+  const int64_t nk = (int64_t)V.n * V.kg;
+  V.hagg0 = kb;
+  V.r32 = kb + 3 * nk;
+  V.B = A.B + I.rhs_off;
+  V.X = A.X + I.rhs_off;
+  const int kg = V.kg;
+  const int Tq = (kBT / kg) * kg;  // lanes that own (row, rhs) pairs
   int status = 0;
   const uint64_t t_start = wall_clock64();
 
-  // ---- 1. precision phase --------------------------------------------------
+  // ---- 1. precision phase: P-only sweeps until P~ settles ------------------
+  // The FP32 change of P~ settles at a rounding floor that can lie above
+  // kPrecTol on weakly dominant systems; the phase also ends once the change
+  // is small and has stopped halving (the FP64 refinement absorbs the rest).
   int tp = 1;
+  float best = INFINITY;
+  int tbest = 0;
   for (;; ++tp) {
-    const float* Pold = (tp & 1) ? P0 : P1;
-    float* Pnew = (tp & 1) ? P1 : P0;
     if (tid == 0) s_max[0] = 0u;
     __syncthreads();
-    float lmax = 0.f;
-    for (int i = tid; i < n; i += kBT) {
-      const int R = I.r0 + i;
-      const int lo = A.off_ptr[R], hi = A.off_ptr[R + 1];
-      float Pt = A.d32[R];
-      if (tp > 1)
-        for (int s = lo; s < hi; ++s) Pt += Pold[A.rev[s] - I.s0];
-      if (tp > 1) lmax = fmaxf(lmax, fabsf(Pt - Ptprev[i]) / fabsf(Pt));
-      Ptprev[i] = Pt;
-      for (int s = lo; s < hi; ++s) {
-        const float pin = (tp > 1) ? Pold[A.rev[s] - I.s0] : 0.f;
-        const float av = A.a32[s];
-        Pnew[s - I.s0] = -av * av / (Pt - pin);
-      }
-    }
-    lds_max(&s_max[0], lmax);
-    __syncthreads();
+    RowOut ro{0.f, 0.f, 0.0};
+    tile_pass<kTP>(A, V, tp, sh, ro);
+    lds_max(&s_max[0], ro.dmax);
+    __syncthreads();  // also orders this round's aggregates before the next pass
     const float ch = __uint_as_float(s_max[0]);
     __syncthreads();
+    if (ch < 0.5f * best) {
+      best = ch;
+      tbest = tp;
+    }
     if (tp >= 3 && ch <= kPrecTol) break;
+    if (tp - tbest >= kPrecStallSweeps && best <= kPrecStall) break;
     if (tp >= A.inner_max || !(ch <= 1e30f)) break;
   }
-  // freeze from the last round's precisions
+  // freeze the h-update coefficients from the precisions of round tp
   {
-    const float* Pf = (tp & 1) ? P1 : P0;
-    for (int i = tid; i < n; i += kBT) {
-      const int R = I.r0 + i;
-      const int lo = A.off_ptr[R], hi = A.off_ptr[R + 1];
-      float Pt = A.d32[R];
-      for (int s = lo; s < hi; ++s) Pt += Pf[A.rev[s] - I.s0];
-      invPt[i] = 1.f / Pt;
-      for (int s = lo; s < hi; ++s) g[s - I.s0] = -A.a32[s] / (Pt - Pf[A.rev[s] - I.s0]);
-      if (!isfinite(1.f / Pt)) *s_flag = 1;
-    }
+    if (tid == 0) s_max[0] = 0u;
+    __syncthreads();
+    RowOut ro{0.f, 0.f, 0.0};
+    tile_pass<kTFreeze>(A, V, tp, sh, ro);
+    if (!(ro.dmax == 0.f)) *s_flag = 1;
     __syncthreads();
   }
 
-  // ---- 2. refinement -------------------------------------------------------
+  // ---- 2. FP64 refinement --------------------------------------------------
   const int jj = tid % kg;
   double bpart = 0.0;
   if (tid < Tq)
-    for (int q = tid; q < n * kg; q += Tq) {
+    for (int q = tid; q < V.n * kg; q += Tq) {
       const int i = q / kg;
-      const double bv = B[(int64_t)i * k + I.j0 + jj];
-      X[(int64_t)i * k + I.j0 + jj] = 0.0;
-      r32[q] = (float)bv;
+      const double bv = V.B[(int64_t)i * V.k + V.j0 + jj];
+      V.X[(int64_t)i * V.k + V.j0 + jj] = 0.0;
+      V.r32[q] = (float)bv;
       bpart += bv * bv;
     }
-  column_sums(bpart, kg, Tq, s_part, s_bn);
+  col_sums(bpart, tid % kg, kg, s_part, s_cidx, s_bn);
   if (tid < kg) s_bn[tid] = sqrt(s_bn[tid]);
   __syncthreads();
 
@@ -183,33 +452,12 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* 
     // inner: h-only sweeps on the correction system A d = r
     int t = 1;
     for (;; ++t) {
-      const float* hold = (t & 1) ? h0 : h1;
-      float* hnew = (t & 1) ? h1 : h0;
       if (tid < 2 * kMaxGroup) s_max[tid] = 0u;
       __syncthreads();
-      float dmax = 0.f, xmax = 0.f;
-      if (tid < Tq)
-        for (int q = tid; q < n * kg; q += Tq) {
-          const int i = q / kg;
-          const int R = I.r0 + i;
-          const int lo = A.off_ptr[R], hi = A.off_ptr[R + 1];
-          float ht = r32[q];
-          if (t > 1)
-            for (int s = lo; s < hi; ++s) ht += hold[(int64_t)(A.rev[s] - I.s0) * kg + jj];
-          const float dn = ht * invPt[i];
-          const float dold = (t > 1) ? d[q] : 0.f;
-          d[q] = dn;
-          dmax = fmaxf(dmax, fabsf(dn - dold));
-          xmax = fmaxf(xmax, fabsf(dn));
-          for (int s = lo; s < hi; ++s) {
-            const float hin = (t > 1) ? hold[(int64_t)(A.rev[s] - I.s0) * kg + jj] : 0.f;
-            hnew[(int64_t)(s - I.s0) * kg + jj] = g[s - I.s0] * (ht - hin);
-          }
-        }
-      if (tid < Tq) {
-        lds_max(&s_max[jj], dmax);
-        lds_max(&s_max[kMaxGroup + jj], xmax);
-      }
+      RowOut ro{0.f, 0.f, 0.0};
+      tile_pass<kTH>(A, V, t, sh, ro);
+      lds_max(&s_max[tile_col(kg)], ro.dmax);
+      lds_max(&s_max[kMaxGroup + tile_col(kg)], ro.xmax);
       __syncthreads();
       bool done = t >= 2;
       for (int j = 0; j < kg; ++j) {
@@ -221,22 +469,18 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* 
       if (done || status || total + t >= A.max_iter || t >= A.inner_max) break;
     }
     total += t;
-    // x += d (FP64), then r = b - A x
-    if (tid < Tq)
-      for (int q = tid; q < n * kg; q += Tq) X[(int64_t)(q / kg) * k + I.j0 + jj] += (double)d[q];
+    // x += d (FP64) with d = h~ / P~ of the last inner round, then r = b - A x
+    {
+      const float* hT = V.hagg(t);
+      if (tid < Tq)
+        for (int q = tid; q < V.n * kg; q += Tq)
+          V.X[(int64_t)(q / kg) * V.k + V.j0 + jj] += (double)(hT[q] * V.invPt[q / kg]);
+      __syncthreads();
+    }
+    RowOut ro{0.f, 0.f, 0.0};
     __syncthreads();
-    double rpart = 0.0;
-    if (tid < Tq)
-      for (int q = tid; q < n * kg; q += Tq) {
-        const int i = q / kg;
-        const int R = I.r0 + i;
-        double r = B[(int64_t)i * k + I.j0 + jj] - A.d64[R] * X[(int64_t)i * k + I.j0 + jj];
-        for (int s = A.off_ptr[R]; s < A.off_ptr[R + 1]; ++s)
-          r -= A.a64[s] * X[(int64_t)(A.off_col[s] - I.r0) * k + I.j0 + jj];
-        r32[q] = (float)r;
-        rpart += r * r;
-      }
-    column_sums(rpart, kg, Tq, s_part, s_col);
+    tile_pass<kTSpmv>(A, V, 0, sh, ro);
+    col_sums(ro.r2, tile_col(kg), kg, s_part, s_cidx, s_col);
     ++outer;
     relmax = 0.0;
     for (int j = 0; j < kg; ++j) {
@@ -271,23 +515,60 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, unsigned* 
   __syncthreads();
 }
 
+// The item record read by every lane, made provably uniform (the compiler
+// cannot use scalar loads for it), so that everything derived from it stays in
+// scalar registers.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ Item uniform_item(const Item& x) {
+  Item u;
+  u.sys = uni(x.sys);
+  u.j0 = uni(x.j0);
+  u.kg = uni(x.kg);
+  u.k = uni(x.k);
+  u.r0 = uni(x.r0);
+  u.r1 = uni(x.r1);
+  u.s0 = uni(x.s0);
+  u.s1 = uni(x.s1);
+  u.off_e = uni(x.off_e);
+  u.off_n = uni(x.off_n);
+  u.off_he = uni(x.off_he);
+  u.off_nk = uni(x.off_nk);
+  u.rhs_off = uni(x.rhs_off);
+  return u;
+}
+
 __global__ __launch_bounds__(kBT) void k_batched(BatchArgs A) {
   __shared__ int s_item;
   __shared__ int s_flag;
   __shared__ unsigned s_max[2 * kMaxGroup];
   __shared__ double s_part[kBT];
+  __shared__ int s_cidx[kBT];
   __shared__ double s_col[kMaxGroup];
   __shared__ double s_bn[kMaxGroup];
+  // per-wave tile scratch
+  __shared__ __align__(16) unsigned char s_stage[kWaves][kWChunk * sizeof(float)];
+  __shared__ uint16_t s_row[kWaves][kWChunk];
+  __shared__ int32_t s_ptr[kWaves][kWave + 4];
+  __shared__ float s_own[kBT];
+  __shared__ float s_own1[kBT];
+  const int w = threadIdx.x / kWave;
+  const WaveShared sh{s_stage[w], s_row[w], s_ptr[w], s_own + w * kWave, s_own1 + w * kWave};
   for (;;) {
     if (threadIdx.x == 0) {
       s_item = (int)atomicAdd(A.queue, 1u);
       s_flag = 0;
     }
     __syncthreads();
-    const int it = s_item;
+    // uniform across the workgroup: keeps the item's fields in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= A.num_items) return;  // every workgroup leaves once the queue is empty
-    solve_item(A, A.items[it], it, s_max, s_part, s_col, s_bn, &s_flag);
+    solve_item(A, uniform_item(A.items[it]), it, sh, s_max, s_part, s_cidx, s_col, s_bn, &s_flag);
   }
 }
 
@@ -295,10 +576,44 @@ __global__ void k_reset_queue(uint32_t* q) {
   if (threadIdx.x == 0) *q = 0u;
 }
 
+// Smallest diagonal-dominance ratio |A_ii| / sum_j |A_ij| over the rows of
+// each system (+inf for a system without off-diagonal entries).
+__global__ __launch_bounds__(256) void k_sys_ratio(int num_sys, const int32_t* __restrict__ sys_row_off,
+                                                   const int32_t* __restrict__ off_ptr,
+                                                   const double* __restrict__ a, const double* __restrict__ d,
+                                                   float* __restrict__ out) {
+  __shared__ float s_min[256];
+  for (int s = blockIdx.x; s < num_sys; s += gridDim.x) {
+    float m = INFINITY;
+    for (int r = sys_row_off[s] + (int)threadIdx.x; r < sys_row_off[s + 1]; r += 256) {
+      double sum = 0.0;
+      for (int q = off_ptr[r]; q < off_ptr[r + 1]; ++q) sum += fabs(a[q]);
+      if (sum > 0.0) m = fminf(m, (float)(fabs(d[r]) / sum));
+    }
+    s_min[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) s_min[threadIdx.x] = fminf(s_min[threadIdx.x], s_min[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[s] = s_min[0];
+    __syncthreads();
+  }
+}
+
+// Relative sweep count of a system for the work estimate: Jacobi-like
+// contraction by about 1 / rho per sweep for dominance ratio rho, so the
+// sweeps to a fixed reduction scale as 1 / ln(rho) (bounded both ways).
+double sweep_weight(float ratio) {
+  if (!(ratio > 1.0f)) return 100.0;
+  return std::min(100.0, std::max(0.1, 1.0 / std::log((double)ratio)));
+}
+
 struct BatchState {
   int32_t num_sys = 0;
   std::vector<int32_t> sys_row_off;
   std::vector<int64_t> sys_slot_off;
+  std::vector<double> sys_weight;  // relative sweeps per system (work estimate)
   // per-solve work list and scratch (grown on demand)
   std::vector<Item> items;
   Item* items_d = nullptr;
@@ -368,6 +683,29 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off) 
   // the graph is captured and replayed on a stream of the handle's own, ordered
   // after the caller's stream by synchronisation (capture needs a non-null stream)
   GABP_HIP(c, hipStreamCreateWithFlags(&bs->gs, hipStreamNonBlocking));
+  // per-system dominance ratios for the work estimate
+  bs->sys_weight.assign(num_sys, 1.0);
+  if (c->E > 0) {
+    int32_t* so_d = nullptr;
+    float* ratio_d = nullptr;
+    std::vector<float> ratio(num_sys);
+    hipError_t e = hipMalloc((void**)&so_d, sizeof(int32_t) * (num_sys + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&ratio_d, sizeof(float) * num_sys);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(so_d, sys_row_off, sizeof(int32_t) * (num_sys + 1), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_sys_ratio, dim3(std::min(num_sys, 4096)), dim3(256), 0, c->stream, num_sys, so_d,
+                         c->off_ptr_d, c->a64_d, c->d64_d, ratio_d);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ratio.data(), ratio_d, sizeof(float) * num_sys, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    free_raw(so_d);
+    free_raw(ratio_d);
+    if (e != hipSuccess) return hip_fail(c, e, "batched work estimate");
+    for (int s = 0; s < num_sys; ++s) bs->sys_weight[s] = sweep_weight(ratio[s]);
+  }
   // FP32 copies of the diagonal (no loading for batched solves)
   {
     void* p = nullptr;
@@ -396,14 +734,17 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
                     bs->key_nrhs == std::vector<int32_t>(nrhs, nrhs + S) &&
                     bs->key_off == std::vector<int64_t>(rhs_off, rhs_off + S + 1);
   if (!same) {
-    // Work items, largest first.  The work of a right-hand side per sweep is
-    // taken as E_s + n_s; a system's right-hand sides are grouped so that no
-    // item exceeds half of an even share of the whole batch per workgroup,
-    // which keeps the longest item below the average workgroup load.
+    // Work items, costliest first.  The work of one right-hand side is taken
+    // as (E_s + n_s) per sweep times the system's relative sweep count; a
+    // system's right-hand sides are grouped so that no item exceeds half of
+    // an even share of the whole batch per workgroup, which keeps the longest
+    // item below the average workgroup load.
+    auto unit = [&](int s) {
+      return (double)(bs->sys_slot_off[s + 1] - bs->sys_slot_off[s] + bs->sys_row_off[s + 1] - bs->sys_row_off[s]) *
+             bs->sys_weight[s];
+    };
     double total = 0.0;
-    for (int s = 0; s < S; ++s)
-      total += (double)(bs->sys_slot_off[s + 1] - bs->sys_slot_off[s] + bs->sys_row_off[s + 1] -
-                        bs->sys_row_off[s]) * nrhs[s];
+    for (int s = 0; s < S; ++s) total += unit(s) * nrhs[s];
     const double cap = std::max(1.0, total / (2.0 * std::max(1, bs->grid)));
     std::vector<Item> items;
     int64_t oe = 0, on = 0, ohe = 0, onk = 0;
@@ -412,7 +753,7 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
       if (r1 == r0) continue;
       const int64_t E = bs->sys_slot_off[s + 1] - bs->sys_slot_off[s];
       const int32_t k = nrhs[s];
-      const int32_t group = (int32_t)std::max(1.0, std::min((double)kMaxGroup, std::floor(cap / (double)(E + r1 - r0))));
+      const int32_t group = (int32_t)std::max(1.0, std::min((double)kMaxGroup, std::floor(cap / std::max(1e-30, unit(s)))));
       for (int32_t j0 = 0; j0 < k; j0 += group) {
         Item it{};
         it.sys = s;
@@ -435,15 +776,14 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
         items.push_back(it);
       }
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-      const int64_t wa = ((a.s1 - a.s0) + (a.r1 - a.r0)) * a.kg, wb = ((b.s1 - b.s0) + (b.r1 - b.r0)) * b.kg;
-      return wa > wb;
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+      return unit(a.sys) * a.kg > unit(b.sys) * b.kg;
     });
     bs->items = items;
-    gabp_status r = grow(c, &bs->ebuf, &bs->ecap, 3 * oe);
-    if (r == GABP_OK) r = grow(c, &bs->nbuf, &bs->ncap, 2 * on);
+    gabp_status r = grow(c, &bs->ebuf, &bs->ecap, 4 * oe);
+    if (r == GABP_OK) r = grow(c, &bs->nbuf, &bs->ncap, 4 * on);
     if (r == GABP_OK) r = grow(c, &bs->hbuf, &bs->hcap, 2 * ohe);
-    if (r == GABP_OK) r = grow(c, &bs->kbuf, &bs->kcap, 2 * onk);
+    if (r == GABP_OK) r = grow(c, &bs->kbuf, &bs->kcap, 4 * onk);
     if (r != GABP_OK) return r;
     if (items.size() > bs->items_cap) {
       free_raw(bs->items_d);
@@ -461,7 +801,6 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     BatchArgs a{};
     a.off_ptr = c->off_ptr_d;
     a.off_col = c->off_col_d;
-    a.rev = c->rev_d;
     a.a32 = c->a32_d;
     a.a64 = c->a64_d;
     a.d32 = c->din32_d;
@@ -520,19 +859,30 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     pf.num_items = (int32_t)ii.size();
     pf.workgroups = bs->launched_grid;
     uint64_t lo = ~0ull, hi = 0;
-    double busy = 0.0, longest = 0.0;
-    for (const ItemInfo& q : ii) {
-      lo = std::min(lo, q.t0);
-      hi = std::max(hi, q.t1);
-      const double ms = (double)(q.t1 - q.t0) / bs->clock_khz;
+    double busy = 0.0, longest = -1.0;
+    size_t arg = 0;
+    for (size_t q = 0; q < ii.size(); ++q) {
+      lo = std::min(lo, ii[q].t0);
+      hi = std::max(hi, ii[q].t1);
+      const double ms = (double)(ii[q].t1 - ii[q].t0) / bs->clock_khz;
       busy += ms;
-      longest = std::max(longest, ms);
-      pf.precision_sweeps += q.psweeps;
-      pf.inner_sweeps += q.sweeps;
+      if (ms > longest) {
+        longest = ms;
+        arg = q;
+      }
+      pf.precision_sweeps += ii[q].psweeps;
+      pf.inner_sweeps += ii[q].sweeps;
     }
     pf.makespan_ms = ii.empty() ? 0.0 : (double)(hi - lo) / bs->clock_khz;
     pf.busy_ms = busy;
-    pf.longest_item_ms = longest;
+    pf.longest_item_ms = std::max(0.0, longest);
+    if (!ii.empty()) {
+      pf.longest_sys = bs->items[arg].sys;
+      pf.longest_nrhs = bs->items[arg].kg;
+      pf.longest_sweeps = ii[arg].sweeps;
+      pf.longest_psweeps = ii[arg].psweeps;
+      pf.longest_start_ms = (double)(ii[arg].t0 - lo) / bs->clock_khz;
+    }
   }
   // per-system info: worst over the system's items
   std::vector<gabp_info> out(S);

@@ -95,3 +95,32 @@ def test_batched_rejects_bad_rhs_layout(small_batch):
     bad[1] += 1
     X, infos, st = s.solve(bt.nrhs, bad, B, tol=TOL, check=False)
     assert st == binding.E_ARG
+
+
+def test_batched_groups_not_dividing_the_workgroup():
+    # many small systems, so that every system is one work item whose group
+    # is all of its k in {3, 5, 6, 7} right-hand sides: 512 lanes are then not
+    # a multiple of the group, tiles span several chunks and lanes carry
+    # several (slot, rhs) tasks of different right-hand sides
+    rng = np.random.default_rng(11)
+    probs, ks = [], []
+    for q in range(3000):
+        px, py = int(rng.integers(8, 13)), int(rng.integers(8, 13))
+        # one dominance ratio for all: equal work weights, so group = k
+        probs.append(workloads.grid2d_problem(px, py, 5000 + q, ratio=1.3))
+        ks.append(int(rng.choice([3, 5, 6, 7])))
+    bt = workloads.batch_of(probs, ks, seed=12)
+    s, B, X, infos, st = _solve(bt)
+    assert st == binding.OK
+    prof = s.profile()
+    assert prof["num_items"] == bt.num_sys  # one item per system: group = k
+    Xh = X.cpu().numpy()
+    for q in range(0, bt.num_sys, 7):
+        p = bt.system(q)
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        ref = np.linalg.solve(p.dense(), p.b)
+        assert np.linalg.norm(xs - ref) / np.linalg.norm(ref) <= 1e-8, q
+    # the FP32 inner solves to 1e-5 make each outer step gain ~5 digits
+    assert max(i["outer_iters"] for i in infos) <= 6
+    assert all(i["converged"] == 1 for i in infos)

@@ -310,6 +310,21 @@ def config3(num_sys=4096, nmin=64, nmax=65536, kmax=32, seed=SEED_BASE + 3, work
             systems = [sy for part in ex.map(_batch_chunk, chunks) for sy in part]
     else:
         systems = _batch_chunk((seqs, nmin, nmax, kmax))
+    return _assemble(systems)
+
+
+def batch_of(problems, nrhs, seed):
+    """Batch of the given systems with ``nrhs[s]`` right-hand sides each,
+    B ~ N(0,1) drawn in system order from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    systems = []
+    for p, k in zip(problems, nrhs):
+        B = rng.standard_normal((p.n, int(k)))
+        systems.append((p.row_ptr, p.col, p.val, B.ravel(), p.n, int(k), p.name, 0.0))
+    return _assemble(systems)
+
+
+def _assemble(systems):
     rps, cols, Bs, sizes, nrhs, kinds, ratios = [], [], [], [], [], [], []
     vals = []
     row0 = 0
