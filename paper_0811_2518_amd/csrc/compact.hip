@@ -96,18 +96,6 @@ __host__ __device__ constexpr size_t cn_lds(int K, int elt) {
          (size_t)kBlock * K;
 }
 
-// Aggregate record of node q from the array `arr` (round t-1 or t-2); the
-// prior (A_qq, b_q) -- or (1/P~_q, b_q) with frozen precisions -- stands in
-// for round 0.
-template <typename T, int MODE>
-__device__ __forceinline__ Msg<T> agg_of(const CnodeArgs<T>& A, const void* arr, bool prior, int q) {
-  if (prior) {
-    if (MODE == kHOnly || (MODE == kResid && A.honly_nodes)) return Msg<T>{A.inv_pt[q], A.rhs[q]};
-    return Msg<T>{A.diag[q], A.rhs[q]};
-  }
-  return ld_agg<T>(arr, q);
-}
-
 // Mean of a node from its aggregate record.
 template <typename T, int MODE>
 __device__ __forceinline__ T mean_of(const CnodeArgs<T>& A, Msg<T> g) {
@@ -235,23 +223,17 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     }
     if (A.first && A.xout_prev) A.xout_prev[r] = mean_of<T, MODE>(A, o1);
     if (A.first && A.ptout_prev) A.ptout_prev[r] = o1.P;
-    if (MODE == kJoint && A.first && A.a0out) {  // the prior as the aggregates of round 0
-      vec2<T> v;
-      v.x = o1.P;
-      v.y = o1.h;
-      ((vec2<T>*)A.a0out)[r] = v;
-    }
   };
 
   if (ne > S) {  // one long row: strided slots, block reductions
-    const Msg<T> o1 = agg_of<T, MODE>(A, A.agg1, A.first, r0);
-    const Msg<T> o2 = need_o2 ? agg_of<T, MODE>(A, A.agg2, A.second, r0) : Msg<T>{0, 0};
+    const Msg<T> o1 = ld_agg<T>(A.agg1, r0);
+    const Msg<T> o2 = need_o2 ? ld_agg<T>(A.agg2, r0) : Msg<T>{0, 0};
     T pP = 0, ph = 0;
     double pax = 0.0;
     for (int i = tid; i < ne; i += kBlock) {
       SlotIn<T> in;
       load_slot<T, MODE>(A, e0 + i, in);
-      const Msg<T> g = agg_of<T, MODE>(A, A.agg1, A.first, in.c);
+      const Msg<T> g = ld_agg<T>(A.agg1, in.c);
       T Pn, hn, ax;
       compute_slot<T, MODE>(A, e0 + i, in, g, o1, o2, Pn, hn, ax);
       pP += Pn;
@@ -294,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     T dr = 0, br = 0;
     if (tid < nrow) {
       rp = A.off_ptr[r] - e0;
-      o1 = agg_of<T, MODE>(A, A.agg1, A.first, r);
-      if (need_o2) o2 = agg_of<T, MODE>(A, A.agg2, A.second, r);
+      o1 = ld_agg<T>(A.agg1, r);
+      if (need_o2) o2 = ld_agg<T>(A.agg2, r);
       dr = A.diag[r];
       br = A.rhs[r];
     }
@@ -304,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * kBlock;
-      if (i < ne) g[k] = agg_of<T, MODE>(A, A.agg1, A.first, in[k].c);
+      if (i < ne) g[k] = ld_agg<T>(A.agg1, in[k].c);
     }
     // 3. row structure and own aggregates into LDS
     if (tid < nrow) {
@@ -401,9 +383,32 @@ __global__ void k_cnode_out(int32_t n, const int32_t* __restrict__ off_ptr, cons
   }
 }
 
+// The prior of every node as the aggregate record of round 0: (A_ii, b_i), or
+// (1 / P~_i, b_i) with frozen precisions.  Gathered like any later round.
+template <typename T>
+__global__ void k_cnode_prior(int32_t n, const T* __restrict__ first, const T* __restrict__ rhs,
+                              vec2<T>* __restrict__ out) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    vec2<T> v;
+    v.x = first[r];
+    v.y = rhs[r];
+    out[r] = v;
+  }
+}
+
 }  // namespace
 
 size_t cnode_lds_bytes(int K, int elt) { return cn_lds(K, elt); }
+
+template <typename T>
+hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_cnode_prior<T>, dim3(blocks), dim3(256), 0, s, n, first, rhs, (vec2<T>*)out);
+  return hipGetLastError();
+}
+template hipError_t launch_cnode_prior<double>(int32_t, const double*, const double*, void*, hipStream_t);
+template hipError_t launch_cnode_prior<float>(int32_t, const float*, const float*, void*, hipStream_t);
 
 template <typename T>
 hipError_t launch_cnode(int mode, int K, const CnodeArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {

@@ -111,7 +111,6 @@ struct CnodeArgs {
   const void* agg2;        // [n] aggregates of round t-2 (freeze: T-1)
   const void* agg1;        // [n] aggregates of round t-1 (freeze: T)
   void* anew;              // [n] aggregates of round t
-  void* a0out;             // [n] first joint sweep only: the prior written as round-0 aggregates
   const void* coef;        // [E] frozen {g_in, g_out}
   void* coef_out;          // freeze output
   const T* inv_pt;         // [n] frozen 1 / P~
@@ -123,8 +122,9 @@ struct CnodeArgs {
   double* partials;
   DevStatus* st;
   int32_t nblk;
-  int32_t first;           // t == 1 (freeze: T == 0): round t-1 is the prior, no outgoing message yet
-  int32_t second;          // t == 2 (freeze: T == 1): round t-2 is the prior, its messages are zero
+  int32_t first;           // t == 1 (freeze: T == 0): no outgoing message yet
+  int32_t second;          // t == 2 (freeze: T == 1): the incoming messages of round t-2 are zero
+                           // (round 0's aggregate record is the prior, written before sweep 1)
   int32_t check;
   int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
 };
@@ -286,6 +286,8 @@ hipError_t launch_cnode(int mode, int K, const CnodeArgs<T>& a, hipStream_t s, h
 hipError_t launch_cnode_out(int32_t n, const int32_t* off_ptr, const double* a, const void* in_prev,
                             const void* agg_prev, bool zero_in, double* P, double* h, hipStream_t s);
 size_t cnode_lds_bytes(int K, int elt);
+template <typename T>
+hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s);
 size_t bcast_state_bytes(int elt);
 size_t bcast_coef_bytes(int elt);
 size_t bcast_lds_bytes(int K, int elt);

@@ -41,13 +41,19 @@ const T* coef_array(const Ctx* c) {
 struct Poller {
   int pending = -1, slot = 0;
   gabp_status err = GABP_OK;
+  DevStatus seen{};  // the last status observed on the host
+  bool have = false;
   bool step(Ctx* c, const DevStatus* st) {
     hipError_t e = hipMemcpyAsync(&c->st_h[slot], st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev[slot], c->stream);
     bool done = false;
     if (e == hipSuccess && pending >= 0) {
       e = hipEventSynchronize(c->ev[pending]);
-      if (e == hipSuccess && c->st_h[pending].done) done = true;
+      if (e == hipSuccess) {
+        seen = c->st_h[pending];
+        have = true;
+        done = seen.done != 0;
+      }
     }
     if (e != hipSuccess) {
       err = hip_fail(c, e, "status poll");
@@ -56,6 +62,44 @@ struct Poller {
     pending = slot;
     slot ^= 1;
     return done;
+  }
+};
+
+// Size of the next chunk of sweeps.  Without a usable history the chunks
+// double up to 16.  Once two checked rounds have been observed, the relative
+// residual's decay rate predicts the round that reaches tol, and the chunk
+// only covers the sweeps up to the one that checks that round (a zero chunk
+// just polls the sweeps already queued), so few early-return sweeps are
+// queued past convergence.
+struct ChunkPlan {
+  int chunk = 2;
+  double rel0 = -1.0, rel1 = -1.0;
+  int round0 = -1, round1 = -1;
+  int idle = 0;
+  int next(const Poller& p, int queued_through, int lag, int check_every, double tol) {
+    int c = std::min(chunk * 2, 16);
+    if (p.have && p.seen.last_round > round1) {
+      rel0 = rel1;
+      round0 = round1;
+      rel1 = p.seen.last_rel;
+      round1 = p.seen.last_round;
+    }
+    if (tol > 0.0 && round0 >= 0 && rel0 > 0.0 && rel1 > tol && rel1 < rel0) {
+      const double rate = std::pow(rel1 / rel0, 1.0 / (round1 - round0));
+      if (rate < 1.0) {
+        const double m = std::ceil(std::log(tol / rel1) / std::log(rate));
+        if (m < 1e6) {
+          const int ce = std::max(1, check_every);
+          int need = round1 + std::max(1, (int)m);
+          need = ((need + ce - 1) / ce) * ce;  // the next checked round at or after it
+          c = std::max(0, std::min(16, need + lag - queued_through));
+        }
+      }
+    }
+    if (c == 0 && ++idle > 1) c = 1;  // never poll twice without queueing work
+    if (c > 0) idle = 0;
+    chunk = std::max(c, 1);
+    return c;
   }
 };
 
@@ -102,6 +146,7 @@ gabp_status run_edge(Ctx* c, const RunCfg& cfg) {
   const int last = M + 2;
   int t = 1, chunk = 2;
   Poller poll;
+  ChunkPlan plan;
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -132,7 +177,7 @@ gabp_status run_edge(Ctx* c, const RunCfg& cfg) {
                                         true, s));
     }
     stop = poll.step(c, cfg.st);
-    chunk = std::min(chunk * 2, 16);
+    chunk = plan.next(poll, t - 1, 2, ce, exact ? -1.0 : cfg.tol);
   }
   return poll.err;
 }
@@ -170,6 +215,7 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
   const int last = M + 1;
   int t = 1, chunk = 2;
   Poller poll;
+  ChunkPlan plan;
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -201,7 +247,7 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
                                         true, s));
     }
     stop = poll.step(c, cfg.st);
-    chunk = std::min(chunk * 2, 16);
+    chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
   }
   return poll.err;
 }
@@ -241,10 +287,14 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const double tol = exact ? -1.0 : cfg.tol;
   GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
 
+  // round 0: the prior as aggregate record, (A_ii, b_i) or (1 / P~_i, b_i)
+  GABP_HIP(c, launch_cnode_prior<T>(c->n, cfg.honly ? (const T*)c->inv_pt_d : (const T*)cfg.diag,
+                                    (const T*)cfg.rhs, c->agg_d[0], s));
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   const int last = M + 1;
   int t = 1, chunk = 2;
   Poller poll;
+  ChunkPlan plan;
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -257,7 +307,6 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       k.agg1 = c->agg_d[(t - 1) % 3];
       k.agg2 = c->agg_d[(t + 1) % 3];  // round t-2
       k.anew = c->agg_d[t % 3];
-      if (mode == kJoint && t == 1) k.a0out = c->agg_d[0];
       if (mode != kResid) {
         const bool wx = exact ? t == M : in_set(t);
         k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
@@ -279,7 +328,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
                                         true, s));
     }
     stop = poll.step(c, cfg.st);
-    chunk = std::min(chunk * 2, 16);
+    chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
   }
   return poll.err;
 }
