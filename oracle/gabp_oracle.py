@@ -12,8 +12,8 @@ messages of round t-1 only (parallel scheduling, Ch. 2 Sec. 2.3).  Round 0 has
 all messages zero, so the round-0 means are b_i / A_ii; the tentative means of
 round t use the messages of round t (Ch. 4 toy example tables).
 
-Stop rule (a reading: the paper only says "converged w.r.t. epsilon"): the
-relative residual ||b - A x_t||_2 / ||b||_2 <= tol, evaluated on rounds t with
+Stop rule (a reading: the algorithm states its stop condition only as the
+messages having converged to within a tolerance): the relative residual ||b - A x_t||_2 / ||b||_2 <= tol, evaluated on rounds t with
 t % check_every == 0 and on the last allowed round.
 """
 from __future__ import annotations
@@ -28,7 +28,7 @@ __all__ = [
     "dense_marginal_precisions", "residual", "naive_gabp", "broadcast_gabp",
     "fixpoint_violation", "is_strictly_dd", "walk_rho", "walk_rho_dense",
     "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
-    "convfix_gabp", "adjoint_gradient", "fd_gradient", "loss",
+    "convfix_gabp", "convfix_single_loop", "adjoint_gradient", "fd_gradient", "loss",
 ]
 
 
@@ -163,14 +163,14 @@ def naive_gabp(A, b, sweeps):
 # ---------------------------------------------------------------------------
 
 def _broadcast(g, Pii, muii, P, mu):
-    """Step 2, first half: every node i forms P~_i and mu~_i from all k -> i."""
+    """Node aggregates of Alg. 2: every node i forms P~_i and mu~_i from all k -> i."""
     Pt = Pii + np.bincount(g.dst, weights=P, minlength=g.n)
     mut = (Pii * muii + np.bincount(g.dst, weights=P * mu, minlength=g.n)) / Pt
     return Pt, mut
 
 
 def _internal_scalars(g, Pt, mut, P, mu):
-    """Step 2, second half: message i -> j from node i's broadcast minus j -> i."""
+    """Message update of Alg. 2: message i -> j from node i's broadcast minus j -> i."""
     Pji = P[g.rev]
     muji = mu[g.rev]
     Pi = Pt[g.src]
@@ -364,6 +364,60 @@ def convfix_gabp(n, row_ptr, col, val, b, Gamma, tol=1e-9, max_outer=1000,
         x = res["x"]
     return {"x": x, "outer": k, "inner_sweeps": inner_total, "rel_residual": rel,
             "converged": rel <= tol}
+
+
+def convfix_single_loop(n, row_ptr, col, val, b, Gamma, s=0.5, tol=1e-9, max_sweeps=100000,
+                        check_every=1, history=False):
+    """Single-loop form of the correction method of Ch. 5 Sec. 5.3.
+
+    One synchronous Alg. 2 round per outer step on the loaded matrix
+    J' = A + Gamma, whose prior potentials follow the damped feedback
+    h^(t+1) = b + Gamma ((1 - s) x^(t-1) + s x^(t)), with h^(0) = b and
+    x^(-1) = 0 (reading: of the section's two forms of the damped update, the
+    explicit two-point one).  Round t's node aggregates use h^(t); the messages
+    of round t+1 are formed from round t's aggregates as in Alg. 2.  Stops when
+    the relative residual of the ORIGINAL system A x = b is <= tol (checked on
+    rounds t % check_every == 0 and the last); tol <= 0 runs exactly
+    ``max_sweeps`` rounds.  Gamma = 0 is plain Alg. 2.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    Gamma = np.asarray(Gamma, dtype=np.float64)
+    rows = _rows_of(row_ptr)
+    loaded = np.asarray(val, dtype=np.float64).copy()
+    on = rows == np.asarray(col)
+    loaded[on] += Gamma[rows[on]]
+    g = edge_graph(n, row_ptr, col, loaded)
+    Pii = g.diag
+    h = b.copy()                      # prior potentials of the current round
+    x_prev = np.zeros(n)              # x^(t-1)
+    P = np.zeros(g.num_edges)
+    mu = np.zeros(g.num_edges)
+    hist = []
+    t = 0
+    rel = float("nan")
+    converged = False
+    while True:
+        Pt, x = _broadcast(g, Pii, h / Pii, P, mu)      # round t, prior h^(t)
+        if tol > 0 and (t % check_every == 0 or t == max_sweeps):
+            _, rel = residual(n, row_ptr, col, val, x, b)
+            hist.append((t, rel))
+            if rel <= tol:
+                converged = True
+                break
+            if not np.isfinite(rel):
+                break
+        if t >= max_sweeps:
+            break
+        P, mu = _internal_scalars(g, Pt, x, P, mu)       # messages of round t+1
+        h = b + Gamma * ((1.0 - s) * x_prev + s * x)     # h^(t+1)
+        x_prev = x
+        t += 1
+    if tol <= 0:
+        _, rel = residual(n, row_ptr, col, val, x, b)
+    out = {"x": x, "prec": Pt, "sweeps": t, "converged": converged, "rel_residual": rel}
+    if history:
+        out["history"] = hist
+    return out
 
 
 # ---------------------------------------------------------------------------

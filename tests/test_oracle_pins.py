@@ -322,6 +322,63 @@ def test_adjoint_gradient_matches_finite_differences():
     np.testing.assert_allclose(gv, fv, rtol=1e-5, atol=1e-8)
 
 
+def _two_node_single_loop(a11, a12, a22, g1, g2, b1, b2, s, T):
+    """Scalar rounds of the single-loop correction method on a 2-node system,
+    written out by hand: on one edge, P~_i - P_ji equals the loaded A_ii, so
+    the message i -> j is (-a12^2 / d'_i, -a12 h_i / d'_i) with h_i the
+    prior potential of node i in the sending round."""
+    d1, d2 = a11 + g1, a22 + g2
+    h = [b1, b2]                      # h^(0)
+    xp = [0.0, 0.0]                   # x^(-1)
+    m12 = m21 = (0.0, 0.0)            # round-0 messages (P, h)
+    xs = []
+    for t in range(T + 1):
+        x1 = (h[0] + m21[1]) / (d1 + m21[0])
+        x2 = (h[1] + m12[1]) / (d2 + m12[0])
+        xs.append((x1, x2))
+        # round t+1 messages from round t priors, then h^(t+1)
+        m12 = (-a12 * a12 / d1, -a12 * h[0] / d1)
+        m21 = (-a12 * a12 / d2, -a12 * h[1] / d2)
+        h = [b1 + g1 * ((1 - s) * xp[0] + s * x1), b2 + g2 * ((1 - s) * xp[1] + s * x2)]
+        xp = [x1, x2]
+    return xs
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0])
+def test_single_loop_two_node_rounds_by_hand(s):
+    a11, a12, a22, g1, g2, b1, b2 = 1.0, 0.9, 1.3, 0.5, 0.3, 1.0, -2.0
+    ref = _two_node_single_loop(a11, a12, a22, g1, g2, b1, b2, s, 8)
+    rp = np.array([0, 2, 4], np.int32)
+    col = np.array([0, 1, 0, 1], np.int32)
+    val = np.array([a11, a12, a12, a22])
+    for T in range(9):
+        r = oracle.convfix_single_loop(2, rp, col, val, np.array([b1, b2]), np.array([g1, g2]), s=s,
+                                       tol=0, max_sweeps=T)
+        np.testing.assert_allclose(r["x"], ref[T], rtol=1e-14, atol=1e-15)
+    # the limit is A^-1 b
+    r = oracle.convfix_single_loop(2, rp, col, val, np.array([b1, b2]), np.array([g1, g2]), s=s, tol=1e-13)
+    np.testing.assert_allclose(r["x"], np.linalg.solve([[a11, a12], [a12, a22]], [b1, b2]), rtol=1e-12)
+
+
+def test_single_loop_without_loading_is_plain_gabp():
+    p = workloads.er_problem(300, 6, 71, ratio=1.1)
+    for T in (0, 1, 2, 5, 12):
+        a = oracle.convfix_single_loop(p.n, p.row_ptr, p.col, p.val, p.b, np.zeros(p.n), tol=0, max_sweeps=T)
+        b = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=T)
+        np.testing.assert_allclose(a["x"], b["x"], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0])
+def test_single_loop_converges_where_plain_gabp_diverges(s):
+    p = workloads.config5(n=200, rows=400)
+    lo, hi = oracle.walk_rho(p.n, p.row_ptr, p.col, p.val, rtol=1e-10, iters=20000)
+    Gamma = oracle.walk_loading(hi, 0.05) * np.diag(p.dense())
+    r = oracle.convfix_single_loop(p.n, p.row_ptr, p.col, p.val, p.b, Gamma, s=s, tol=1e-10, max_sweeps=20000)
+    assert r["converged"]
+    xstar = np.linalg.solve(p.dense(), p.b)
+    assert np.linalg.norm(r["x"] - xstar) <= 1e-8 * np.linalg.norm(xstar)
+
+
 # ---------------------------------------------------------------------------
 # planted mistakes: each plausible slip in the broadcast oracle fails a pin
 # ---------------------------------------------------------------------------
