@@ -233,6 +233,17 @@ def suite_convfix(torch, g, workloads, inner_tol=1e-2):
            "inner_sweeps": info["sweeps"], "status": info["status"], "rel_residual": res,
            "inner_tol": inner_tol, "edge_updates_per_s": p.num_offdiag * info["sweeps"] / dt}
     s.close()
+    # the single-loop form (one FP64 sweep per outer step, damped feedback s)
+    for damp in (0.5, 1.0):
+        sl = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", gamma=-1.0, single_loop=True,
+                      damping=damp, reuse_precision=False)
+        sl.solve(b, tol=1e-9, max_iter=100000, check=False)  # warm-up
+        dt, (x, info) = timed(torch, lambda: sl.solve(b, tol=1e-9, max_iter=100000, check=False))
+        res = float(np.linalg.norm(p.b - p.scipy() @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        out[f"single_loop_s{damp}"] = {"time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"],
+                                       "status": info["status"], "rel_residual": res,
+                                       "edge_updates_per_s": p.num_offdiag * info["sweeps"] / dt}
+        sl.close()
     return out
 
 

@@ -78,6 +78,7 @@ typedef struct {
                             /* estimate of rho(|R|) (walk-summability, Ch. 5.2)     */
   double  loading_delta;    /* margin for gamma < 0: gamma = (1+delta) rho - 1      */
   double  inner_tol;        /* inner relative residual target per outer step        */
+  double  damping;          /* GABP_FLAG_SINGLE_LOOP: feedback step s in (0, 1]     */
 } gabp_opts;
 
 /* Reuse precision messages frozen by an earlier solve on the same handle: the
@@ -91,6 +92,15 @@ typedef struct {
  * interval is the kernel's own execution; totals land in gabp_info.sweep_ms /
  * timed_sweeps (at most 2048 sweeps per call are timed). */
 #define GABP_FLAG_TIME_SWEEPS 2
+
+/* With diagonal loading (gamma != 0): the single-loop form of the correction
+ * method (Ch. 5 Sec. 5.3) instead of the double loop.  One FP64 sweep of
+ * Alg. 2 on A + Gamma per outer step; the prior potentials of round t are
+ * h^(t) = b + Gamma ((1 - s) x^(t-2) + s x^(t-1)) with s = opts.damping
+ * (x^(-1) = 0, h^(0) = b), and the residual of A x = b itself is checked.
+ * Needs precision GABP_FP64; the handle uses the compact layout.
+ * gabp_info.outer_iters = sweeps. */
+#define GABP_FLAG_SINGLE_LOOP 4
 
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
@@ -123,7 +133,7 @@ typedef struct {
 
 /* Default options: FP64, check every sweep, autotuned block size and layout,
  * no loading, inner_tol 1e-5, inner_max_iter 10000, max_outer 1000, reuse
- * flag on. */
+ * flag on, damping 0.5. */
 void gabp_default_opts(gabp_opts *opts);
 
 /*

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_NOT_SYMMETRIC",
 FP64, FP32_REFINE = 0, 1
 FLAG_REUSE_PRECISION = 1
 FLAG_TIME_SWEEPS = 2
+FLAG_SINGLE_LOOP = 4
 
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
@@ -35,7 +36,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("check_every", c_i32), ("edges_per_block", c_i32),
                 ("inner_max_iter", c_i32), ("max_outer", c_i32), ("flags", c_i32),
                 ("layout", c_i32), ("reserved", c_i32),
-                ("gamma", c_f64), ("loading_delta", c_f64), ("inner_tol", c_f64)]
+                ("gamma", c_f64), ("loading_delta", c_f64), ("inner_tol", c_f64), ("damping", c_f64)]
 
 
 class Info(ctypes.Structure):
@@ -150,7 +151,8 @@ class Solver:
 
     def __init__(self, row_ptr, col, val, *, precision="fp64", check_every=1, edges_per_block=0,
                  gamma=0.0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
-                 reuse_precision=True, time_sweeps=False, layout="auto", device="cuda", stream=None):
+                 reuse_precision=True, time_sweeps=False, layout="auto", single_loop=False, damping=0.5,
+                 device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
         self.stream, sh = _stream_handle(stream)
@@ -163,7 +165,9 @@ class Solver:
             check_every=check_every, edges_per_block=edges_per_block, gamma=gamma,
             loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
             max_outer=max_outer, layout={"auto": 0, "edge": 1, "node": 2, "compact": 3}[layout],
-            flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0))
+            damping=damping,
+            flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0)
+            | (FLAG_SINGLE_LOOP if single_loop else 0))
         h = ctypes.c_void_p()
         st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
                                ctypes.byref(self.opts), sh, ctypes.byref(h))

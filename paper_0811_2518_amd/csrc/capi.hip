@@ -43,6 +43,11 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
   if (o.layout < 0 || o.layout > kLayoutCompact || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
   if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
     return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
+  if (!(o.damping > 0.0 && o.damping <= 1.0)) return fail(c, GABP_E_ARG, "damping must lie in (0, 1]");
+  if ((o.flags & GABP_FLAG_SINGLE_LOOP) && o.precision != GABP_FP64)
+    return fail(c, GABP_E_ARG, "the single loop runs FP64 messages");
+  if ((o.flags & GABP_FLAG_SINGLE_LOOP) && o.layout != 0 && o.layout != kLayoutCompact)
+    return fail(c, GABP_E_ARG, "the single loop needs the compact layout");
   return GABP_OK;
 }
 
@@ -123,6 +128,7 @@ void release_unused_layout(Ctx* c) {
 }
 
 bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->gamma_used == 0.0 && c->opts.gamma == 0.0; }
+bool single_loop_mode(const Ctx* c) { return !plain_mode(c) && (c->opts.flags & GABP_FLAG_SINGLE_LOOP); }
 
 }  // namespace
 
@@ -140,6 +146,7 @@ void gabp_default_opts(gabp_opts* o) {
   o->gamma = 0.0;
   o->loading_delta = 0.05;
   o->inner_tol = 1e-5;
+  o->damping = 0.5;
 }
 
 gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
@@ -187,6 +194,7 @@ gabp_status gabp_solve(gabp_handle h, const double* b, double* x, double* var, d
   if (!b || !x) return fail(c, GABP_E_ARG, "NULL b or x");
   if (plain_mode(c)) return solve_plain(c, b, x, var, tol, max_iter, info, true);
   if (var) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
+  if (single_loop_mode(c)) return solve_single_loop(c, b, x, tol, max_iter, info);
   if (!(tol > 0.0)) return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
   return solve_outer(c, b, x, tol, max_iter, info);
 }
@@ -226,8 +234,9 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
   if (c->n == 0) return GABP_OK;
   if (!x || !grad_x || !grad_b) return fail(c, GABP_E_ARG, "NULL x, grad_x or grad_b");
   // A is symmetric: the adjoint system A^T lambda = dL/dx is a second GaBP solve against A
-  gabp_status r = plain_mode(c) ? solve_plain(c, grad_x, grad_b, nullptr, tol, max_iter, info, true)
-                                : solve_outer(c, grad_x, grad_b, tol, max_iter, info);
+  gabp_status r = plain_mode(c)         ? solve_plain(c, grad_x, grad_b, nullptr, tol, max_iter, info, true)
+                  : single_loop_mode(c) ? solve_single_loop(c, grad_x, grad_b, tol, max_iter, info)
+                                        : solve_outer(c, grad_x, grad_b, tol, max_iter, info);
   if (r < 0) return r;
   if (grad_vals) {
     GABP_HIP(c, launch_grad_vals(c->row_ptr_d, c->col_d, grad_b, x, grad_vals, c->n, c->stream));

@@ -203,6 +203,16 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
 
   // per-row epilogue: publish the aggregates (P, h) of round t, the means
   // and, on the first sweep, the round-0 means
+  // prior potential of round t: b, or with the single-loop feedback
+  // b + Gamma ((1 - s) x^(t-2) + s x^(t-1)), Gamma = diag - chk_diag
+  auto prior_h = [&](int r, T br, Msg<T> o1, Msg<T> o2) -> T {
+    if (MODE != kJoint || !A.feedback) return br;
+    const T x1 = o1.h / o1.P;
+    const T x2 = A.first ? T(0) : o2.h / o2.P;
+    return br + (A.diag[r] - A.chk_diag[r]) * ((T(1) - A.damp) * x2 + A.damp * x1);
+  };
+  // diagonal of the checked system
+  auto chk_d = [&](int r, T dr) -> T { return A.chk_diag ? A.chk_diag[r] : dr; };
   auto publish = [&](int r, Msg<T> o1, T P, T h) {
     if (MODE == kJoint) {
       vec2<T> v;
@@ -245,9 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     ph = bsum_c(ph, s_redT);
     pax = bsum_c(pax, s_red);
     if (tid == 0) {
-      publish(r0, o1, A.diag[r0] + pP, A.rhs[r0] + ph);
+      publish(r0, o1, A.diag[r0] + pP, prior_h(r0, A.rhs[r0], o1, o2) + ph);
       if (A.check) {
-        const double acc = (double)A.rhs[r0] - (double)A.diag[r0] * (double)mean_of<T, MODE>(A, o1) - pax;
+        const double acc =
+            (double)A.rhs[r0] - (double)chk_d(r0, A.diag[r0]) * (double)mean_of<T, MODE>(A, o1) - pax;
         res2 = acc * acc;
       }
     }
@@ -323,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     // 5. row sums: diagonal first, then the slots in CSR order
     if (tid < nrow) {
       const int lo = s_ptr[tid], hi = s_ptr[tid + 1];
-      T P = dr, h = br;
+      T P = dr, h = prior_h(r, br, o1, o2);
       if (MODE == kJoint || MODE == kHOnly)
         for (int j = lo; j < hi; ++j) {
           if (MODE == kJoint) P += s_Pn[j];
@@ -331,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
         }
       publish(r, o1, P, h);
       if (A.check) {
-        double acc = (double)br - (double)dr * (double)mean_of<T, MODE>(A, o1);
+        double acc = (double)br - (double)chk_d(r, dr) * (double)mean_of<T, MODE>(A, o1);
         for (int j = lo; j < hi; ++j) acc -= (double)s_ax[j];
         res2 = acc * acc;
       }

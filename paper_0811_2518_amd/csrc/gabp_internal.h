@@ -119,6 +119,10 @@ struct CnodeArgs {
   T* xout_prev;            // [n] first sweep only: means of round 0
   T* ptout;                // [n] P~ of round t (nullable)
   T* ptout_prev;           // [n] first sweep only: P~ of round 0 (nullable)
+  const T* chk_diag;       // [n] diagonal of the checked system (nullptr: diag)
+  T damp;                  // feedback step s
+  int32_t feedback;        // single-loop correction: prior h^(t) = rhs + (diag - chk_diag)
+                           //   ((1 - s) x^(t-2) + s x^(t-1)), joint sweeps only
   double* partials;
   DevStatus* st;
   int32_t nblk;
@@ -298,6 +302,8 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
                         int32_t max_iter, gabp_info* info, bool allow_reuse);
 gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter,
                         gabp_info* info);
+gabp_status solve_single_loop(Ctx* c, const double* b, double* x, double tol, int32_t max_iter,
+                              gabp_info* info);
 gabp_status autotune(Ctx* c);
 gabp_status estimate_walk_rho(Ctx* c, double* lo, double* hi, int max_iter, double rtol);
 

@@ -26,6 +26,11 @@ struct RunCfg {
   void* x2[2] = {nullptr, nullptr};   // T [n] x by round parity
   void* pt2[2] = {nullptr, nullptr};  // T [n] P~ by round parity (nullable)
   DevStatus* st = nullptr;
+  // single-loop correction (compact layout): damped feedback of the means
+  // into the prior potentials, residual checked against chk_diag
+  bool feedback = false;
+  double damp = 0.5;
+  const void* chk_diag = nullptr;     // T [n]
 };
 
 template <typename T>
@@ -284,6 +289,9 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   a.st = cfg.st;
   a.nblk = c->nblk;
   a.honly_nodes = cfg.honly ? 1 : 0;
+  a.feedback = cfg.feedback ? 1 : 0;
+  a.damp = (T)cfg.damp;
+  a.chk_diag = (const T*)cfg.chk_diag;
   const double tol = exact ? -1.0 : cfg.tol;
   GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
 
@@ -509,6 +517,53 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   return r;
 }
 
+// Single-loop form of the correction method (Ch. 5 Sec. 5.3): FP64 sweeps of
+// Alg. 2 on A + Gamma whose prior potentials follow the damped feedback
+// h^(t) = b + Gamma ((1 - s) x^(t-2) + s x^(t-1)); the residual of A x = b
+// itself is checked, so the stop rule is that of the plain solve.
+gabp_status solve_single_loop(Ctx* c, const double* b, double* x, double tol, int32_t max_iter,
+                              gabp_info* info) {
+  hipStream_t s = c->stream;
+  if (c->layout != kLayoutCompact) return fail(c, GABP_E_ARG, "the single loop needs the compact layout");
+  reset_timing(c);
+  c->frozen_valid = false;
+  GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
+  RunCfg cfg;
+  cfg.rhs = b;
+  cfg.diag = c->din64_d;
+  cfg.chk_diag = c->d64_d;
+  cfg.feedback = true;
+  cfg.damp = c->opts.damping;
+  cfg.rhs_norm = c->norms_d;
+  cfg.tol = tol;
+  cfg.max_iter = max_iter;
+  cfg.check_every = c->opts.check_every;
+  cfg.x2[0] = c->x64_d[0];
+  cfg.x2[1] = c->x64_d[1];
+  cfg.st = c->st_d;
+  gabp_status rs = run_sweeps<double>(c, cfg);
+  if (rs != GABP_OK) return rs;
+  const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
+  const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
+  GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, nullptr, c->n, s));
+  DevStatus st;
+  gabp_status r = read_status(c, c->st_d, &st);
+  if (r != GABP_OK) return r;
+  const bool exact = tol <= 0.0;
+  r = map_status(c, st, exact);
+  if (info) {
+    info->sweeps = st.conv_round >= 0 ? st.conv_round : max_iter;
+    info->outer_iters = info->sweeps;  // one outer step per sweep
+    info->converged = (st.conv_round >= 0) ? 1 : 0;
+    info->status = r;
+    info->rel_residual = st.last_rel;
+    info->gamma = c->gamma_used;
+    report_timing(c, info);
+  }
+  c->last_msg_round = -1;
+  return r;
+}
+
 gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter, gabp_info* info) {
   hipStream_t s = c->stream;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
@@ -700,10 +755,11 @@ gabp_status autotune(Ctx* c) {
   const int epb = c->opts.edges_per_block;
   std::vector<int> layouts, Ks;
   if (c->opts.layout) layouts.push_back(c->opts.layout);
+  else if (c->opts.flags & GABP_FLAG_SINGLE_LOOP) layouts = {kLayoutCompact};
   else layouts = {kLayoutEdge, kLayoutNode, kLayoutCompact};
   if (epb) Ks.push_back(epb / kBlock);
   else Ks = {2, 4, 8};
-  int best_l = c->opts.layout ? c->opts.layout : kLayoutNode, best_k = epb ? epb / kBlock : 4;
+  int best_l = c->opts.layout ? c->opts.layout : layouts.back(), best_k = epb ? epb / kBlock : 4;
   if (c->E >= 200000 && layouts.size() * Ks.size() > 1) {
     const std::string key = tune_key(c);
     const char* path = std::getenv("GABP_AUTOTUNE_CACHE");

@@ -31,13 +31,13 @@ def test_default_opts_match_header_documentation():
     o = pkg.default_opts()
     assert o.precision == binding.FP64 and o.check_every == 1 and o.edges_per_block == 0
     assert o.inner_tol == 1e-5 and o.inner_max_iter == 10000 and o.max_outer == 1000
-    assert o.flags == binding.FLAG_REUSE_PRECISION and o.gamma == 0.0
+    assert o.flags == binding.FLAG_REUSE_PRECISION and o.gamma == 0.0 and o.damping == 0.5
 
 
 def test_struct_layouts():
     import ctypes
-    # gabp_opts: 8 int32 then 3 doubles; gabp_info: 4 int32, 3 doubles, 2 int32
-    assert ctypes.sizeof(binding.Opts) == 8 * 4 + 3 * 8
+    # gabp_opts: 8 int32 then 4 doubles; gabp_info: 4 int32, 3 doubles, 2 int32
+    assert ctypes.sizeof(binding.Opts) == 8 * 4 + 4 * 8
     assert ctypes.sizeof(binding.Info) == 4 * 4 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(binding.Props) == 8 + 8 + 6 * 4 + 8 + 3 * 8
     assert ctypes.sizeof(binding.BatchProfile) == 2 * 4 + 3 * 8 + 2 * 8 + 4 * 4 + 8

@@ -283,6 +283,53 @@ def test_diagonal_loading_fixes_divergent_system():
         assert info["gamma"] == pytest.approx(gam)
 
 
+@pytest.mark.parametrize("s", [0.5, 1.0])
+def test_single_loop_matches_oracle_rounds_and_converges(s):
+    # the single-loop correction method (Ch. 5 Sec. 5.3) where plain GaBP diverges
+    p = workloads.config5(n=3000, rows=6000)
+    lo, hi = oracle.walk_rho(p.n, p.row_ptr, p.col, p.val, rtol=1e-8, iters=20000)
+    gam = oracle.walk_loading(hi, 0.05)
+    Gamma = gam * np.diag(p.dense())
+    sv = solver(p, gamma=gam, single_loop=True, damping=s)
+    assert sv.props()["layout"] == 3
+    for T in (1, 2, 3, 10, 40):
+        x, info = sv.solve(dev(p.b), tol=0, max_iter=T)
+        ref = oracle.convfix_single_loop(p.n, p.row_ptr, p.col, p.val, p.b, Gamma, s=s, tol=0, max_sweeps=T)
+        assert rel(x, ref["x"]) <= TOL, (T, rel(x, ref["x"]))
+    x, info = sv.solve(dev(p.b), tol=1e-9, max_iter=20000)
+    ref = oracle.convfix_single_loop(p.n, p.row_ptr, p.col, p.val, p.b, Gamma, s=s, tol=1e-9,
+                                     max_sweeps=20000)
+    assert info["converged"] == 1 and ref["converged"]
+    assert info["sweeps"] == ref["sweeps"] and info["outer_iters"] == info["sweeps"]
+    assert info["gamma"] == pytest.approx(gam)
+    _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+    assert rr <= 1.05e-9
+    assert rel(x, np.linalg.solve(p.dense(), p.b)) <= 1e-7
+
+
+def test_single_loop_with_automatic_loading_and_adjoint():
+    p = workloads.config5(n=2000, rows=4000)
+    sv = solver(p, gamma=-1.0, single_loop=True)
+    x, info = sv.solve(dev(p.b), tol=1e-10, max_iter=20000)
+    assert info["converged"] == 1 and info["gamma"] > 0
+    A = p.dense()
+    assert rel(x, np.linalg.solve(A, p.b)) <= 1e-8
+    g = np.random.default_rng(5).standard_normal(p.n)
+    gb, gv, binfo = sv.backward(x, dev(g), tol=1e-10, max_iter=20000)
+    assert binfo["converged"] == 1
+    assert rel(gb, np.linalg.solve(A, g)) <= 1e-8
+
+
+def test_single_loop_rejects_fp32_and_other_layouts():
+    p = workloads.config5(n=300, rows=600)
+    for kw in ({"precision": "fp32"}, {"layout": "node"}):
+        with pytest.raises(binding.GabpError) as e:
+            solver(p, gamma=1.0, single_loop=True, **kw)
+        assert e.value.status == binding.E_ARG
+    with pytest.raises(binding.GabpError):
+        solver(p, gamma=1.0, single_loop=True, damping=0.0)
+
+
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
