@@ -213,7 +213,17 @@ def suite_adjoint(torch, g, workloads):
            "backward_ms": 1e3 * dtb, "backward_sweeps": binfo["sweeps"],
            "adjoint_rel_residual": float(np.linalg.norm(gx - A @ lam) / np.linalg.norm(gx)),
            "backward_edge_updates_per_s": p.num_offdiag * binfo["sweeps"] / dtb}
+    layout = s.props()["layout"]
     s.close()
+    # roofline of the FP64 joint sweep on this structured graph, where the
+    # neighbour gathers stay in L2 (same slope timing as the headline kernel)
+    per = sweep_period(torch, g, p, b)
+    kb = kernel_bytes_of(layout, p.n, p.num_offdiag, 8)
+    ab = alg_sweep_bytes(p.n, p.num_offdiag, 8)
+    out["joint_sweep"] = {"layout": LAYOUT_NAMES[layout], "avg_launch_ms": per,
+                          "alg_frac": ab / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "kernel_frac": kb / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "kernel_bytes_per_launch": kb, "alg_bytes_per_launch": ab}
     return out
 
 
@@ -311,6 +321,7 @@ def probe(torch, g, workloads, args):
         dst.copy_(src)
     torch.cuda.synchronize()
     log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
+    del src, dst
     p = workloads.config2(args.n)
     b = torch.from_numpy(p.b).to("cuda")
     for prec, layout in (("fp64", "compact"), ("fp64", "node"), ("fp64", "edge"), ("fp32", "compact")):
