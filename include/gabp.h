@@ -97,9 +97,11 @@ typedef struct {
  * method (Ch. 5 Sec. 5.3) instead of the double loop.  One FP64 sweep of
  * Alg. 2 on A + Gamma per outer step; the prior potentials of round t are
  * h^(t) = b + Gamma ((1 - s) x^(t-2) + s x^(t-1)) with s = opts.damping
- * (x^(-1) = 0, h^(0) = b), and the residual of A x = b itself is checked.
- * Needs precision GABP_FP64; the handle uses the compact layout.
- * gabp_info.outer_iters = sweeps. */
+ * (x^(-1) = 0, h^(0) = b), and the residual of A x = b itself is checked;
+ * gabp_info.outer_iters = sweeps.  With GABP_FP32_REFINE the FP64 refinement
+ * loop stays, and each inner correction solve A d = r runs this single loop
+ * in FP32 (joint sweeps from zero messages, inner residual of A itself).
+ * The handle uses the compact layout. */
 #define GABP_FLAG_SINGLE_LOOP 4
 
 typedef struct {

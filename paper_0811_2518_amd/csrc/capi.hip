@@ -44,8 +44,6 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
   if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
     return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
   if (!(o.damping > 0.0 && o.damping <= 1.0)) return fail(c, GABP_E_ARG, "damping must lie in (0, 1]");
-  if ((o.flags & GABP_FLAG_SINGLE_LOOP) && o.precision != GABP_FP64)
-    return fail(c, GABP_E_ARG, "the single loop runs FP64 messages");
   if ((o.flags & GABP_FLAG_SINGLE_LOOP) && o.layout != 0 && o.layout != kLayoutCompact)
     return fail(c, GABP_E_ARG, "the single loop needs the compact layout");
   return GABP_OK;
@@ -100,6 +98,10 @@ gabp_status alloc_solver(Ctx* c) {
   if (gamma > 0.0) {
     TRY(dev_alloc(c, (void**)&c->din64_d, sizeof(double) * n));
     GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0 + gamma, c->din64_d, c->din32_d, c->n, c->stream));
+    if (fp32 && (c->opts.flags & GABP_FLAG_SINGLE_LOOP)) {
+      TRY(dev_alloc(c, (void**)&c->d32_d, sizeof(float) * n));
+      GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0, nullptr, c->d32_d, c->n, c->stream));
+    }
   } else {
     c->din64_d = c->d64_d;
     GABP_HIP(c, launch_scale_diag(c->d64_d, 1.0, nullptr, c->din32_d, c->n, c->stream));
@@ -194,7 +196,7 @@ gabp_status gabp_solve(gabp_handle h, const double* b, double* x, double* var, d
   if (!b || !x) return fail(c, GABP_E_ARG, "NULL b or x");
   if (plain_mode(c)) return solve_plain(c, b, x, var, tol, max_iter, info, true);
   if (var) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
-  if (single_loop_mode(c)) return solve_single_loop(c, b, x, tol, max_iter, info);
+  if (single_loop_mode(c) && c->opts.precision == GABP_FP64) return solve_single_loop(c, b, x, tol, max_iter, info);
   if (!(tol > 0.0)) return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
   return solve_outer(c, b, x, tol, max_iter, info);
 }
@@ -235,7 +237,8 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
   if (!x || !grad_x || !grad_b) return fail(c, GABP_E_ARG, "NULL x, grad_x or grad_b");
   // A is symmetric: the adjoint system A^T lambda = dL/dx is a second GaBP solve against A
   gabp_status r = plain_mode(c)         ? solve_plain(c, grad_x, grad_b, nullptr, tol, max_iter, info, true)
-                  : single_loop_mode(c) ? solve_single_loop(c, grad_x, grad_b, tol, max_iter, info)
+                  : single_loop_mode(c) && c->opts.precision == GABP_FP64
+                        ? solve_single_loop(c, grad_x, grad_b, tol, max_iter, info)
                                         : solve_outer(c, grad_x, grad_b, tol, max_iter, info);
   if (r < 0) return r;
   if (grad_vals) {

@@ -161,6 +161,7 @@ struct Ctx {
   double* d64_d = nullptr;     // A_ii
   float* a32_d = nullptr;
   float* din32_d = nullptr;    // inner diagonal in FP32 (loaded)
+  float* d32_d = nullptr;      // A_ii in FP32 (single-loop inner solves with loading)
   double* din64_d = nullptr;   // inner diagonal in FP64 (loaded; == d64 when gamma = 0)
   double gamma_used = 0.0;
   double rho_lo = 0.0, rho_hi = 0.0;  // bounds on rho(|R|) when loading was chosen automatically

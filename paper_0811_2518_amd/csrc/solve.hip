@@ -567,6 +567,10 @@ gabp_status solve_single_loop(Ctx* c, const double* b, double* x, double tol, in
 gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t max_iter, gabp_info* info) {
   hipStream_t s = c->stream;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
+  // single-loop inner solves (loading present): no frozen precisions, the
+  // feedback needs the joint sweeps
+  const bool single = (c->opts.flags & GABP_FLAG_SINGLE_LOOP) && c->gamma_used > 0.0;
+  if (single && c->layout != kLayoutCompact) return fail(c, GABP_E_ARG, "the single loop needs the compact layout");
   const int prec = c->opts.precision;
   reset_timing(c);
   // frozen precisions of an earlier call are used only when asked for
@@ -619,9 +623,14 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     if (k >= c->opts.max_outer || total >= max_iter) break;
     const int budget = std::max(0, std::min(c->opts.inner_max_iter, max_iter - total));
     RunCfg cfg;
-    cfg.honly = c->frozen_valid && c->frozen_prec == prec;
+    cfg.honly = !single && c->frozen_valid && c->frozen_prec == prec;
     cfg.rhs = fp32 ? (const void*)c->rin32_d : (const void*)c->rin64_d;
     cfg.diag = fp32 ? (const void*)c->din32_d : (const void*)c->din64_d;
+    if (single) {  // inner solves by the single loop on A + Gamma, checked against A
+      cfg.feedback = true;
+      cfg.damp = c->opts.damping;
+      cfg.chk_diag = fp32 ? (const void*)c->d32_d : (const void*)c->d64_d;
+    }
     cfg.rhs_norm = c->norms_d + 1;
     cfg.tol = c->opts.inner_tol;
     cfg.max_iter = budget;
@@ -641,7 +650,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     }
     const int used = si.conv_round >= 0 ? si.conv_round : budget;
     total += used;
-    if (!cfg.honly && si.conv_round >= 0) {
+    if (!single && !cfg.honly && si.conv_round >= 0) {
       const int last = held_round(c, si.conv_round, budget);
       r = fp32 ? freeze<float>(c, last, cfg.diag, cfg.rhs, prec) : freeze<double>(c, last, cfg.diag, cfg.rhs, prec);
       if (r != GABP_OK) return r;

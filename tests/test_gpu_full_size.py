@@ -1,0 +1,107 @@
+"""Full-size workloads in the benchmark's launch configuration (autotuned
+handles, default options): checked on properties that hold at any size --
+residuals computed independently on the host -- and on sampled outputs the
+FP64 oracle can compute one by one."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+import paper_0811_2518_amd as g
+import workloads
+from paper_0811_2518_amd import binding
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def relres(A, x, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(b - A @ x) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def batch_full():
+    return workloads.config3()
+
+
+def test_full_batch_every_system_converges_and_samples_match_dense(batch_full):
+    bt = batch_full
+    print(f"batch: {bt.num_sys} systems, {bt.sys_row_off[-1]} rows, {bt.rhs_off[-1]} rhs entries", flush=True)
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV)
+    B = torch.from_numpy(bt.B).to(DEV)
+    X, infos, st = s.solve(bt.nrhs, bt.rhs_off, B, tol=1e-10, max_iter=100000)
+    assert st == binding.OK
+    assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos)
+    Xh = X.cpu().numpy()
+    del X, B
+    s.close()
+    # independent FP64 residual of every right-hand side of every system
+    worst = 0.0
+    for q in range(bt.num_sys):
+        p = bt.system(q)
+        k = p.b.shape[1]
+        A = p.scipy()
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        r = np.linalg.norm(p.b - A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
+        worst = max(worst, float(r.max()))
+    assert worst <= 1.05e-10, worst
+    # sampled systems small enough for a dense reference
+    rng = np.random.default_rng(3)
+    small = [q for q in range(bt.num_sys) if bt.sys_row_off[q + 1] - bt.sys_row_off[q] <= 1500]
+    for q in rng.choice(small, size=12, replace=False):
+        p = bt.system(int(q))
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        ref = oracle.dense_solve(p.dense(), p.b)
+        assert np.linalg.norm(xs - ref) / np.linalg.norm(ref) <= 1e-8, q
+
+
+def test_full_grid3d_adjoint_residuals_and_sampled_gradient():
+    p = workloads.config4()
+    t = p.extra["target"]
+    s = g.Solver(p.row_ptr, p.col, p.val, device=DEV)
+    x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=1e-12, max_iter=20000)
+    assert info["converged"] == 1
+    A = p.scipy()
+    xh = x.cpu().numpy()
+    assert relres(A, xh, p.b) <= 1.05e-12
+    gx = xh - t
+    gb, gv, binfo = s.backward(x, x - torch.from_numpy(t).to(DEV), tol=1e-12, max_iter=20000)
+    assert binfo["converged"] == 1
+    lam = gb.cpu().numpy()
+    assert relres(A, lam, gx) <= 1.05e-12
+    # the gradient on the pattern: -(lambda_i x_j + lambda_j x_i) off the
+    # diagonal, -lambda_i x_i on it, from independently solved x and lambda
+    xr, i1 = spla.cg(A, p.b, rtol=1e-14, maxiter=5000)
+    lr, i2 = spla.cg(A, xr - t, rtol=1e-14, maxiter=5000)
+    assert i1 == 0 and i2 == 0
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    ref = np.where(rows == p.col, -lr[rows] * xr[p.col], -(lr[rows] * xr[p.col] + lr[p.col] * xr[rows]))
+    gvh = gv.cpu().numpy()
+    idx = np.random.default_rng(4).choice(len(p.col), 5000, replace=False)
+    np.testing.assert_allclose(gvh[idx], ref[idx], rtol=1e-8, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.fixture(scope="module")
+def btb_full():
+    return workloads.config5()
+
+
+@pytest.mark.parametrize("mode", ["double_loop_fp32_inner", "single_loop_fp64", "single_loop_fp32_inner"])
+def test_full_btb_convergence_fix(btb_full, mode):
+    p = btb_full
+    if mode == "single_loop_fp64":
+        s = g.Solver(p.row_ptr, p.col, p.val, gamma=-1.0, single_loop=True, device=DEV)
+    elif mode == "single_loop_fp32_inner":
+        s = g.Solver(p.row_ptr, p.col, p.val, precision="fp32", gamma=-1.0, single_loop=True,
+                     inner_tol=1e-4, inner_max_iter=20000, device=DEV)
+    else:
+        s = g.Solver(p.row_ptr, p.col, p.val, precision="fp32", gamma=-1.0, inner_tol=1e-2,
+                     inner_max_iter=2000, max_outer=5000, device=DEV)
+    pr = s.props()
+    assert pr["rho_hi"] > 1.0 and pr["gamma"] > 0.0  # not walk-summable: loading chosen
+    x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=1e-9, max_iter=1000000)
+    assert info["converged"] == 1
+    assert relres(p.scipy(), x.cpu().numpy(), p.b) <= 1.05e-9

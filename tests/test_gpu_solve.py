@@ -320,14 +320,26 @@ def test_single_loop_with_automatic_loading_and_adjoint():
     assert rel(gb, np.linalg.solve(A, g)) <= 1e-8
 
 
-def test_single_loop_rejects_fp32_and_other_layouts():
+def test_single_loop_rejects_other_layouts_and_bad_damping():
     p = workloads.config5(n=300, rows=600)
-    for kw in ({"precision": "fp32"}, {"layout": "node"}):
-        with pytest.raises(binding.GabpError) as e:
-            solver(p, gamma=1.0, single_loop=True, **kw)
-        assert e.value.status == binding.E_ARG
-    with pytest.raises(binding.GabpError):
-        solver(p, gamma=1.0, single_loop=True, damping=0.0)
+    with pytest.raises(binding.GabpError) as e:
+        solver(p, gamma=1.0, single_loop=True, layout="node")
+    assert e.value.status == binding.E_ARG
+    for d in (0.0, 1.5):
+        with pytest.raises(binding.GabpError):
+            solver(p, gamma=1.0, single_loop=True, damping=d)
+
+
+@pytest.mark.parametrize("s", [0.5, 1.0])
+def test_single_loop_fp32_inner_with_fp64_refinement(s):
+    # FP32 single-loop inner solves of A d = r inside the FP64 refinement loop
+    p = workloads.config5(n=3000, rows=6000)
+    sv = solver(p, precision="fp32", gamma=-1.0, single_loop=True, damping=s, inner_tol=1e-4)
+    x, info = sv.solve(dev(p.b), tol=1e-9, max_iter=200000)
+    assert info["converged"] == 1 and info["outer_iters"] >= 2 and info["gamma"] > 0
+    _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+    assert rr <= 1.05e-9
+    assert rel(x, np.linalg.solve(p.dense(), p.b)) <= 1e-7
 
 
 # ---------------------------------------------------------------------------
