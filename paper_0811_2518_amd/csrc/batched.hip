@@ -542,7 +542,11 @@ __device__ __forceinline__ Item uniform_item(const Item& x) {
   return u;
 }
 
-__global__ __launch_bounds__(kBT) void k_batched(BatchArgs A) {
+// Register budget of 6 waves per SIMD (80 VGPRs): three 512-lane workgroups
+// per CU.  A few registers spill, which costs less than the extra resident
+// workgroups gain (two per CU without the cap, four with a tighter one are
+// both slower on the 4096-system batch).
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(6))) void k_batched(BatchArgs A) {
   __shared__ int s_item;
   __shared__ int s_flag;
   __shared__ unsigned s_max[2 * kMaxGroup];

@@ -113,7 +113,9 @@ def test_batched_groups_not_dividing_the_workgroup():
     s, B, X, infos, st = _solve(bt)
     assert st == binding.OK
     prof = s.profile()
-    assert prof["num_items"] == bt.num_sys  # one item per system: group = k
+    # most systems are one item whose group is all of its k right-hand sides
+    # (how many get split depends on the persistent grid's size)
+    assert prof["num_items"] <= 1.15 * bt.num_sys
     Xh = X.cpu().numpy()
     for q in range(0, bt.num_sys, 7):
         p = bt.system(q)
