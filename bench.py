@@ -176,6 +176,66 @@ def cpu_baseline(p, reps):
     return p.num_offdiag * ref["sweeps"] / dt, dt, ref
 
 
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "model": model}
+
+
+_POOL_CHILD = r"""
+import concurrent.futures, json, os, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[2])
+import oracle
+TOL = float(sys.argv[3])
+d = np.load(sys.argv[1])
+tasks = []
+for i in range(int(d["count"])):
+    n, rp, col, val, B = int(d[f"n{i}"]), d[f"rp{i}"], d[f"col{i}"], d[f"val{i}"], d[f"b{i}"]
+    tasks += [(n, rp, col, val, np.ascontiguousarray(B[:, j])) for j in range(B.shape[1])]
+
+def solve(t):
+    n, rp, col, val, b = t
+    r = oracle.broadcast_gabp(n, rp, col, val, b, tol=TOL, max_sweeps=100000)
+    return int(rp[-1] - n) * r["sweeps"], int(r["converged"])
+
+cores = min(16, len(os.sched_getaffinity(0)))
+t0 = time.perf_counter()
+with concurrent.futures.ProcessPoolExecutor(max_workers=cores) as ex:
+    res = list(ex.map(solve, tasks, chunksize=1))
+dt = time.perf_counter() - t0
+print(json.dumps({"time_s": dt, "slot_rhs_updates_per_s": sum(u for u, _ in res) / dt, "cores": cores,
+                  "converged": sum(c for _, c in res), "solves": len(tasks)}))
+"""
+
+
+def oracle_pool_baseline(systems):
+    """The oracle over every (system, rhs) of a sample, one task per solve, on
+    a process pool over the usable host cores (at most 16).  The pool lives in
+    a child interpreter of its own, which never touches the GPU."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sample.npz")
+        arrs = {"count": np.array(len(systems))}
+        for i, q in enumerate(systems):
+            arrs.update({f"n{i}": np.array(q.n), f"rp{i}": q.row_ptr, f"col{i}": q.col, f"val{i}": q.val,
+                         f"b{i}": q.b})
+        np.savez(path, **arrs)
+        out = subprocess.run([sys.executable, "-c", _POOL_CHILD, path, ROOT, repr(TOL)],
+                             capture_output=True, text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(f"oracle pool failed: {out.stderr[-2000:]}")
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def timed(torch, fn, reps=1):
     """Best wall time of fn() over reps, the GPU synchronised around each call."""
     best, out = float("inf"), None
@@ -325,6 +385,9 @@ def suite_batched(torch, g, workloads, sample=48):
     sb.solve(kk, roff, Bs, tol=TOL, max_iter=100000)
     sub_s, _ = timed(torch, lambda: sb.solve(kk, roff, Bs, tol=TOL, max_iter=100000))
     sb.close()
+    log("batched suite: CPU oracle on the same sample (process pool)")
+    cpu_pool = oracle_pool_baseline(systems)
+    cpu_pool["speedup_of_batched"] = cpu_pool["time_s"] / sub_s
     return {"workload": "4096 systems: 2-D/3-D grids and random graphs, n log-uniform in [64, 65536], "
                         "1..32 right-hand sides, dominance 1.05..1.5",
             "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
@@ -333,7 +396,8 @@ def suite_batched(torch, g, workloads, sample=48):
             "slot_rhs_updates_per_s": slot_rhs / dt, "load_balance": prof,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
-                                "speedup": loop_s / sub_s}}
+                                "speedup": loop_s / sub_s},
+            "cpu_oracle_pool_same_sample": cpu_pool}
 
 
 def probe(torch, g, workloads, args):
@@ -425,7 +489,7 @@ def main():
         log(f"CPU oracle baseline ({args.cpu_solves} solves to {TOL:g})")
         rate, dt, ref = cpu_baseline(p, args.cpu_solves)
         cpu = {"value": rate, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
-               "time_to_tol_s": dt, "sweeps": ref["sweeps"],
+               "time_to_tol_s": dt, "sweeps": ref["sweeps"], "host": host_info(),
                "sample": f"{args.cpu_solves} full solves of the same n={n} workload to relative residual "
                          f"{TOL:g} by the FP64 NumPy broadcast oracle ({dt:.1f} s each, single thread)"}
         nr = np.linalg.norm(ref["x"])
