@@ -56,11 +56,16 @@ def sweep_bytes(n, E, elt, check=True, honly=False):
 
 
 def source_hash():
-    """Hash of the sweep kernel sources (traffic counters are valid for these only)."""
+    """Hash of the sweep kernel sources with comments and whitespace removed
+    (traffic counters are valid for this code only)."""
+    import re
     h = hashlib.sha256()
     for f in ("sweep.hip", "bcast.hip", "compact.hip"):
-        with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

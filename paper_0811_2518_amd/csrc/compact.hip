@@ -201,8 +201,6 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
   double res2 = 0.0;
   bool bad = false;
 
-  // per-row epilogue: publish the aggregates (P, h) of round t, the means
-  // and, on the first sweep, the round-0 means
   // prior potential of round t: b, or with the single-loop feedback
   // b + Gamma ((1 - s) x^(t-2) + s x^(t-1)), Gamma = diag - chk_diag
   auto prior_h = [&](int r, T br, Msg<T> o1, Msg<T> o2) -> T {
@@ -213,6 +211,8 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
   };
   // diagonal of the checked system
   auto chk_d = [&](int r, T dr) -> T { return A.chk_diag ? A.chk_diag[r] : dr; };
+  // per-row epilogue: publish the aggregates (P, h) of round t, the means
+  // and, on the first sweep, the round-0 means
   auto publish = [&](int r, Msg<T> o1, T P, T h) {
     if (MODE == kJoint) {
       vec2<T> v;
