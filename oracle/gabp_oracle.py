@@ -12,6 +12,10 @@ messages of round t-1 only (parallel scheduling, Ch. 2 Sec. 2.3).  Round 0 has
 all messages zero, so the round-0 means are b_i / A_ii; the tentative means of
 round t use the messages of round t (Ch. 4 toy example tables).
 
+``serial_gabp`` is the serial scheduling of the same section: one set of
+messages updated in place, the nodes visited colour class by colour class of
+a first-fit colouring in row order (``greedy_colouring``).
+
 Stop rule (a reading: the algorithm states its stop condition only as the
 messages having converged to within a tolerance): the relative residual ||b - A x_t||_2 / ||b||_2 <= tol, evaluated on rounds t with
 t % check_every == 0 and on the last allowed round.
@@ -29,6 +33,7 @@ __all__ = [
     "fixpoint_violation", "is_strictly_dd", "walk_rho", "walk_rho_dense",
     "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
     "convfix_gabp", "convfix_single_loop", "adjoint_gradient", "fd_gradient", "loss",
+    "greedy_colouring", "serial_gabp", "naive_serial_gabp",
 ]
 
 
@@ -235,6 +240,149 @@ def fixpoint_violation(g, P, mu, b):
     eP = np.max(np.abs(Pn - P)) / max(np.max(np.abs(P)), 1e-300)
     emu = np.max(np.abs(mun - mu)) / max(np.max(np.abs(mu)), 1e-300)
     return max(eP, emu)
+
+
+# ---------------------------------------------------------------------------
+# serial scheduling (Ch. 2 Sec. 2.3): one set of messages, updated in place,
+# the nodes visited colour class by colour class
+# ---------------------------------------------------------------------------
+
+def greedy_colouring(n, row_ptr, col):
+    """First-fit colouring in row order of the stored off-diagonal pattern.
+
+    Node i, visited in increasing i, takes the smallest colour that none of
+    its already coloured neighbours (stored columns j < i) holds.  Returns an
+    int64 array of colours; no two neighbours share one.
+    """
+    rp = [int(v) for v in row_ptr]
+    cl = [int(v) for v in col]
+    colour = [-1] * n
+    stamp = [-1] * (max((rp[i + 1] - rp[i] for i in range(n)), default=0) + 2)
+    for i in range(n):
+        for s in range(rp[i], rp[i + 1]):
+            j = cl[s]
+            if j < i:
+                stamp[colour[j]] = i
+        c = 0
+        while stamp[c] == i:
+            c += 1
+        colour[i] = c
+    return np.asarray(colour, dtype=np.int64)
+
+
+def serial_gabp(n, row_ptr, col, val, b, colour=None, tol=1e-10, max_sweeps=2000,
+                check_every=1, history=False, return_messages=False):
+    """Serially scheduled broadcast GaBP (Ch. 2 Sec. 2.3 with the Alg. 2 updates).
+
+    There is a single set of messages, initially zero, and every update
+    overwrites it.  A sweep visits the colour classes of ``colour`` (default:
+    ``greedy_colouring``) in increasing order.  No two nodes of a class are
+    neighbours, so a class can be updated at once and the order inside it is
+    immaterial.  Updating node i:
+      - forms P~_i and mu~_i from its current incoming messages (the Alg. 2
+        aggregate);
+      - takes mu~_i as its mean of this sweep;
+      - replaces every outgoing message i -> j by the Alg. 2 update, which
+        subtracts the current j -> i.
+    x^(t) collects the means of sweep t; round 0 is the prior b_i / A_ii.
+
+    Stop rule (reading): the relative residual of x^(t) is <= tol, checked
+    from sweep 1 on at t % check_every == 0 and at the last allowed sweep.
+    The prior round is not checked.  ``tol <= 0`` runs exactly
+    ``max_sweeps`` sweeps.  Returns the same fields as ``broadcast_gabp``,
+    plus ``colours``.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    g = edge_graph(n, row_ptr, col, val)
+    if colour is None:
+        colour = greedy_colouring(n, row_ptr, col)
+    colour = np.asarray(colour, dtype=np.int64)
+    ncol = int(colour.max()) + 1 if n else 0
+    Pii = g.diag
+    hii = b                               # P_ii mu_ii
+    P = np.zeros(g.num_edges)             # message src -> dst
+    h = np.zeros(g.num_edges)             # P * mu of that message
+    x = b / Pii
+    prec = Pii.copy()
+    nodes = [np.nonzero(colour == k)[0] for k in range(ncol)]
+    into = [np.nonzero(colour[g.dst] == k)[0] for k in range(ncol)]   # edges k_node <- *
+    out_of = [np.nonzero(colour[g.src] == k)[0] for k in range(ncol)]  # edges k_node -> *
+    hist = []
+    t = 0
+    rel = float("nan")
+    converged = False
+    while t < max_sweeps:
+        t += 1
+        for k in range(ncol):
+            v, ein, eout = nodes[k], into[k], out_of[k]
+            # aggregates of class k from the current incoming messages
+            Pt = Pii[v] + np.bincount(g.dst[ein], weights=P[ein], minlength=n)[v]
+            ht = hii[v] + np.bincount(g.dst[ein], weights=h[ein], minlength=n)[v]
+            prec[v] = Pt
+            x[v] = ht / Pt
+            # outgoing messages: node i's broadcast minus the current j -> i
+            Ptn = np.zeros(n)
+            htn = np.zeros(n)
+            Ptn[v] = Pt
+            htn[v] = ht
+            src = g.src[eout]
+            D = Ptn[src] - P[g.rev[eout]]
+            newP = -g.a[eout] * g.a[eout] / D
+            newh = -g.a[eout] * (htn[src] - h[g.rev[eout]]) / D
+            P[eout] = newP
+            h[eout] = newh
+        if tol > 0 and (t % check_every == 0 or t == max_sweeps):
+            _, rel = residual(n, row_ptr, col, val, x, b)
+            hist.append((t, rel))
+            if rel <= tol:
+                converged = True
+                break
+            if not np.isfinite(rel):
+                break
+    if tol <= 0 or t == 0:
+        _, rel = residual(n, row_ptr, col, val, x, b)
+    out = {"x": x.copy(), "prec": prec.copy(), "sweeps": t, "converged": converged,
+           "rel_residual": rel, "colours": ncol}
+    if history:
+        out["history"] = hist
+    if return_messages:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            mu = np.where(P != 0.0, h / np.where(P != 0.0, P, 1.0), 0.0)
+        out.update(graph=g, P=P.copy(), mu=mu)
+    return out
+
+
+def naive_serial_gabp(A, b, order, sweeps):
+    """Alg. 1 with serial scheduling on a small dense matrix, one node at a time.
+
+    ``order`` lists the nodes in visiting order.  Visiting node i replaces
+    each outgoing message i -> j by the Alg. 1 formulas with exclusion sums
+    over N(i) \\ j of the CURRENT incoming messages (one data structure), and
+    records the mean of i from the same messages.  Entries may be floats or
+    ``fractions.Fraction``.  Returns the means after each sweep, sweeps 0
+    (the prior) to ``sweeps``.
+    """
+    n = len(A)
+    zero = b[0] * 0
+    nbr = [[k for k in range(n) if k != i and A[k][i] != 0] for i in range(n)]
+    Pii = [A[i][i] for i in range(n)]
+    muii = [b[i] / A[i][i] for i in range(n)]
+    P = {(k, i): zero for i in range(n) for k in nbr[i]}
+    mu = {(k, i): zero for i in range(n) for k in nbr[i]}
+    mean = list(muii)
+    out = [list(mean)]
+    for _ in range(sweeps):
+        for i in order:
+            num = Pii[i] * muii[i] + sum((P[(k, i)] * mu[(k, i)] for k in nbr[i]), zero)
+            den = Pii[i] + sum((P[(k, i)] for k in nbr[i]), zero)
+            mean[i] = num / den
+            for j in nbr[i]:
+                d = Pii[i] + sum((P[(k, i)] for k in nbr[i] if k != j), zero)
+                m = Pii[i] * muii[i] + sum((P[(k, i)] * mu[(k, i)] for k in nbr[i] if k != j), zero)
+                P[(i, j)] = -A[i][j] * A[i][j] / d
+                mu[(i, j)] = m / A[i][j]
+        out.append(list(mean))
+    return out
 
 
 # ---------------------------------------------------------------------------
