@@ -71,7 +71,12 @@ typedef struct {
                             /* timing at create, 1 = outgoing records + reverse-    */
                             /* slot index, 2 = node broadcast (edge pairs in place),*/
                             /* 3 = compact node broadcast (one incoming message per */
-                            /* slot, the outgoing one recomputed by its sender)     */
+                            /* slot, the outgoing one recomputed by its sender),    */
+                            /* 4 = colour-serial: SERIAL scheduling (Ch. 2 Sec.     */
+                            /* 2.3) over the colour classes of a first-fit colouring*/
+                            /* in row order -- a different iteration from 1-3, with */
+                            /* fewer sweeps; never picked by the timing at create;  */
+                            /* no precision reuse, no single loop, no gabp_messages */
   int32_t reserved;         /* must be 0                                            */
   double  gamma;            /* diagonal loading of Ch. 5: the inner solves use      */
                             /* A + gamma * diag(A); 0 = none; < 0 = chosen from an  */
@@ -122,7 +127,8 @@ typedef struct {
   int64_t num_offdiag;      /* directed message slots E = nnz - n         */
   int32_t edges_per_block;  /* slots per workgroup in the sweep kernel    */
   int32_t layout;           /* 1 = reverse-slot index, 2 = node broadcast,*/
-                            /* 3 = compact node broadcast                 */
+                            /* 3 = compact node broadcast, 4 = colour-    */
+                            /* serial                                     */
   int32_t pad;
   int32_t num_blocks;       /* workgroups per sweep launch                */
   int32_t max_degree;       /* largest off-diagonal row length            */
@@ -176,13 +182,19 @@ gabp_status gabp_create(int32_t n, const int32_t *row_ptr, const int32_t *col_id
  * residual in FP64 and M^-1 applied by GaBP sweeps (FP32 messages for
  * GABP_FP32_REFINE).  Returns GABP_OK, GABP_NOT_CONVERGED, GABP_E_DIVERGED or
  * GABP_E_NONFINITE.
+ * Layout 4 replaces the synchronous sweep with a serial one.  A sweep
+ * updates the colour classes in increasing colour order.  A node update
+ * forms the node's aggregate from its current incoming messages (the mean
+ * of that sweep) and overwrites its outgoing messages.  x_t collects the
+ * means of sweep t.  Sweep 0, the prior, is checked only when max_iter = 0.
  */
 gabp_status gabp_solve(gabp_handle h, const double *b, double *x, double *var,
                        double tol, int32_t max_iter, gabp_info *info);
 
 /*
  * gabp_messages -- copy the messages left by the last gabp_solve that ran
- * with tol <= 0 (exactly max_iter sweeps), plain FP64 mode.
+ * with tol <= 0 (exactly max_iter sweeps), plain FP64 mode, layouts 1-3
+ * (GABP_E_ARG for layout 4).
  *   P, hmsg    device float64 [num_offdiag] (outputs).  Slot s is the s-th
  *              stored off-diagonal entry (i, j) of A in CSR order (diagonal
  *              skipped) and holds the message i -> j: its precision P_ij and
@@ -260,6 +272,18 @@ typedef struct {
 
 /* gabp_get_batch_profile -- load-balance figures of the last batched solve. */
 gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile *out);
+
+/*
+ * gabp_get_colours -- the colour classes of a layout-4 handle, the node
+ * groups updated together by serial scheduling (Ch. 2 Sec. 2.3).
+ *   colour       HOST int32 [n] (output, nullable): colour of each row of
+ *                the matrix given to gabp_create.  First fit in row order:
+ *                row i takes the smallest colour held by none of its stored
+ *                neighbours j < i, so no two neighbours share a colour.
+ *   num_colours  HOST (output, nullable): number of classes
+ * GABP_E_ARG for other handles.
+ */
+gabp_status gabp_get_colours(gabp_handle h, int32_t *colour, int32_t *num_colours);
 
 /* gabp_props -- static properties of a handle (host output). */
 gabp_status gabp_get_props(gabp_handle h, gabp_props *props);

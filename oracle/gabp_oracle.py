@@ -288,7 +288,7 @@ def serial_gabp(n, row_ptr, col, val, b, colour=None, tol=1e-10, max_sweeps=2000
 
     Stop rule (reading): the relative residual of x^(t) is <= tol, checked
     from sweep 1 on at t % check_every == 0 and at the last allowed sweep.
-    The prior round is not checked.  ``tol <= 0`` runs exactly
+    The prior round is checked only when ``max_sweeps`` is 0.  ``tol <= 0`` runs exactly
     ``max_sweeps`` sweeps.  Returns the same fields as ``broadcast_gabp``,
     plus ``colours``.
     """
@@ -341,6 +341,9 @@ def serial_gabp(n, row_ptr, col, val, b, colour=None, tol=1e-10, max_sweeps=2000
                 break
     if tol <= 0 or t == 0:
         _, rel = residual(n, row_ptr, col, val, x, b)
+        if tol > 0:  # no sweep allowed: the prior is the last allowed round
+            hist.append((0, rel))
+            converged = bool(rel <= tol)
     out = {"x": x.copy(), "prec": prec.copy(), "sweeps": t, "converged": converged,
            "rel_residual": rel, "colours": ncol}
     if history:

@@ -25,10 +25,12 @@ FP64, FP32_REFINE = 0, 1
 FLAG_REUSE_PRECISION = 1
 FLAG_TIME_SWEEPS = 2
 FLAG_SINGLE_LOOP = 4
+LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
-           "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_props",
+           "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
+           "gabp_get_props",
            "gabp_destroy", "gabp_last_error")
 
 
@@ -97,6 +99,8 @@ def lib():
     L.gabp_solve_batched.restype = c_i32
     L.gabp_get_batch_profile.argtypes = [c_void_p, P(BatchProfile)]
     L.gabp_get_batch_profile.restype = c_i32
+    L.gabp_get_colours.argtypes = [c_void_p, c_void_p, P(c_i32)]
+    L.gabp_get_colours.restype = c_i32
     L.gabp_get_props.argtypes = [c_void_p, P(Props)]
     L.gabp_get_props.restype = c_i32
     L.gabp_destroy.argtypes = [c_void_p]
@@ -164,7 +168,7 @@ class Solver:
             precision={"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}[precision],
             check_every=check_every, edges_per_block=edges_per_block, gamma=gamma,
             loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
-            max_outer=max_outer, layout={"auto": 0, "edge": 1, "node": 2, "compact": 3}[layout],
+            max_outer=max_outer, layout=LAYOUTS[layout],
             damping=damping,
             flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0)
             | (FLAG_SINGLE_LOOP if single_loop else 0))
@@ -200,6 +204,16 @@ class Solver:
         d = info.as_dict()
         d["status"] = st
         return (x, d, v) if var else (x, d)
+
+    def colours(self):
+        """(colour of each row as a NumPy int32 array, number of classes); layout "serial" only."""
+        import numpy as np
+        col = np.zeros(max(self.n, 1), dtype=np.int32)
+        k = c_i32(0)
+        st = lib().gabp_get_colours(self._h, col.ctypes.data_as(c_void_p), ctypes.byref(k))
+        if st != OK:
+            raise _err(self._h, st, "gabp_get_colours")
+        return col[: self.n], int(k.value)
 
     def messages(self):
         """(P, h) of the last fixed-sweep FP64 solve, slot order of the off-diagonal CSR."""

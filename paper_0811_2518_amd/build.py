@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgabp.so")
-SOURCES = ["ingest.hip", "sweep.hip", "bcast.hip", "compact.hip", "loading.hip", "solve.hip", "batched.hip", "capi.hip"]
+SOURCES = ["ingest.hip", "colour.hip", "sweep.hip", "bcast.hip", "compact.hip", "serial.hip", "loading.hip", "solve.hip",
+           "batched.hip", "capi.hip"]
 ARCH = os.environ.get("GABP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -40,7 +40,7 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
       o.edges_per_block != 2048)
     return fail(c, GABP_E_ARG, "edges_per_block must be 0, 512, 1024 or 2048");
   if (o.inner_max_iter < 0 || o.max_outer < 0) return fail(c, GABP_E_ARG, "negative iteration cap");
-  if (o.layout < 0 || o.layout > kLayoutCompact || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
+  if (o.layout < 0 || o.layout > kLayoutSerial || o.reserved != 0) return fail(c, GABP_E_ARG, "layout");
   if (!(o.inner_tol > 0.0) || !std::isfinite(o.gamma) || !std::isfinite(o.loading_delta))
     return fail(c, GABP_E_ARG, "inner_tol, gamma and loading_delta must be finite (inner_tol > 0)");
   if (!(o.damping > 0.0 && o.damping <= 1.0)) return fail(c, GABP_E_ARG, "damping must lie in (0, 1]");
@@ -68,9 +68,19 @@ gabp_status alloc_solver(Ctx* c) {
   const int64_t n = c->n, E = c->E;
   const bool fp32 = c->opts.precision == GABP_FP32_REFINE;
   const size_t elt = fp32 ? sizeof(float) : sizeof(double);
-  const bool edge = !node_family(c->opts.layout), node = c->opts.layout != kLayoutEdge;
+  const bool serial = c->opts.layout == kLayoutSerial;
+  const bool edge = !serial && !node_family(c->opts.layout);
+  const bool node = !serial && c->opts.layout != kLayoutEdge;
   if (node)
     for (int i = 0; i < 3; ++i) TRY(dev_alloc(c, &c->agg_d[i], 2 * elt * n));
+  if (serial) {  // one set of aggregates and of messages, updated in place
+    TRY(dev_alloc(c, &c->agg_d[0], 2 * elt * n));
+    TRY(dev_alloc(c, &c->bstate_d, 2 * elt * E));
+    TRY(dev_alloc(c, (void**)&c->lsum_d, sizeof(double) * n));
+    TRY(dev_alloc(c, (void**)&c->bperm_d, sizeof(double) * n));
+    TRY(dev_alloc(c, (void**)&c->xperm_d, sizeof(double) * n));
+    TRY(dev_alloc(c, (void**)&c->vperm_d, sizeof(double) * n));
+  }
   for (int i = 0; i < 2; ++i) {
     if (edge) {
       TRY(dev_alloc(c, &c->msg_d[i], msg_bytes((int)elt, true) * E));
@@ -82,8 +92,10 @@ gabp_status alloc_solver(Ctx* c) {
     if (fp32) TRY(dev_alloc(c, (void**)&c->x32_d[i], sizeof(float) * n));
   }
   if (node) TRY(dev_alloc(c, &c->bstate_d, bcast_state_bytes((int)elt) * E));
-  TRY(dev_alloc(c, &c->gcoef_d, std::max(bcast_coef_bytes((int)elt), elt) * E));
-  TRY(dev_alloc(c, &c->inv_pt_d, elt * n));
+  if (!serial) {  // frozen precisions
+    TRY(dev_alloc(c, &c->gcoef_d, std::max(bcast_coef_bytes((int)elt), elt) * E));
+    TRY(dev_alloc(c, &c->inv_pt_d, elt * n));
+  }
   if (fp32) TRY(dev_alloc(c, (void**)&c->rin32_d, sizeof(float) * n));
   TRY(dev_alloc(c, (void**)&c->rin64_d, sizeof(double) * n));
   TRY(dev_alloc(c, (void**)&c->din32_d, sizeof(float) * n));
@@ -110,6 +122,7 @@ gabp_status alloc_solver(Ctx* c) {
 }
 
 void release_unused_layout(Ctx* c) {
+  if (c->layout == kLayoutSerial) return;  // allocated for that layout alone
   if (node_family(c->layout)) {
     for (int i = 0; i < 2; ++i) {
       dev_free(c, c->msg_d[i]);
@@ -165,6 +178,7 @@ gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_id
   gabp_status r = check_opts(c, c->opts);
   if (r == GABP_OK) r = common_setup(c);
   if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, nullptr, 0);
+  if (r == GABP_OK && n > 0 && c->opts.layout == kLayoutSerial) r = apply_colour_order(c);
   if (r == GABP_OK && n > 0) r = alloc_solver(c);
   if (r == GABP_OK && n > 0) r = autotune(c);
   if (r == GABP_OK && n > 0) release_unused_layout(c);
@@ -194,16 +208,32 @@ gabp_status gabp_solve(gabp_handle h, const double* b, double* x, double* var, d
     return GABP_OK;
   }
   if (!b || !x) return fail(c, GABP_E_ARG, "NULL b or x");
-  if (plain_mode(c)) return solve_plain(c, b, x, var, tol, max_iter, info, true);
-  if (var) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
-  if (single_loop_mode(c) && c->opts.precision == GABP_FP64) return solve_single_loop(c, b, x, tol, max_iter, info);
-  if (!(tol > 0.0)) return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
-  return solve_outer(c, b, x, tol, max_iter, info);
+  if (var && !plain_mode(c)) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
+  if (!plain_mode(c) && !(single_loop_mode(c) && c->opts.precision == GABP_FP64) && !(tol > 0.0))
+    return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
+  // colour-ordered handles solve in their internal numbering
+  const bool perm = c->perm_d != nullptr;
+  if (perm) GABP_HIP(c, launch_gather(b, c->inv_d, c->bperm_d, c->n, c->stream));
+  const double* bi = perm ? c->bperm_d : b;
+  double* xi = perm ? c->xperm_d : x;
+  double* vi = (perm && var) ? c->vperm_d : var;
+  gabp_status r;
+  if (plain_mode(c)) r = solve_plain(c, bi, xi, vi, tol, max_iter, info, true);
+  else if (single_loop_mode(c) && c->opts.precision == GABP_FP64) r = solve_single_loop(c, bi, xi, tol, max_iter, info);
+  else r = solve_outer(c, bi, xi, tol, max_iter, info);
+  if (perm && r >= 0) {
+    GABP_HIP(c, launch_gather(xi, c->perm_d, x, c->n, c->stream));
+    if (var) GABP_HIP(c, launch_gather(vi, c->perm_d, var, c->n, c->stream));
+    GABP_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return r;
 }
 
 gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
   if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
   Ctx* c = h;
+  if (c->layout == kLayoutSerial)
+    return fail(c, GABP_E_ARG, "messages are exported by the synchronous layouts only");
   if (c->last_msg_round < 0 || c->opts.precision != GABP_FP64)
     return fail(c, GABP_E_ARG, "no FP64 messages from a fixed-sweep solve (tol <= 0) are held");
   if (c->E == 0) return GABP_OK;
@@ -236,11 +266,19 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
   if (c->n == 0) return GABP_OK;
   if (!x || !grad_x || !grad_b) return fail(c, GABP_E_ARG, "NULL x, grad_x or grad_b");
   // A is symmetric: the adjoint system A^T lambda = dL/dx is a second GaBP solve against A
-  gabp_status r = plain_mode(c)         ? solve_plain(c, grad_x, grad_b, nullptr, tol, max_iter, info, true)
+  const bool perm = c->perm_d != nullptr;
+  if (perm) GABP_HIP(c, launch_gather(grad_x, c->inv_d, c->bperm_d, c->n, c->stream));
+  const double* gi = perm ? c->bperm_d : grad_x;
+  double* li = perm ? c->xperm_d : grad_b;
+  gabp_status r = plain_mode(c)         ? solve_plain(c, gi, li, nullptr, tol, max_iter, info, true)
                   : single_loop_mode(c) && c->opts.precision == GABP_FP64
-                        ? solve_single_loop(c, grad_x, grad_b, tol, max_iter, info)
-                                        : solve_outer(c, grad_x, grad_b, tol, max_iter, info);
+                        ? solve_single_loop(c, gi, li, tol, max_iter, info)
+                                        : solve_outer(c, gi, li, tol, max_iter, info);
   if (r < 0) return r;
+  if (perm) {
+    GABP_HIP(c, launch_gather(li, c->perm_d, grad_b, c->n, c->stream));
+    if (!grad_vals) GABP_HIP(c, hipStreamSynchronize(c->stream));
+  }
   if (grad_vals) {
     GABP_HIP(c, launch_grad_vals(c->row_ptr_d, c->col_d, grad_b, x, grad_vals, c->n, c->stream));
     GABP_HIP(c, hipStreamSynchronize(c->stream));
@@ -306,6 +344,16 @@ gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile* out) {
   Ctx* c = h;
   if (!c->batched) return fail(c, GABP_E_ARG, "not a batched handle");
   return batched_profile(c, out);
+}
+
+gabp_status gabp_get_colours(gabp_handle h, int32_t* colour, int32_t* num_colours) {
+  if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = h;
+  if (c->batched || c->opts.layout != kLayoutSerial)
+    return fail(c, GABP_E_ARG, "not a colour-serial handle (layout 4)");
+  if (num_colours) *num_colours = c->ncol;
+  if (colour && c->n > 0) std::memcpy(colour, c->colour_h.data(), sizeof(int32_t) * c->n);
+  return GABP_OK;
 }
 
 gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {

@@ -1,0 +1,133 @@
+// Colour classes for serial scheduling (Ch. 2 Sec. 2.3).
+//
+// Nodes of one class are pairwise non-adjacent, so a class can be updated at
+// once, and a sweep over the classes in turn is a serial schedule.  The
+// colouring is first fit in row order: node i takes the smallest colour
+// that none of its neighbours j < i holds.  That is a sequential O(E) pass on
+// the host over the already validated off-diagonal pattern.  The
+// off-diagonal CSR is then renumbered on the device so that each class is a
+// contiguous row range, rows kept in increasing caller order inside a class.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "gabp_internal.h"
+
+namespace gabp {
+
+namespace {
+
+#define GABP_TRY_STATUS(x)          \
+  do {                              \
+    gabp_status s_ = (x);           \
+    if (s_ != GABP_OK) return s_;   \
+  } while (0)
+
+// One lane per new row p: copy the slots of caller row inv[p], with the
+// columns renumbered (the slot order inside the row is kept).
+__global__ void k_permute_rows(int32_t n, const int32_t* __restrict__ inv, const int32_t* __restrict__ perm,
+                               const int32_t* __restrict__ old_ptr, const int32_t* __restrict__ old_col,
+                               const double* __restrict__ old_a64, const float* __restrict__ old_a32,
+                               const double* __restrict__ old_d64, const int32_t* __restrict__ new_ptr,
+                               int32_t* __restrict__ new_col, double* __restrict__ new_a64,
+                               float* __restrict__ new_a32, double* __restrict__ new_d64) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const int32_t r = inv[p];
+    int32_t k = new_ptr[p];
+    for (int32_t s = old_ptr[r]; s < old_ptr[r + 1]; ++s, ++k) {
+      new_col[k] = perm[old_col[s]];
+      new_a64[k] = old_a64[s];
+      new_a32[k] = old_a32[s];
+    }
+    new_d64[p] = old_d64[r];
+  }
+}
+
+}  // namespace
+
+gabp_status apply_colour_order(Ctx* c) {
+  hipStream_t s = c->stream;
+  const int32_t n = c->n;
+  const int64_t E = c->E;
+  const std::vector<int32_t>& op = c->off_ptr_h;
+  std::vector<int32_t> col((size_t)E);
+  if (E > 0)
+    GABP_HIP(c, hipMemcpyAsync(col.data(), c->off_col_d, sizeof(int32_t) * E, hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+
+  // first fit in row order
+  std::vector<int32_t>& colour = c->colour_h;
+  colour.assign(n, 0);
+  std::vector<int32_t> stamp((size_t)c->max_degree + 2, -1);
+  int32_t ncol = n > 0 ? 1 : 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t e = op[i]; e < op[i + 1]; ++e) {
+      const int32_t j = col[e];
+      if (j < i) stamp[colour[j]] = i;
+    }
+    int32_t k = 0;
+    while (stamp[k] == i) ++k;
+    colour[i] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+
+  // classes as contiguous ranges, caller order inside a class
+  c->ncol = ncol;
+  c->colour_start.assign(ncol + 1, 0);
+  for (int32_t i = 0; i < n; ++i) ++c->colour_start[colour[i] + 1];
+  std::partial_sum(c->colour_start.begin(), c->colour_start.end(), c->colour_start.begin());
+  std::vector<int32_t> perm_inv(2 * (size_t)n);  // [perm | inv]
+  std::vector<int32_t> next(c->colour_start.begin(), c->colour_start.end() - 1);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t p = next[colour[i]]++;
+    perm_inv[i] = p;
+    perm_inv[n + p] = i;
+  }
+  std::vector<int32_t> new_ptr((size_t)n + 1, 0);
+  for (int32_t p = 0; p < n; ++p) {
+    const int32_t r = perm_inv[n + p];
+    new_ptr[p + 1] = new_ptr[p] + (op[r + 1] - op[r]);
+  }
+
+  void* pi = nullptr;
+  GABP_TRY_STATUS(dev_alloc(c, &pi, sizeof(int32_t) * 2 * (size_t)n));
+  c->perm_d = (int32_t*)pi;
+  c->inv_d = c->perm_d + n;
+  int32_t* nptr_d = nullptr;
+  int32_t* ncol_d = nullptr;
+  double* na64_d = nullptr;
+  float* na32_d = nullptr;
+  double* nd64_d = nullptr;
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&nptr_d, sizeof(int32_t) * ((size_t)n + 1)));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&ncol_d, sizeof(int32_t) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&na64_d, sizeof(double) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&na32_d, sizeof(float) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&nd64_d, sizeof(double) * (size_t)n));
+  GABP_HIP(c, hipMemcpyAsync(c->perm_d, perm_inv.data(), sizeof(int32_t) * 2 * (size_t)n, hipMemcpyHostToDevice, s));
+  GABP_HIP(c, hipMemcpyAsync(nptr_d, new_ptr.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_permute_rows, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n, c->inv_d,
+                       c->perm_d, c->off_ptr_d, c->off_col_d, c->a64_d, c->a32_d, c->d64_d, nptr_d, ncol_d, na64_d,
+                       na32_d, nd64_d);
+    GABP_HIP(c, hipGetLastError());
+  }
+  GABP_HIP(c, hipStreamSynchronize(s));
+  dev_free(c, c->off_ptr_d);
+  dev_free(c, c->off_col_d);
+  dev_free(c, c->a64_d);
+  dev_free(c, c->a32_d);
+  dev_free(c, c->d64_d);
+  dev_free(c, c->rev_d);  // the serial sweeps pull through aggregates only
+  c->rev_d = nullptr;
+  c->off_ptr_d = nptr_d;
+  c->off_col_d = ncol_d;
+  c->a64_d = na64_d;
+  c->a32_d = na32_d;
+  c->d64_d = nd64_d;
+  c->off_ptr_h = std::move(new_ptr);
+  return GABP_OK;
+}
+
+}  // namespace gabp

@@ -133,9 +133,36 @@ struct CnodeArgs {
   int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
 };
 
+// Arguments of one colour-serial launch (serial.hip): the rows of one colour
+// class, updated in place.
+template <typename T>
+struct SerialArgs {
+  const int32_t* blk_row;
+  const int32_t* blk_e0;
+  const int32_t* off_ptr;
+  const int32_t* col;      // [E] neighbour of each slot (colour-ordered numbering)
+  const T* a;              // [E] A_ji of slot (j, i)
+  const T* diag;           // [n] P_ii (possibly loaded)
+  const T* rhs;            // [n]
+  void* out;               // [E] {P, h} of the message j -> i sent at j's last update
+  void* agg;               // [n] {P~, h~} of each node's last update
+  double* lsum;            // [n] residual part of the earlier classes (read: check, written: wl)
+  T* xout;                 // [n] means of this sweep (nullable)
+  T* ptout;                // [n] P~ of this sweep (nullable)
+  double* partials;        // [all workgroups] squared residual sums
+  DevStatus* st;
+  int32_t blk0;            // first workgroup of the class
+  int32_t nblk;            // workgroups of the class
+  int32_t lo, hi;          // rows of the class
+  int32_t first;           // sweep 1: later classes have sent nothing yet
+  int32_t check;           // residual of the previous sweep's means
+  int32_t wl;              // store the earlier classes' residual part for the next sweep
+};
+
 constexpr int kLayoutEdge = 1;     // outgoing message records + reverse-slot index
 constexpr int kLayoutNode = 2;     // node broadcast: aggregates published, edge pairs kept in place
 constexpr int kLayoutCompact = 3;  // node broadcast, one incoming message per slot, outgoing recomputed
+constexpr int kLayoutSerial = 4;   // serial scheduling over colour classes, rows stored in colour order
 inline bool node_family(int layout) { return layout == kLayoutNode || layout == kLayoutCompact; }
 
 // Everything a handle owns.  Device arrays are suffixed _d.
@@ -208,6 +235,19 @@ struct Ctx {
   int timed_sweeps = 0;
   int timed_mode = 0;
 
+  // colour-serial layout: rows renumbered so that each colour class is a
+  // contiguous range; the caller's order is restored at the C ABI
+  int32_t ncol = 0;
+  std::vector<int32_t> colour_start;  // [ncol+1] first row of each class
+  std::vector<int32_t> colour_blk;    // [ncol+1] first workgroup of each class
+  std::vector<int32_t> colour_h;      // [n] colour of each caller row
+  int32_t* perm_d = nullptr;          // [n] caller row -> internal row, then [n] internal -> caller
+  int32_t* inv_d = nullptr;
+  double* bperm_d = nullptr;          // right-hand side, x and variances in internal order
+  double* xperm_d = nullptr;
+  double* vperm_d = nullptr;
+  double* lsum_d = nullptr;           // [n] residual part of the earlier classes
+
   // batched
   bool batched = false;
   void* batch = nullptr;
@@ -231,6 +271,9 @@ gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const dou
                    const int32_t* sys_row_off_d, int32_t num_sys);
 gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row);
 gabp_status set_partition(Ctx* c, int K);
+// colour.hip: first-fit colouring in row order and the colour-ordered
+// renumbering of the off-diagonal CSR (colour-serial layout)
+gabp_status apply_colour_order(Ctx* c);
 
 // ---- kernels (sweep.hip) ---------------------------------------------------
 template <typename T>
@@ -293,6 +336,12 @@ hipError_t launch_cnode_out(int32_t n, const int32_t* off_ptr, const double* a, 
 size_t cnode_lds_bytes(int K, int elt);
 template <typename T>
 hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s);
+template <typename T>
+hipError_t launch_serial(const SerialArgs<T>& a, int K, bool resid, hipStream_t s);
+template <typename T>
+hipError_t launch_serial_prior_x(int32_t n, const T* diag, const T* rhs, T* x, T* pt, hipStream_t s);
+size_t serial_lds_bytes(int K, int elt);
+hipError_t launch_gather(const double* src, const int32_t* idx, double* dst, int32_t n, hipStream_t s);
 size_t bcast_state_bytes(int elt);
 size_t bcast_coef_bytes(int elt);
 size_t bcast_lds_bytes(int K, int elt);

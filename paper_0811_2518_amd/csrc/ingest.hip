@@ -234,7 +234,8 @@ gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const dou
 
 // Greedy packing of whole rows into workgroups of at most 256*K slots and 256
 // rows; a row longer than 256*K gets a workgroup of its own (handled by the
-// sweep kernel's long-row path).
+// sweep kernel's long-row path).  With colour classes, no workgroup spans two
+// classes.
 gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
   const int64_t cap = (int64_t)kBlock * K;
   blk_row.clear();
@@ -242,9 +243,15 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
   int64_t slots = 0;
   int32_t rows = 0;
   const auto& op = c->off_ptr_h;
+  size_t next_class = 1;  // index into colour_start of the next class boundary
   for (int32_t r = 0; r < c->n; ++r) {
     const int64_t d = op[r + 1] - op[r];
-    if (rows > 0 && (slots + d > cap || rows == kMaxRowsPerBlock)) {
+    bool boundary = false;
+    while (next_class < c->colour_start.size() && c->colour_start[next_class] <= r) {
+      boundary = boundary || c->colour_start[next_class] == r;
+      ++next_class;
+    }
+    if (rows > 0 && (boundary || slots + d > cap || rows == kMaxRowsPerBlock)) {
       blk_row.push_back(r);
       slots = 0;
       rows = 0;
@@ -279,6 +286,11 @@ gabp_status set_partition(Ctx* c, int K) {
   GABP_HIP(c, hipStreamSynchronize(c->stream));
   c->K = K;
   c->nblk = nb;
+  if (c->ncol > 0) {  // first workgroup of each colour class
+    c->colour_blk.assign(c->ncol + 1, nb);
+    for (int32_t k = c->ncol - 1; k >= 0; --k)
+      c->colour_blk[k] = (int32_t)(std::lower_bound(br.begin(), br.begin() + nb + 1, c->colour_start[k]) - br.begin());
+  }
   if (c->partials_d == nullptr || nb > c->partials_capacity) {
     void* p = nullptr;
     GABP_TRY(dev_alloc(c, &p, sizeof(double) * (nb + 1024)));

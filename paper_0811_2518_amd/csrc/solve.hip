@@ -341,8 +341,100 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   return poll.err;
 }
 
+// Colour-serial layout: sweep t updates the colour classes in turn (one
+// launch each) and checks the means of sweep t-1; sweeps 1..M, then a
+// residual-only launch for sweep M.  Sweep 0 (the prior) is checked only
+// when it is the last allowed sweep.
+template <typename T>
+gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
+  hipStream_t s = c->stream;
+  const bool exact = cfg.tol <= 0.0;
+  const int M = cfg.max_iter;
+  const int ce = std::max(1, cfg.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+  const double tol = exact ? -1.0 : cfg.tol;
+
+  SerialArgs<T> a{};
+  a.blk_row = c->blk_row_d;
+  a.blk_e0 = c->blk_e0_d;
+  a.off_ptr = c->off_ptr_d;
+  a.col = c->off_col_d;
+  a.a = coef_array<T>(c);
+  a.diag = (const T*)cfg.diag;
+  a.rhs = (const T*)cfg.rhs;
+  a.out = c->bstate_d;
+  a.agg = c->agg_d[0];
+  a.lsum = c->lsum_d;
+  a.partials = c->partials_d;
+  a.st = cfg.st;
+  GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
+
+  if (M == 0) {  // the prior means b_i / P_ii
+    GABP_HIP(c, launch_serial_prior_x<T>(c->n, a.diag, a.rhs, (T*)cfg.x2[0], cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr,
+                                         s));
+    if (!exact) {
+      GABP_HIP(c, launch_cnode_prior<T>(c->n, a.diag, a.rhs, a.agg, s));
+      SerialArgs<T> k = a;
+      k.blk0 = 0;
+      k.nblk = c->nblk;
+      k.check = 1;
+      GABP_HIP(c, launch_serial<T>(k, c->K, true, s));
+      GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, 0, nullptr, true, s));
+    }
+    return GABP_OK;
+  }
+
+  const int last = M + 1;
+  int t = 1, chunk = 2;
+  Poller poll;
+  ChunkPlan plan;
+  bool stop = false;
+  while (t <= last && !stop) {
+    const int tend = std::min(last, t + chunk - 1);
+    for (; t <= tend; ++t) {
+      const bool ck = exact ? (t == M + 1) : (t >= 2 && in_set(t - 1));
+      if (t == M + 1) {  // residual of sweep M, every node at sweep M
+        if (!ck) continue;
+        SerialArgs<T> k = a;
+        k.blk0 = 0;
+        k.nblk = c->nblk;
+        k.check = 1;
+        GABP_HIP(c, launch_serial<T>(k, c->K, true, s));
+      } else {
+        const bool wx = exact ? t == M : in_set(t);
+        hipEvent_t e0, e1;
+        start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && ck, &e0, &e1);
+        if (e0) {
+          c->timed_mode = 0;
+          GABP_HIP(c, hipEventRecord(e0, s));
+        }
+        for (int q = 0; q < c->ncol; ++q) {
+          SerialArgs<T> k = a;
+          k.blk0 = c->colour_blk[q];
+          k.nblk = c->colour_blk[q + 1] - c->colour_blk[q];
+          k.lo = c->colour_start[q];
+          k.hi = c->colour_start[q + 1];
+          k.first = (t == 1);
+          k.check = ck ? 1 : 0;
+          k.wl = (!exact && t < M && in_set(t)) ? 1 : 0;
+          k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
+          k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
+          GABP_HIP(c, launch_serial<T>(k, c->K, false, s));
+        }
+        if (e1) GABP_HIP(c, hipEventRecord(e1, s));
+      }
+      if (ck)
+        GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr, true, s));
+    }
+    stop = poll.step(c, cfg.st);
+    chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
+  }
+  return poll.err;
+}
+
 template <typename T>
 gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+  if (c->layout == kLayoutSerial) return run_serial<T>(c, cfg);
   if (c->layout == kLayoutCompact) return run_cnode<T>(c, cfg);
   return c->layout == kLayoutNode ? run_node<T>(c, cfg) : run_edge<T>(c, cfg);
 }
@@ -392,6 +484,7 @@ gabp_status read_status(Ctx* c, const DevStatus* st_d, DevStatus* out) {
 // b term).
 template <typename T>
 gabp_status freeze(Ctx* c, int round, const void* diag, const void* rhs, int prec) {
+  if (c->layout == kLayoutSerial) return GABP_OK;  // the serial sweeps always update P and h
   DevStatus* st = c->st_d + 1;  // fresh status: the freeze must not be skipped
   GABP_HIP(c, launch_reset_status(st, 1, c->stream));
   if (c->layout == kLayoutCompact) {
@@ -508,7 +601,8 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     report_timing(c, info);
   }
   c->last_msg_round = (exact && !honly && r == GABP_OK) ? max_iter : -1;
-  if (r == GABP_OK && !exact && !honly && (c->opts.flags & GABP_FLAG_REUSE_PRECISION)) {
+  if (r == GABP_OK && !exact && !honly && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) &&
+      c->layout != kLayoutSerial) {
     const int last = held_round(c, st.conv_round, max_iter);
     gabp_status fr = freeze<double>(c, last, c->din64_d, b, GABP_FP64);
     if (fr != GABP_OK) return fr;
@@ -650,7 +744,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     }
     const int used = si.conv_round >= 0 ? si.conv_round : budget;
     total += used;
-    if (!single && !cfg.honly && si.conv_round >= 0) {
+    if (!single && !cfg.honly && si.conv_round >= 0 && c->layout != kLayoutSerial) {
       const int last = held_round(c, si.conv_round, budget);
       r = fp32 ? freeze<float>(c, last, cfg.diag, cfg.rhs, prec) : freeze<double>(c, last, cfg.diag, cfg.rhs, prec);
       if (r != GABP_OK) return r;
@@ -709,7 +803,7 @@ bool cache_lookup(const std::string& path, const std::string& key, int* layout, 
     const auto pl = line.find("\"layout\": ");
     if (pk == std::string::npos || pl == std::string::npos) continue;
     const int k = std::atoi(line.c_str() + pk + 5), l = std::atoi(line.c_str() + pl + 10);
-    if ((k == 2 || k == 4 || k == 8) && (l == kLayoutEdge || node_family(l))) {
+    if ((k == 2 || k == 4 || k == 8) && (l == kLayoutEdge || node_family(l) || l == kLayoutSerial)) {
       *K = k;
       *layout = l;
       found = true;

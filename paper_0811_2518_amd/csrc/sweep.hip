@@ -457,10 +457,36 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
   store_partial(res2, s_red, A.partials, b);
 }
 
+// The first outer step from x = 0: x_new = 0 and r = b, so no gather is
+// needed. Same row partition and per-workgroup partial sums as k_outer, so
+// the residual norm is that of k_outer bit for bit.
+__global__ __launch_bounds__(kBlock) void k_outer_zero(OuterArgs A) {
+  __shared__ double s_red[kBlock / 64];
+  const int b = xcd_remap(blockIdx.x, A.nblk);
+  const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
+  double res2 = 0.0;
+  if ((int)threadIdx.x < r1 - r0) {
+    const int r = r0 + threadIdx.x;
+    const double res = A.b[r];
+    A.xnew[r] = 0.0;
+    if (A.rin32) A.rin32[r] = (float)res;
+    if (A.rin64) A.rin64[r] = res;
+    res2 = res * res;
+  }
+  store_partial(res2, s_red, A.partials, b);
+}
+
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
   if (a.nblk <= 0) return hipSuccess;
+  hipError_t e;
+  if (!a.xold && !a.use_d) {
+    hipLaunchKernelGGL(k_outer_zero, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s);
+  }
   hipLaunchKernelGGL(k_update, dim3(std::min((a.n + 255) / 256, 4096)), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_outer_only(K, a, s);
   if (e != hipSuccess) return e;

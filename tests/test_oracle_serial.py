@@ -173,3 +173,13 @@ def test_serial_stop_rule_and_history():
     assert r["converged"] and r["history"][-1][1] <= 1e-10 < r["history"][-2][1]
     _, rel = oracle.residual(p.n, p.row_ptr, p.col, p.val, r["x"], p.b)
     assert rel == pytest.approx(r["rel_residual"], rel=1e-12)
+
+
+def test_serial_prior_round_checked_only_without_sweeps():
+    d = np.array([2.0, 4.0, 5.0])
+    p = workloads.from_dense(np.diag(d), np.array([1.0, 2.0, 3.0]))
+    r = oracle.serial_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-10, max_sweeps=0)
+    assert r["converged"] and r["sweeps"] == 0
+    np.testing.assert_array_equal(r["x"], p.b / d)
+    r = oracle.serial_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-10, max_sweeps=5, history=True)
+    assert r["converged"] and r["sweeps"] == 1 and r["history"][0][0] == 1
