@@ -55,17 +55,18 @@ def sweep_bytes(n, E, elt, check=True, honly=False):
     return slot * E + node * n
 
 
-def source_hash():
-    """Hash of the sweep kernel sources with comments and whitespace removed
-    (traffic counters are valid for this code only)."""
+def source_hash(src="compact.hip"):
+    """Hash of one kernel's source file and the shared internal header, with
+    comments and whitespace removed (traffic counters are valid for this code
+    only)."""
     import re
     h = hashlib.sha256()
-    for f in ("sweep.hip", "bcast.hip", "compact.hip"):
+    for f in (src, "gabp_internal.h"):
         with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", f)) as fh:
-            src = fh.read()
-        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
-        src = re.sub(r"//[^\n]*", " ", src)
-        h.update("".join(src.split()).encode())
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -94,12 +95,31 @@ def compact_layout_bytes(n, E, elt):
     return (4 + 7 * elt) * E + (4 + 9 * elt) * n
 
 
-LAYOUT_NAMES = {1: "reverse-slot index", 2: "node broadcast", 3: "compact node broadcast"}
+def serial_layout_bytes(n, E, elt):
+    """Bytes the colour-serial sweep moves, each element once: per slot column
+    4 + A_ij elt + the outgoing message read and written 4 elt + the gathered
+    neighbour aggregate 2 elt; per node row pointer 4 + A_ii, b_i + own
+    aggregate read and written 4 elt + x written elt + the earlier classes'
+    residual part read and written 16."""
+    return (4 + 7 * elt) * E + (4 + 7 * elt + 16) * n
+
+
+LAYOUT_NAMES = {1: "reverse-slot index", 2: "node broadcast", 3: "compact node broadcast",
+                4: "colour-serial node broadcast"}
 LAYOUT_KERNELS = {1: ("k_sweep", "k_sweep_fp64_joint"), 2: ("k_bcast", "k_bcast_fp64_joint"),
-                  3: ("k_cnode", "k_cnode_fp64_joint")}
+                  3: ("k_cnode", "k_cnode_fp64_joint"), 4: ("k_serial", "k_serial_fp64")}
+LAYOUT_SRC = {1: "sweep.hip", 2: "bcast.hip", 3: "compact.hip", 4: "serial.hip"}
+# counter entries of profiles/traffic.json: profiler kernel name (512 slots per
+# workgroup, FP64 joint sweep) and source file
+TRAFFIC_KERNELS = {"k_cnode_fp64_joint": ("k_cnode<double, 2, 0>", "compact.hip"),
+                   "k_bcast_fp64_joint": ("k_bcast<double, 2, 0>", "bcast.hip"),
+                   "k_sweep_fp64_joint": ("k_sweep<double, 2, 0>", "sweep.hip"),
+                   "k_serial_fp64": ("k_serial<double, 2, false>", "serial.hip")}
 
 
 def kernel_bytes_of(layout, n, E, elt):
+    if layout == 4:
+        return serial_layout_bytes(n, E, elt)
     if layout == 3:
         return compact_layout_bytes(n, E, elt)
     if layout == 2:
@@ -115,13 +135,63 @@ def measured_traffic(kernel_tag):
     with open(path) as f:
         data = json.load(f)
     ent = data.get(kernel_tag)
-    if not ent or ent.get("sweep_hip_sha") != source_hash():
+    if not ent or ent.get("source_sha") != source_hash(TRAFFIC_KERNELS[kernel_tag][1]):
         return None
     return ent.get("bytes_per_launch")
 
 
-def run_solves(torch, g, p, b, precision, steps, warmup):
-    s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False)
+def traffic_from(fetch_dir, write_dir, n):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of `bench.py --probe`
+    (FETCH_SIZE, then WRITE_SIZE): per-dispatch medians of the sweep kernels,
+    scaled so that the probe's 1 GiB copy reads 1 GiB and writes 1 GiB.  The
+    colour-serial entry is per sweep: the class launches of a sweep summed."""
+    import csv
+    import statistics
+
+    def rows(d):
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            return list(csv.DictReader(fh))
+
+    f, w = rows(fetch_dir), rows(write_dir)
+    assert len(f) == len(w) and all(a["Kernel_Name"] == b["Kernel_Name"] for a, b in zip(f, w))
+    copy_f = [float(r["Counter_Value"]) for r in f if "copyBuffer" in r["Kernel_Name"]][:3]
+    copy_w = [float(r["Counter_Value"]) for r in w if "copyBuffer" in r["Kernel_Name"]][:3]
+    fs = (1 << 20) / statistics.median(copy_f)  # KiB of the 1 GiB copy
+    ws = (1 << 20) / statistics.median(copy_w)
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # us
+    out = {}
+    print(f"calibration: copy FETCH_SIZE {statistics.median(copy_f):.1f} KiB, WRITE_SIZE "
+          f"{statistics.median(copy_w):.1f} KiB -> scale {fs:.4f} / {ws:.4f}")
+    print("| kernel | units | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB per unit | unit |")
+    print("|---|---:|---:|---:|---:|---|")
+    for tag, (kname, src) in TRAFFIC_KERNELS.items():
+        idx = [i for i, r in enumerate(f) if kname in r["Kernel_Name"]]
+        if not idx:
+            continue
+        if tag == "k_serial_fp64":
+            # one sweep = one period of the repeating sequence of class grid sizes
+            grids = [f[i]["Grid_Size"] for i in idx]
+            P = next(p for p in range(1, len(grids) + 1)
+                     if all(grids[i] == grids[i + p] for i in range(len(grids) - p)))
+            units = [idx[k:k + P] for k in range(0, len(idx) - P + 1, P)]
+            units = [u for u in units if dur(f[u[0]]) >= 20.0]
+            unit = f"sweep ({P} class launches)"
+        else:
+            units = [[i] for i in idx if dur(f[i]) >= 20.0]
+            unit = "launch"
+        fk = statistics.median(sum(float(f[i]["Counter_Value"]) for i in u) for u in units)
+        wk = statistics.median(sum(float(w[i]["Counter_Value"]) for i in u) for u in units)
+        b = (fk * fs + wk * ws) * 1024.0
+        out[tag] = {"kernel": kname, "workload": f"G(n,4n) n={n}", "unit": unit, "units": len(units),
+                    "fetch_kib": fk, "write_kib": wk, "fetch_scale": fs, "write_scale": ws,
+                    "bytes_per_launch": b, "source_file": src, "source_sha": source_hash(src)}
+        print(f"| `{kname}` | {len(units)} | {fk:.1f} | {wk:.1f} | {b / 1e6:.1f} | {unit} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+def run_solves(torch, g, p, b, precision, steps, warmup, layout="auto"):
+    s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False, layout=layout)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         s.solve(b, tol=TOL, max_iter=2000, x=x)
@@ -143,12 +213,13 @@ def run_solves(torch, g, p, b, precision, steps, warmup):
     return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs}
 
 
-def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3):
+def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto"):
     """Per-sweep time of the checked FP64 joint sweep: slope between two
     fixed-length runs (tolerance below reach, so every sweep carries the fused
     check and nothing stops early), each timed with events around the whole
-    call.  Includes the one-workgroup finish kernel and the dispatch gaps."""
-    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False)
+    call.  Includes the one-workgroup finish kernel and the dispatch gaps
+    (for the colour-serial layout: all class launches of a sweep)."""
+    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False, layout=layout)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     s.solve(b, tol=1e-300, max_iter=n1, x=x)
     best = {}
@@ -264,6 +335,12 @@ def suite_grid(torch, g, workloads):
            "time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "rel_residual": res,
            "edge_updates_per_s": p.num_offdiag * info["sweeps"] / dt, "layout": s.props()["layout"]}
     s.close()
+    s = g.Solver(p.row_ptr, p.col, p.val, layout="serial")
+    s.solve(b, tol=TOL, max_iter=2000)
+    dt, (x, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=2000), reps=5)
+    out["serial"] = {"time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "colours": s.colours()[1],
+                     "rel_residual": float(np.linalg.norm(p.b - p.scipy() @ x.cpu().numpy()) / np.linalg.norm(p.b))}
+    s.close()
     return out
 
 
@@ -285,6 +362,15 @@ def suite_adjoint(torch, g, workloads):
            "adjoint_rel_residual": float(np.linalg.norm(gx - A @ lam) / np.linalg.norm(gx)),
            "backward_edge_updates_per_s": p.num_offdiag * binfo["sweeps"] / dtb}
     layout = s.props()["layout"]
+    s.close()
+    s = g.Solver(p.row_ptr, p.col, p.val, layout="serial")
+    s.backward(s.solve(b, tol=TOL, max_iter=5000)[0], torch.zeros_like(b) + 1.0, tol=TOL)
+    dtf, (x, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=5000))
+    dtb, (gb, gv, binfo) = timed(torch, lambda: s.backward(x, x - t, tol=TOL, max_iter=5000))
+    gx = (x - t).cpu().numpy()
+    out["serial"] = {"forward_ms": 1e3 * dtf, "forward_sweeps": info["sweeps"],
+                     "backward_ms": 1e3 * dtb, "backward_sweeps": binfo["sweeps"], "colours": s.colours()[1],
+                     "adjoint_rel_residual": float(np.linalg.norm(gx - A @ gb.cpu().numpy()) / np.linalg.norm(gx))}
     s.close()
     # roofline of the FP64 joint sweep on this structured graph, where the
     # neighbour gathers stay in L2 (same slope timing as the headline kernel)
@@ -428,7 +514,8 @@ def probe(torch, g, workloads, args):
     del src, dst
     p = workloads.config2(args.n)
     b = torch.from_numpy(p.b).to("cuda")
-    for prec, layout in (("fp64", "compact"), ("fp64", "node"), ("fp64", "edge"), ("fp32", "compact")):
+    for prec, layout in (("fp64", "compact"), ("fp64", "node"), ("fp64", "edge"), ("fp32", "compact"),
+                         ("fp64", "serial")):
         s = g.Solver(p.row_ptr, p.col, p.val, precision=prec, reuse_precision=False, layout=layout,
                      edges_per_block=512)
         for _ in range(args.steps):
@@ -450,7 +537,13 @@ def main():
                     help="skip the other workloads (grid, adjoint, convergence fix, batched)")
     ap.add_argument("--probe", action="store_true",
                     help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from the FETCH_SIZE and WRITE_SIZE counter runs "
+                         "of the probe (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic:
+        traffic_from(*args.traffic, args.n)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of the sweep is a design note, not built", file=sys.stderr)
@@ -476,6 +569,13 @@ def main():
     r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup)
     log("sweep period (fixed-length runs)")
     per_launch_ms = sweep_period(torch, g, p, b)
+    log("colour-serial schedule: FP64 and FP32 + FP64 refinement solves")
+    r64s = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, layout="serial")
+    r32s = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup, layout="serial")
+    per_serial_ms = sweep_period(torch, g, p, b, layout="serial")
+    sc = g.Solver(p.row_ptr, p.col, p.val, layout="serial")
+    ncol = sc.colours()[1]
+    sc.close()
 
     i64 = r64["infos"][-1]
     sweeps64 = i64["sweeps"]
@@ -512,7 +612,34 @@ def main():
         nr = np.linalg.norm(ref["x"])
         vs_oracle = {"fp64": {"rel_err": float(np.linalg.norm(r64["x"] - ref["x"]) / nr),
                               "sweeps_equal": int(sweeps64 == ref["sweeps"])},
-                     "fp32_refine": {"rel_err": float(np.linalg.norm(r32["x"] - ref["x"]) / nr)}}
+                     "fp32_refine": {"rel_err": float(np.linalg.norm(r32["x"] - ref["x"]) / nr)},
+                     "serial_fp64": {"rel_err": float(np.linalg.norm(r64s["x"] - ref["x"]) / nr)},
+                     "serial_fp32_refine": {"rel_err": float(np.linalg.norm(r32s["x"] - ref["x"]) / nr)}}
+
+    # colour-serial schedule (serial scheduling over colour classes)
+    i64s, i32s = r64s["infos"][-1], r32s["infos"][-1]
+    ms64s = r64s["event_ms"] / args.steps
+    ms32s = r32s["event_ms"] / args.steps
+    A = p.scipy()
+    kb_s = serial_layout_bytes(n, E, 8)
+    serial = {
+        "colours": ncol,
+        "fp64": {"time_to_tol_ms": ms64s, "sweeps": i64s["sweeps"],
+                 "rel_residual": float(np.linalg.norm(p.b - A @ r64s["x"]) / np.linalg.norm(p.b)),
+                 "rel_err_vs_synchronous": float(np.linalg.norm(r64s["x"] - r64["x"]) / nr),
+                 "edge_updates_per_s": E * i64s["sweeps"] / (ms64s * 1e-3),
+                 "speedup_vs_synchronous_fp64": ms_step / ms64s,
+                 "vs_oracle": vs_oracle.get("serial_fp64")},
+        "fp32_refine": {"time_to_tol_ms": ms32s, "inner_sweeps": i32s["sweeps"],
+                        "outer_iters": i32s["outer_iters"],
+                        "rel_residual": float(np.linalg.norm(p.b - A @ r32s["x"]) / np.linalg.norm(p.b)),
+                        "speedup_vs_synchronous_fp64": ms_step / ms32s,
+                        "vs_oracle": vs_oracle.get("serial_fp32_refine")},
+        "sweep": {"avg_sweep_ms": per_serial_ms, "launches_per_sweep": ncol,
+                  "kernel_bytes_per_sweep": kb_s, "traffic": measured_traffic("k_serial_fp64"),
+                  "kernel_frac": kb_s / (per_serial_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "alg_frac": alg_sweep_bytes(n, E, 8) / (per_serial_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+    }
 
     suite = {}
     if not args.no_suite:
@@ -565,7 +692,8 @@ def main():
                         "rel_err_vs_fp64": err32, "vs_oracle": vs_oracle.get("fp32_refine"),
                         "edge_updates_per_s": E * i32["sweeps"] / (ms_step32 * 1e-3),
                         "speedup_vs_fp64": ms_step / ms_step32},
-        "kernel_hash": source_hash(),
+        "serial": serial,
+        "kernel_hash": source_hash(LAYOUT_SRC[layout]),
         "suite": suite,
     }
     print(json.dumps(out), flush=True)
