@@ -26,6 +26,9 @@ struct DevStatus {
   double last_rel;     // last relative residual computed
   int32_t last_round;  // round of last_rel (-1: none)
   int32_t pad;
+  double prev_rel;     // the relative residual checked before last_rel
+  int32_t prev_round;  // round of prev_rel (-1: none)
+  int32_t pad2;
 };
 constexpr int32_t kErrNonfinite = 1;
 constexpr int32_t kErrDiverged = 2;
@@ -227,6 +230,8 @@ struct Ctx {
   double* norms_d = nullptr;              // [4]: ||b||, ||r_outer||, spare
   DevStatus* st_d = nullptr;              // [2]: inner / outer
   DevStatus* st_h = nullptr;              // pinned host mirror [4]
+  DevStatus run_seen{};                   // status the last sweep loop's poller observed
+  bool run_seen_final = false;            // ... and it was final (done set, nothing runs after)
   hipEvent_t ev[2] = {nullptr, nullptr};
   // GABP_FLAG_TIME_SWEEPS: event pairs attached to main-mode checking sweeps
   std::vector<hipEvent_t> tev;

@@ -70,22 +70,41 @@ struct Poller {
   }
 };
 
-// Size of the next chunk of sweeps.  Without a usable history the chunks
-// double up to 16.  Once two checked rounds have been observed, the relative
-// residual's decay rate predicts the round that reaches tol, and the chunk
-// only covers the sweeps up to the one that checks that round (a zero chunk
-// just polls the sweeps already queued), so few early-return sweeps are
-// queued past convergence.
+// A sweep loop has ended: keep the status its poller observed.  Once done is
+// set, every later sweep and finish kernel returns at once, so that status is
+// final and the caller need not read it again.
+gabp_status finish_run(Ctx* c, const Poller& p) {
+  c->run_seen = p.seen;
+  c->run_seen_final = p.err == GABP_OK && p.have && p.seen.done != 0;
+  return p.err;
+}
+
+// Size of the next chunk of sweeps.  The first chunk reaches the sweep that
+// checks the second checked round; without a usable history the chunks then
+// double up to 16.  Once two checked rounds have been observed (the device
+// status carries the last two), the relative residual's decay rate predicts
+// the round that reaches tol, and the chunk only covers the sweeps up to the
+// one that checks that round (a zero chunk just polls the sweeps already
+// queued), so few early-return sweeps are queued past convergence.
 struct ChunkPlan {
   int chunk = 2;
   double rel0 = -1.0, rel1 = -1.0;
   int round0 = -1, round1 = -1;
   int idle = 0;
+  int first(int lag, int check_every) {
+    chunk = std::min(16, 2 * std::max(1, check_every) + lag);
+    return chunk;
+  }
   int next(const Poller& p, int queued_through, int lag, int check_every, double tol) {
     int c = std::min(chunk * 2, 16);
     if (p.have && p.seen.last_round > round1) {
-      rel0 = rel1;
-      round0 = round1;
+      if (p.seen.prev_round >= 0) {
+        rel0 = p.seen.prev_rel;
+        round0 = p.seen.prev_round;
+      } else {
+        rel0 = rel1;
+        round0 = round1;
+      }
       rel1 = p.seen.last_rel;
       round1 = p.seen.last_round;
     }
@@ -149,9 +168,9 @@ gabp_status run_edge(Ctx* c, const RunCfg& cfg) {
 
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   const int last = M + 2;
-  int t = 1, chunk = 2;
   Poller poll;
   ChunkPlan plan;
+  int t = 1, chunk = plan.first(2, ce);
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -184,7 +203,7 @@ gabp_status run_edge(Ctx* c, const RunCfg& cfg) {
     stop = poll.step(c, cfg.st);
     chunk = plan.next(poll, t - 1, 2, ce, exact ? -1.0 : cfg.tol);
   }
-  return poll.err;
+  return finish_run(c, poll);
 }
 
 // Node-broadcast layout.  Sweep t publishes the aggregates of round t (and
@@ -218,9 +237,9 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
 
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   const int last = M + 1;
-  int t = 1, chunk = 2;
   Poller poll;
   ChunkPlan plan;
+  int t = 1, chunk = plan.first(1, ce);
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -254,7 +273,7 @@ gabp_status run_node(Ctx* c, const RunCfg& cfg) {
     stop = poll.step(c, cfg.st);
     chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
   }
-  return poll.err;
+  return finish_run(c, poll);
 }
 
 // Compact layout: the incoming messages of even and odd rounds live in the
@@ -300,9 +319,9 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
                                     (const T*)cfg.rhs, c->agg_d[0], s));
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   const int last = M + 1;
-  int t = 1, chunk = 2;
   Poller poll;
   ChunkPlan plan;
+  int t = 1, chunk = plan.first(1, ce);
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -338,7 +357,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
     stop = poll.step(c, cfg.st);
     chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
   }
-  return poll.err;
+  return finish_run(c, poll);
 }
 
 // Colour-serial layout: sweep t updates the colour classes in turn (one
@@ -385,9 +404,9 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
   }
 
   const int last = M + 1;
-  int t = 1, chunk = 2;
   Poller poll;
   ChunkPlan plan;
+  int t = 1, chunk = plan.first(1, ce);
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
@@ -429,11 +448,12 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
     stop = poll.step(c, cfg.st);
     chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
   }
-  return poll.err;
+  return finish_run(c, poll);
 }
 
 template <typename T>
 gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
+  c->run_seen_final = false;
   if (c->layout == kLayoutSerial) return run_serial<T>(c, cfg);
   if (c->layout == kLayoutCompact) return run_cnode<T>(c, cfg);
   return c->layout == kLayoutNode ? run_node<T>(c, cfg) : run_edge<T>(c, cfg);
@@ -734,7 +754,11 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     cfg.st = st_in;
     r = fp32 ? run_sweeps<float>(c, cfg) : run_sweeps<double>(c, cfg);
     if (r != GABP_OK) return r;
-    r = read_status(c, st_in, &si);
+    if (c->run_seen_final && c->tev_used == 0) {  // the poller already waited for the final status
+      si = c->run_seen;
+    } else {
+      r = read_status(c, st_in, &si);
+    }
     if (r != GABP_OK) return r;
     if (si.error & kErrNonfinite) return fail(c, GABP_E_NONFINITE, "non-finite inner message");
     if (si.error & kErrDiverged) {

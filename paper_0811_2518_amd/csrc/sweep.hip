@@ -104,6 +104,8 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
     const double rn = sqrt(tot);
     const double rel = nb > 0.0 ? rn / nb : rn;
     if (norm_out) *norm_out = rn;
+    st->prev_rel = st->last_rel;
+    st->prev_round = st->last_round;
     st->last_rel = rel;
     st->last_round = round;
     if (rel <= tol) {
@@ -518,6 +520,9 @@ __global__ void k_reset_status(DevStatus* st, int count) {
     st[i].last_rel = -1.0;
     st[i].last_round = -1;
     st[i].pad = 0;
+    st[i].prev_rel = -1.0;
+    st[i].prev_round = -1;
+    st[i].pad2 = 0;
   }
 }
 
