@@ -237,6 +237,25 @@ def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto"):
     return (best[n2] - best[n1]) / (n2 - n1)
 
 
+def copy_rate(torch, nbytes=1 << 30, reps=5):
+    """Measured device copy bandwidth (bytes read + written per second) of a
+    1 GiB device-to-device tensor copy, best of reps."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3)
+
+
 def cpu_baseline(p, reps):
     """The FP64 oracle solving the same system to the same tolerance with the
     same stop rule, ``reps`` times (the last result is returned for the
@@ -447,6 +466,15 @@ def suite_batched(torch, g, workloads, sample=48):
     worst = max(i["rel_residual"] for i in infos)
     prof = bs.profile()
     bs.close()
+    # the same batch under the colour-serial schedule inside each work item
+    bss = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, layout="serial")
+    dts, (X, infos_s, st_s) = timed(torch, lambda: bss.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=100000,
+                                                             X=X, check=False))
+    serial = {"time_to_tol_ms": 1e3 * dts, "status": st_s,
+              "converged_systems": sum(i["converged"] for i in infos_s),
+              "worst_rel_residual": max(i["rel_residual"] for i in infos_s),
+              "speedup_vs_synchronous": dt / dts, "load_balance": bss.profile()}
+    bss.close()
     del X
     # per-system loop on a seeded sample: single-system FP32 + refinement handles,
     # one solve per right-hand side, against the batched launch on the same systems
@@ -496,7 +524,7 @@ def suite_batched(torch, g, workloads, sample=48):
             "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
             "E": int(E_s.sum()), "generate_s": gen_s, "time_to_tol_ms": 1e3 * dt, "status": st,
             "converged_systems": nconv, "worst_rel_residual": worst,
-            "slot_rhs_updates_per_s": slot_rhs / dt, "load_balance": prof,
+            "slot_rhs_updates_per_s": slot_rhs / dt, "load_balance": prof, "serial": serial,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
                                 "speedup": loop_s / sub_s},
@@ -569,6 +597,7 @@ def main():
     r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup)
     log("sweep period (fixed-length runs)")
     per_launch_ms = sweep_period(torch, g, p, b)
+    copy_gbs = copy_rate(torch) / 1e9
     log("colour-serial schedule: FP64 and FP32 + FP64 refinement solves")
     r64s = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, layout="serial")
     r32s = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup, layout="serial")
@@ -680,6 +709,9 @@ def main():
                      "alg_model": "48 B/slot + 52 B/node (FP64 sweep, per-unit algorithmic model)",
                      "kernel_bytes_per_launch": kernel_bytes,
                      "kernel_frac": kernel_bytes / (per_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "copy_GBs": copy_gbs,
+                     "frac_vs_copy": achieved / copy_gbs,
+                     "traffic_GBs": traffic / (per_launch_ms * 1e-3) / 1e9 if traffic else None,
                      "avg_launch_ms": per_launch_ms,
                      "timing": "slope of fixed-length checked runs; includes the finish kernel "
                                "and dispatch gaps of each sweep"},

@@ -270,7 +270,7 @@ class BatchedSolver:
     """Many independent systems (block-diagonal CSR with global columns)."""
 
     def __init__(self, sys_row_off, row_ptr, col, val, *, inner_tol=1e-5, check_every=1,
-                 inner_max_iter=10000, max_outer=1000, device="cuda", stream=None):
+                 inner_max_iter=10000, max_outer=1000, layout="auto", device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
         self.stream, sh = _stream_handle(stream)
@@ -280,7 +280,7 @@ class BatchedSolver:
         self.val = _dev(val, torch.float64, self.device)
         self.num_sys = len(self.sys_row_off) - 1
         self.opts = default_opts(precision=FP32_REFINE, inner_tol=inner_tol, check_every=check_every,
-                                 inner_max_iter=inner_max_iter, max_outer=max_outer)
+                                 inner_max_iter=inner_max_iter, max_outer=max_outer, layout=LAYOUTS[layout])
         h = ctypes.c_void_p()
         st = lib().gabp_create_batched(self.num_sys, self.sys_row_off.ctypes.data_as(c_void_p),
                                        _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
@@ -288,6 +288,16 @@ class BatchedSolver:
         if st != OK:
             raise _err(None, st, "gabp_create_batched")
         self._h = h
+
+    def colours(self):
+        """(colour of each global row, number of classes of the largest system); layout "serial" only."""
+        n = int(self.sys_row_off[-1])
+        col = np.zeros(max(n, 1), dtype=np.int32)
+        k = c_i32(0)
+        st = lib().gabp_get_colours(self._h, col.ctypes.data_as(c_void_p), ctypes.byref(k))
+        if st != OK:
+            raise _err(self._h, st, "gabp_get_colours")
+        return col[:n], int(k.value)
 
     def solve(self, nrhs, rhs_off, B, tol=1e-10, max_iter=100000, X=None, check=True):
         torch = _torch()

@@ -51,6 +51,7 @@ struct Item {
   int64_t off_he;          // h messages (2 E kg floats)
   int64_t off_nk;          // h aggregates and inner right-hand side (4 n kg floats)
   int64_t rhs_off;         // B / X offset of the system
+  int32_t cls0, ncls;      // colour-serial: the system's class starts in cls_row, number of classes
 };
 
 struct ItemInfo {
@@ -82,6 +83,10 @@ struct BatchArgs {
   int32_t inner_max;
   int32_t max_outer;
   int32_t max_iter;
+  // colour-serial schedule: rows renumbered by colour class inside each system
+  const int32_t* cls_row;  // global first row of each class (see Item::cls0)
+  const int32_t* umap;     // [n] internal row -> caller row (B and X stay in caller order)
+  int32_t serial;
 };
 
 using f2 = float __attribute__((ext_vector_type(2)));
@@ -107,8 +112,11 @@ struct ItemView {
   float* H0;       // [2][E kg] incoming h messages by round parity, [slot][rhs]
   float* hagg0;    // [3][n kg] h~ by round mod 3, [node][rhs]
   float* r32;      // [n kg] right-hand side of the correction system
-  const double* B; // [n][k] of the system
-  double* X;       // [n][k] of the system
+  const double* B; // [n][k] of the system, caller's row order
+  double* X;       // [n][k] of the system, caller's row order
+  const int32_t* umap;  // colour-serial: item-local internal row -> global caller row (else null)
+  // row of B and X (item-local) that holds internal row i
+  __device__ int urow(int i) const { return umap ? umap[i] - r0 : i; }
   // buffers of a round (pointer arithmetic keeps the view in registers)
   __device__ float* P(int t) const { return P0 + (t & 1) * E; }
   __device__ float* Pagg(int t) const { return Pagg0 + (t % 3) * (int64_t)n; }
@@ -153,8 +161,9 @@ __device__ __forceinline__ void wave_sync() {
 // corrects whatever the inner solves leave).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <int KIND>
-__device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const WaveShared& sh, RowOut& ro) {
+template <int KIND, bool SER>
+__device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const WaveShared& sh, RowOut& ro, int rlo,
+                          int rhi) {
   const int lane = threadIdx.x & (kWave - 1);
   // uniform within the wave: the tile loop runs on scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -162,7 +171,8 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
   const int R = kWave / kgE;    // rows per tile; also slots per k-step of a chunk
   constexpr int KT = (KIND == kTSpmv) ? kKT / 2 : kKT;  // FP64 tasks hold twice the registers
   const int CHS = R * KT;       // slots per chunk
-  const bool first = (t == 1), second = (t == 2);  // sweeps (freeze: T == 0, T == 1)
+  // sweeps (synchronous freeze: T == 0, T == 1); the serial freeze has no first sweep
+  const bool first = (t == 1) && !(SER && KIND == kTFreeze), second = (t == 2);
   // lane -> (slot offset, right-hand side); lanes R * kgE .. 63 idle when kgE
   // does not divide 64
   const bool tl = lane < R * kgE;
@@ -175,20 +185,22 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
   const float* a32p = A.a32 + V.s0;
   const double* a64p = A.a64 + V.s0;
   const float* d32p = A.d32 + V.r0;
-  float* Pt_ = V.P(t);                                      // P: in^(t-2) -> in^(t); freeze: in^(T)
-  const float* Pold_ = V.P(t + 1);                          // freeze: in^(T-1)
-  const float* Pg_ = V.Pagg(KIND == kTFreeze ? t : t + 2);  // gathered P~ of round t-1 (T)
-  float* Ht_ = V.H(t);
-  const float* hg_ = V.hagg(t + 2);                         // gathered h~ of round t-1
+  // synchronous: in^(t-2) -> in^(t) (freeze: in^(T)); serial: one set of
+  // outgoing messages, updated in place
+  float* Pt_ = SER ? V.P0 : V.P(t);
+  const float* Pold_ = V.P(t + 1);                                       // freeze: in^(T-1)
+  const float* Pg_ = SER ? V.Pagg0 : V.Pagg(KIND == kTFreeze ? t : t + 2);  // gathered P~ of round t-1 (T)
+  float* Ht_ = SER ? V.H0 : V.H(t);
+  const float* hg_ = SER ? V.hagg0 : V.hagg(t + 2);                      // gathered h~ of round t-1
   const float* r32_ = V.r32;
   const double* Xs = V.X + V.j0;
   float* stagef = (float*)sh.stage;
   double* staged = (double*)sh.stage;
-  const int ntiles = (V.n + R - 1) / R;
+  const int ntiles = (rhi - rlo + R - 1) / R;
 
   for (int tile = wave; tile < ntiles; tile += kWaves) {
-    const int tr0 = tile * R;
-    const int nr = min(R, V.n - tr0);
+    const int tr0 = rlo + tile * R;
+    const int nr = min(R, rhi - tr0);
     const int e0 = off_ptr[tr0] - (int)V.s0;  // item-local slot of the tile's first row
     const int ne = off_ptr[tr0 + nr] - (int)V.s0 - e0;
     const bool rl = tl && ls < nr;  // lane owns the (row ls, rhs jj) pair
@@ -211,28 +223,36 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
             ta[k] = a32p[e];
             tm[k] = 0.f;
             tcf[k] = f2{0.f, 0.f};
-            if (KIND == kTP && !first && !second) tm[k] = Pt_[e];  // in^(t-2)
-            if (KIND == kTFreeze && !first) {
-              tm[k] = Pt_[e];                                      // in^(T)
-              if (!second) tcf[k].x = Pold_[e];                    // in^(T-1)
+            if (SER) {
+              if (!first) tm[k] = Pt_[e];                          // out_{j->i} of j's last update
+            } else {
+              if (KIND == kTP && !first && !second) tm[k] = Pt_[e];  // in^(t-2)
+              if (KIND == kTFreeze && !first) {
+                tm[k] = Pt_[e];                                      // in^(T)
+                if (!second) tcf[k].x = Pold_[e];                    // in^(T-1)
+              }
             }
           } else if (KIND == kTH) {
             tcf[k] = V.coef[e];
-            tm[k] = (!first && !second) ? Ht_[e * kg + jj] : 0.f;  // h_in^(t-2)
+            if (SER) tm[k] = first ? 0.f : Ht_[e * kg + jj];             // h_out of j's last update
+            else tm[k] = (!first && !second) ? Ht_[e * kg + jj] : 0.f;  // h_in^(t-2)
           } else {
             tad[k] = a64p[e];
           }
         }
       }
       // the gathers: neighbour aggregates of round t-1 (freeze: T), or x
+      // (serial: the neighbour's last update; nothing from a later class in
+      // the first sweep)
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
         const int sl = cs0 + ls + k * R;
         if (tl && sl < ne) {
           const int c = tc[k];
-          if (KIND == kTP || KIND == kTFreeze) tg[k] = first ? d32p[c] : Pg_[c];
-          else if (KIND == kTH) tg[k] = (first ? r32_ : hg_)[c * kg + jj];
-          else txd[k] = Xs[c * V.k + jj];
+          const bool silent = SER && first && c >= rhi;
+          if (KIND == kTP || KIND == kTFreeze) tg[k] = silent ? 0.f : ((first && !SER) ? d32p[c] : Pg_[c]);
+          else if (KIND == kTH) tg[k] = silent ? 0.f : ((first && !SER) ? r32_ : hg_)[c * kg + jj];
+          else txd[k] = Xs[(int64_t)V.urow(c) * V.k + jj];
         }
       }
     };
@@ -240,24 +260,37 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
 
     // row side: slot offsets and own values of round t-2 (freeze: T-1) and
     // t-1 (T); what the epilogue needs besides is loaded here as well
+    // (serial: the row's own aggregate of its last update)
     int rp = 0;
     float er = 0.f, eip = 0.f;  // epilogue: prior / inner right-hand side, 1 / P~
     if (rl) {
       rp = off_ptr[i] - (int)V.s0 - e0;
       float o1 = 0.f, o2 = 0.f;
       if (KIND == kTP) {
-        o1 = first ? d32p[i] : V.Pagg(t + 2)[i];
-        o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 1)[i]);
+        if (SER) {
+          o1 = first ? d32p[i] : V.Pagg0[i];
+        } else {
+          o1 = first ? d32p[i] : V.Pagg(t + 2)[i];
+          o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 1)[i]);
+        }
         er = d32p[i];
       } else if (KIND == kTFreeze) {
-        o1 = first ? d32p[i] : V.Pagg(t)[i];
-        o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 2)[i]);
+        if (SER) {
+          o1 = V.Pagg0[i];
+        } else {
+          o1 = first ? d32p[i] : V.Pagg(t)[i];
+          o2 = second ? d32p[i] : (first ? 0.f : V.Pagg(t + 2)[i]);
+        }
       } else if (KIND == kTH) {
         const int q = i * kg + jj;
         er = r32_[q];
         eip = V.invPt[i];
-        o1 = first ? er : V.hagg(t + 2)[q];
-        o2 = second ? er : (first ? 0.f : V.hagg(t + 1)[q]);
+        if (SER) {
+          o1 = first ? 0.f : V.hagg0[q];
+        } else {
+          o1 = first ? er : V.hagg(t + 2)[q];
+          o2 = second ? er : (first ? 0.f : V.hagg(t + 1)[q]);
+        }
       }
       sh.own[lane] = o2;
       sh.own1[lane] = o1;
@@ -282,7 +315,25 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
           const int e = e0 + sl;
           const int st = (sl - cs0) * kgE + jj;  // stage slot of the task
           const int lr = sh.row[sl - cs0];
-          if (KIND == kTP) {
+          if (SER && KIND == kTP) {
+            // pulled in_{i->j} = F(P~_i, out_{j->i}), kept in the slot until pass 2
+            const float Pin = (first && tc[k] >= rhi) ? 0.f : -ta[k] * ta[k] * rcp(tg[k] - tm[k]);
+            Pt_[e] = Pin;
+            stagef[st] = Pin;
+          } else if (SER && KIND == kTFreeze) {
+            const float av = ta[k];
+            const float r_in = rcp(tg[k] - tm[k]);
+            const float Pin = -av * av * r_in;
+            f2 cf;
+            cf.x = -av * r_in;                       // g_in  = -a / (P~_i - P_{j->i})
+            cf.y = -av * rcp(sh.own1[lr] - Pin);     // g_out = -a / (P~_j - P_{i->j})
+            V.coef[e] = cf;
+            stagef[st] = cf.x + cf.y;  // finiteness only
+          } else if (SER && KIND == kTH) {
+            const float hin = (first && tc[k] >= rhi) ? 0.f : tcf[k].x * (tg[k] - tm[k]);
+            Ht_[e * kg + jj] = hin;
+            stagef[st] = hin;
+          } else if (KIND == kTP) {
             const float av2 = -ta[k] * ta[k];
             float Pout = 0.f;
             if (!first) Pout = av2 * rcp(sh.own[lr] - tm[k]);  // out^(t-1)
@@ -324,24 +375,55 @@ __device__ void tile_pass(const BatchArgs& A, const ItemView& V, int t, const Wa
       const float o1 = sh.own1[lane];
       if (KIND == kTP) {
         const float Pt = er + accf;
-        V.Pagg(t)[i] = Pt;
+        (SER ? V.Pagg0 : V.Pagg(t))[i] = Pt;
         ro.dmax = fmaxf(ro.dmax, fabsf(Pt - o1) / fabsf(Pt));
+        if (SER) sh.own1[lane] = Pt;
       } else if (KIND == kTFreeze) {
         const float ip = rcp(o1);
         V.invPt[i] = ip;
         if (!isfinite(accf) || !isfinite(ip)) ro.dmax = __int_as_float(0x7fc00000);
       } else if (KIND == kTH) {
         const float ht = er + accf;
-        V.hagg(t)[i * kg + jj] = ht;
+        (SER ? V.hagg0 : V.hagg(t))[i * kg + jj] = ht;
         const float dn = ht * eip;
         const float dold = first ? 0.f : o1 * eip;
         ro.dmax = fmaxf(ro.dmax, fabsf(dn - dold));
         ro.xmax = fmaxf(ro.xmax, fabsf(dn));
+        if (SER) sh.own1[lane] = ht;
       } else {
-        const int q = i * V.k + V.j0 + jj;
+        const int q = V.urow(i) * V.k + V.j0 + jj;
         const double r = V.B[q] - A.d64[V.r0 + i] * V.X[q] - accd;
         V.r32[i * kg + jj] = (float)r;
         ro.r2 += r * r;
+      }
+    }
+    // serial pass 2: the new outgoing messages out_{j->i} = F(agg_j, in_{i->j}),
+    // from the row's new aggregate and the pulled message kept in the slot
+    if (SER && (KIND == kTP || KIND == kTH)) {
+      wave_sync();
+      for (int cs0 = 0; cs0 < ne; cs0 += CHS) {
+        const int cs1 = min(ne, cs0 + CHS);
+        if (rl && jj == 0)
+          for (int e = max(lo, cs0); e < min(hi, cs1); ++e) sh.row[e - cs0] = (uint16_t)ls;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+          const int sl = cs0 + ls + k * R;
+          if (tl && sl < ne) {
+            const int e = e0 + sl;
+            const int lr = sh.row[sl - cs0];
+            if (KIND == kTP) {
+              const float av = a32p[e];
+              const float Pin = Pt_[e];
+              Pt_[e] = -av * av * rcp(sh.own1[lr] - Pin);
+            } else {
+              const float gout = V.coef[e].y;
+              const float hin = Ht_[e * kg + jj];
+              Ht_[e * kg + jj] = gout * (sh.own1[lr * kgE + jj] - hin);
+            }
+          }
+        }
+        wave_sync();
       }
     }
     wave_sync();  // the next tile rewrites the wave's LDS row structure
@@ -368,6 +450,16 @@ __device__ void col_sums(double v, int col, int kg, double* s_part, int* s_cidx,
   __syncthreads();
 }
 
+// The item record read by every lane, made provably uniform (the compiler
+// cannot use scalar loads for it), so that everything derived from it stays in
+// scalar registers.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <bool SER>
 __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const WaveShared& sh, unsigned* s_max,
                            double* s_part, int* s_cidx, double* s_col, double* s_bn, int* s_flag) {
   const int tid = threadIdx.x;
@@ -392,6 +484,7 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
   V.r32 = kb + 3 * nk;
   V.B = A.B + I.rhs_off;
   V.X = A.X + I.rhs_off;
+  V.umap = SER ? A.umap + I.r0 : nullptr;
   const int kg = V.kg;
   const int Tq = (kBT / kg) * kg;  // lanes that own (row, rhs) pairs
   int status = 0;
@@ -408,7 +501,15 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
     if (tid == 0) s_max[0] = 0u;
     __syncthreads();
     RowOut ro{0.f, 0.f, 0.0};
-    tile_pass<kTP>(A, V, tp, sh, ro);
+    if (SER) {
+      for (int q = 0; q < I.ncls; ++q) {  // the colour classes in turn
+        const int rlo = uni(A.cls_row[I.cls0 + q]) - I.r0, rhi = uni(A.cls_row[I.cls0 + q + 1]) - I.r0;
+        tile_pass<kTP, true>(A, V, tp, sh, ro, rlo, rhi);
+        __syncthreads();
+      }
+    } else {
+      tile_pass<kTP, false>(A, V, tp, sh, ro, 0, V.n);
+    }
     lds_max(&s_max[0], ro.dmax);
     __syncthreads();  // also orders this round's aggregates before the next pass
     const float ch = __uint_as_float(s_max[0]);
@@ -426,7 +527,7 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
     if (tid == 0) s_max[0] = 0u;
     __syncthreads();
     RowOut ro{0.f, 0.f, 0.0};
-    tile_pass<kTFreeze>(A, V, tp, sh, ro);
+    tile_pass<kTFreeze, SER>(A, V, tp, sh, ro, 0, V.n);
     if (!(ro.dmax == 0.f)) *s_flag = 1;
     __syncthreads();
   }
@@ -437,8 +538,9 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
   if (tid < Tq)
     for (int q = tid; q < V.n * kg; q += Tq) {
       const int i = q / kg;
-      const double bv = V.B[(int64_t)i * V.k + V.j0 + jj];
-      V.X[(int64_t)i * V.k + V.j0 + jj] = 0.0;
+      const int64_t qb = (int64_t)V.urow(i) * V.k + V.j0 + jj;
+      const double bv = V.B[qb];
+      V.X[qb] = 0.0;
       V.r32[q] = (float)bv;
       bpart += bv * bv;
     }
@@ -455,7 +557,15 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
       if (tid < 2 * kMaxGroup) s_max[tid] = 0u;
       __syncthreads();
       RowOut ro{0.f, 0.f, 0.0};
-      tile_pass<kTH>(A, V, t, sh, ro);
+      if (SER) {
+        for (int q = 0; q < I.ncls; ++q) {
+          const int rlo = uni(A.cls_row[I.cls0 + q]) - I.r0, rhi = uni(A.cls_row[I.cls0 + q + 1]) - I.r0;
+          tile_pass<kTH, true>(A, V, t, sh, ro, rlo, rhi);
+          __syncthreads();
+        }
+      } else {
+        tile_pass<kTH, false>(A, V, t, sh, ro, 0, V.n);
+      }
       lds_max(&s_max[tile_col(kg)], ro.dmax);
       lds_max(&s_max[kMaxGroup + tile_col(kg)], ro.xmax);
       __syncthreads();
@@ -471,15 +581,15 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
     total += t;
     // x += d (FP64) with d = h~ / P~ of the last inner round, then r = b - A x
     {
-      const float* hT = V.hagg(t);
+      const float* hT = SER ? V.hagg0 : V.hagg(t);
       if (tid < Tq)
         for (int q = tid; q < V.n * kg; q += Tq)
-          V.X[(int64_t)(q / kg) * V.k + V.j0 + jj] += (double)(hT[q] * V.invPt[q / kg]);
+          V.X[(int64_t)V.urow(q / kg) * V.k + V.j0 + jj] += (double)(hT[q] * V.invPt[q / kg]);
       __syncthreads();
     }
     RowOut ro{0.f, 0.f, 0.0};
     __syncthreads();
-    tile_pass<kTSpmv>(A, V, 0, sh, ro);
+    tile_pass<kTSpmv, SER>(A, V, 0, sh, ro, 0, V.n);
     col_sums(ro.r2, tile_col(kg), kg, s_part, s_cidx, s_col);
     ++outer;
     relmax = 0.0;
@@ -515,15 +625,6 @@ __device__ void solve_item(const BatchArgs& A, const Item& I, int it, const Wave
   __syncthreads();
 }
 
-// The item record read by every lane, made provably uniform (the compiler
-// cannot use scalar loads for it), so that everything derived from it stays in
-// scalar registers.
-__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t uni(int64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 __device__ __forceinline__ Item uniform_item(const Item& x) {
   Item u;
   u.sys = uni(x.sys);
@@ -539,6 +640,8 @@ __device__ __forceinline__ Item uniform_item(const Item& x) {
   u.off_he = uni(x.off_he);
   u.off_nk = uni(x.off_nk);
   u.rhs_off = uni(x.rhs_off);
+  u.cls0 = uni(x.cls0);
+  u.ncls = uni(x.ncls);
   return u;
 }
 
@@ -546,6 +649,9 @@ __device__ __forceinline__ Item uniform_item(const Item& x) {
 // per CU.  A few registers spill, which costs less than the extra resident
 // workgroups gain (two per CU without the cap, four with a tighter one are
 // both slower on the 4096-system batch).
+// SER: the colour-serial schedule (a separate kernel, so that the synchronous
+// one keeps its own register allocation).
+template <bool SER>
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(6))) void k_batched(BatchArgs A) {
   __shared__ int s_item;
   __shared__ int s_flag;
@@ -572,7 +678,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(6))) void k
     const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= A.num_items) return;  // every workgroup leaves once the queue is empty
-    solve_item(A, uniform_item(A.items[it]), it, sh, s_max, s_part, s_cidx, s_col, s_bn, &s_flag);
+    solve_item<SER>(A, uniform_item(A.items[it]), it, sh, s_max, s_part, s_cidx, s_col, s_bn, &s_flag);
   }
 }
 
@@ -624,6 +730,7 @@ struct BatchState {
   ItemInfo* infos_d = nullptr;
   size_t items_cap = 0;
   uint32_t* queue_d = nullptr;
+  int32_t* cls_row_d = nullptr;  // colour-serial: class starts of every system
   float* ebuf = nullptr;
   float* nbuf = nullptr;
   float* hbuf = nullptr;
@@ -675,11 +782,22 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off) 
   for (int s = 0; s <= num_sys; ++s)
     bs->sys_slot_off[s] = c->n > 0 ? c->off_ptr_h[sys_row_off[s]] : 0;
   GABP_HIP(c, hipMalloc((void**)&bs->queue_d, sizeof(uint32_t)));
+  if (c->opts.layout == kLayoutSerial) {
+    c->layout = kLayoutSerial;
+    if (c->cls_row.empty()) {  // no rows: one empty class list per system
+      c->cls_row.assign(num_sys, 0);
+      c->cls_base.resize(num_sys + 1);
+      for (int s = 0; s <= num_sys; ++s) c->cls_base[s] = s;
+    }
+    GABP_HIP(c, hipMalloc((void**)&bs->cls_row_d, sizeof(int32_t) * c->cls_row.size()));
+    GABP_HIP(c, hipMemcpyAsync(bs->cls_row_d, c->cls_row.data(), sizeof(int32_t) * c->cls_row.size(),
+                               hipMemcpyHostToDevice, c->stream));
+  }
   // the persistent grid: as many workgroups as can be resident at once
   int dev = 0, ncu = 0, per_cu = 0;
   GABP_HIP(c, hipGetDevice(&dev));
   GABP_HIP(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  GABP_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, kBT, 0));
+  GABP_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<false>, kBT, 0));
   bs->grid = std::max(1, ncu * std::max(1, per_cu));
   int khz = 0;
   GABP_HIP(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -773,6 +891,10 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
         it.off_he = ohe;
         it.off_nk = onk;
         it.rhs_off = rhs_off[s];
+        if (bs->cls_row_d) {
+          it.cls0 = c->cls_base[s];
+          it.ncls = c->cls_base[s + 1] - c->cls_base[s] - 1;
+        }
         oe += E;
         on += (r1 - r0);
         ohe += E * it.kg;
@@ -824,6 +946,9 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     a.inner_max = std::max(1, c->opts.inner_max_iter);
     a.max_outer = std::max(1, c->opts.max_outer);
     a.max_iter = std::max(1, max_iter);
+    a.serial = bs->cls_row_d ? 1 : 0;
+    a.cls_row = bs->cls_row_d;
+    a.umap = bs->cls_row_d ? c->inv_d : nullptr;
     if (bs->exec) {
       (void)hipGraphExecDestroy(bs->exec);
       bs->exec = nullptr;
@@ -838,7 +963,8 @@ gabp_status batched_solve(Ctx* c, const int32_t* nrhs, const int64_t* rhs_off, c
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, bs->gs, bs->queue_d);
     const int grid = std::max(1, std::min<int>(bs->grid, (int)items.size()));
     bs->launched_grid = grid;
-    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kBT), 0, bs->gs, a);
+    if (a.serial) hipLaunchKernelGGL(k_batched<true>, dim3(grid), dim3(kBT), 0, bs->gs, a);
+    else hipLaunchKernelGGL(k_batched<false>, dim3(grid), dim3(kBT), 0, bs->gs, a);
     hipError_t e = hipStreamEndCapture(bs->gs, &bs->graph);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
     GABP_HIP(c, hipGraphInstantiate(&bs->exec, bs->graph, nullptr, nullptr, 0));
@@ -930,6 +1056,7 @@ void batched_destroy(Ctx* c) {
   free_raw(bs->items_d);
   free_raw(bs->infos_d);
   free_raw(bs->queue_d);
+  free_raw(bs->cls_row_d);
   free_raw(bs->ebuf);
   free_raw(bs->nbuf);
   free_raw(bs->hbuf);

@@ -178,7 +178,7 @@ gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_id
   gabp_status r = check_opts(c, c->opts);
   if (r == GABP_OK) r = common_setup(c);
   if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, nullptr, 0);
-  if (r == GABP_OK && n > 0 && c->opts.layout == kLayoutSerial) r = apply_colour_order(c);
+  if (r == GABP_OK && n > 0 && c->opts.layout == kLayoutSerial) r = apply_colour_order(c, nullptr, 0);
   if (r == GABP_OK && n > 0) r = alloc_solver(c);
   if (r == GABP_OK && n > 0) r = autotune(c);
   if (r == GABP_OK && n > 0) release_unused_layout(c);
@@ -308,6 +308,8 @@ gabp_status gabp_create_batched(int32_t num_sys, const int32_t* sys_row_off, con
   gabp_status r = check_opts(c, c->opts);
   if (r == GABP_OK && c->opts.precision != GABP_FP32_REFINE)
     r = fail(c, GABP_E_ARG, "batched solves run FP32 messages with FP64 refinement");
+  if (r == GABP_OK && c->opts.layout != 0 && c->opts.layout != kLayoutSerial)
+    r = fail(c, GABP_E_ARG, "batched solves take layout 0 (synchronous) or 4 (colour-serial)");
   if (r == GABP_OK) r = common_setup(c);
   int32_t* sys_d = nullptr;
   if (r == GABP_OK) r = dev_alloc(c, (void**)&sys_d, sizeof(int32_t) * (num_sys + 1));
@@ -316,6 +318,7 @@ gabp_status gabp_create_batched(int32_t num_sys, const int32_t* sys_row_off, con
     if (e != hipSuccess) r = hip_fail(c, e, "hipMemcpyAsync");
   }
   if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, sys_d, num_sys);
+  if (r == GABP_OK && n > 0 && c->opts.layout == kLayoutSerial) r = apply_colour_order(c, sys_row_off, num_sys);
   if (r == GABP_OK) r = batched_create(c, num_sys, sys_row_off);
   if (r == GABP_OK) {
     hipError_t e = hipStreamSynchronize(stream);
@@ -349,8 +352,7 @@ gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile* out) {
 gabp_status gabp_get_colours(gabp_handle h, int32_t* colour, int32_t* num_colours) {
   if (!h) return fail(nullptr, GABP_E_ARG, "NULL handle");
   Ctx* c = h;
-  if (c->batched || c->opts.layout != kLayoutSerial)
-    return fail(c, GABP_E_ARG, "not a colour-serial handle (layout 4)");
+  if (c->opts.layout != kLayoutSerial) return fail(c, GABP_E_ARG, "not a colour-serial handle (layout 4)");
   if (num_colours) *num_colours = c->ncol;
   if (colour && c->n > 0) std::memcpy(colour, c->colour_h.data(), sizeof(int32_t) * c->n);
   return GABP_OK;

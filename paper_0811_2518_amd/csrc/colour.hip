@@ -7,6 +7,9 @@
 // the host over the already validated off-diagonal pattern.  The
 // off-diagonal CSR is then renumbered on the device so that each class is a
 // contiguous row range, rows kept in increasing caller order inside a class.
+// For a batch of independent systems, first fit in global row order colours
+// every system on its own (no edge crosses a system), and the renumbering
+// stays inside each system's row block.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,7 +50,7 @@ __global__ void k_permute_rows(int32_t n, const int32_t* __restrict__ inv, const
 
 }  // namespace
 
-gabp_status apply_colour_order(Ctx* c) {
+gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys) {
   hipStream_t s = c->stream;
   const int32_t n = c->n;
   const int64_t E = c->E;
@@ -73,18 +76,32 @@ gabp_status apply_colour_order(Ctx* c) {
     ncol = std::max(ncol, k + 1);
   }
 
-  // classes as contiguous ranges, caller order inside a class
+  // classes as contiguous ranges inside each system, caller order inside a
+  // class; cls_row lists every system's class starts (global rows) followed
+  // by its end, cls_base[s] where system s's list begins
   c->ncol = ncol;
-  c->colour_start.assign(ncol + 1, 0);
-  for (int32_t i = 0; i < n; ++i) ++c->colour_start[colour[i] + 1];
-  std::partial_sum(c->colour_start.begin(), c->colour_start.end(), c->colour_start.begin());
+  const int32_t S = sys_row_off ? num_sys : 1;
+  c->cls_base.assign(S + 1, 0);
+  c->cls_row.clear();
   std::vector<int32_t> perm_inv(2 * (size_t)n);  // [perm | inv]
-  std::vector<int32_t> next(c->colour_start.begin(), c->colour_start.end() - 1);
-  for (int32_t i = 0; i < n; ++i) {
-    const int32_t p = next[colour[i]]++;
-    perm_inv[i] = p;
-    perm_inv[n + p] = i;
+  for (int32_t q = 0; q < S; ++q) {
+    const int32_t r0 = sys_row_off ? sys_row_off[q] : 0, r1 = sys_row_off ? sys_row_off[q + 1] : n;
+    int32_t nc = r1 > r0 ? 1 : 0;
+    for (int32_t i = r0; i < r1; ++i) nc = std::max(nc, colour[i] + 1);
+    std::vector<int32_t> start(nc + 1, 0);
+    for (int32_t i = r0; i < r1; ++i) ++start[colour[i] + 1];
+    std::partial_sum(start.begin(), start.end(), start.begin());
+    c->cls_base[q] = (int32_t)c->cls_row.size();
+    for (int32_t k = 0; k <= nc; ++k) c->cls_row.push_back(r0 + start[k]);
+    std::vector<int32_t> next(start.begin(), start.end() - 1);
+    for (int32_t i = r0; i < r1; ++i) {
+      const int32_t p = r0 + next[colour[i]]++;
+      perm_inv[i] = p;
+      perm_inv[n + p] = i;
+    }
   }
+  c->cls_base[S] = (int32_t)c->cls_row.size();
+  if (!sys_row_off) c->colour_start = c->cls_row;
   std::vector<int32_t> new_ptr((size_t)n + 1, 0);
   for (int32_t p = 0; p < n; ++p) {
     const int32_t r = perm_inv[n + p];

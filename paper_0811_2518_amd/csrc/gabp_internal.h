@@ -244,6 +244,8 @@ struct Ctx {
   // contiguous range; the caller's order is restored at the C ABI
   int32_t ncol = 0;
   std::vector<int32_t> colour_start;  // [ncol+1] first row of each class
+  std::vector<int32_t> cls_row;       // per system: first row of each class, then the system's end
+  std::vector<int32_t> cls_base;      // [systems + 1] start of each system's list in cls_row
   std::vector<int32_t> colour_blk;    // [ncol+1] first workgroup of each class
   std::vector<int32_t> colour_h;      // [n] colour of each caller row
   int32_t* perm_d = nullptr;          // [n] caller row -> internal row, then [n] internal -> caller
@@ -278,7 +280,7 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row);
 gabp_status set_partition(Ctx* c, int K);
 // colour.hip: first-fit colouring in row order and the colour-ordered
 // renumbering of the off-diagonal CSR (colour-serial layout)
-gabp_status apply_colour_order(Ctx* c);
+gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys);  // host offsets, nullable
 
 // ---- kernels (sweep.hip) ---------------------------------------------------
 template <typename T>

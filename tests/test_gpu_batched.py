@@ -126,3 +126,79 @@ def test_batched_groups_not_dividing_the_workgroup():
     # the FP32 inner solves to 1e-5 make each outer step gain ~5 digits
     assert max(i["outer_iters"] for i in infos) <= 6
     assert all(i["converged"] == 1 for i in infos)
+
+
+# ---------------------------------------------------------------------------
+# colour-serial schedule inside each work item (serial scheduling, Ch. 2
+# Sec. 2.3): same solutions, fewer sweeps
+# ---------------------------------------------------------------------------
+
+def _check_against_dense(bt, X, infos, every=1):
+    Xh = X.cpu().numpy()
+    for q in range(0, bt.num_sys, every):
+        p = bt.system(q)
+        info = infos[q]
+        assert info["converged"] == 1 and info["rel_residual"] <= TOL, (q, info)
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        for j in range(k):
+            _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, xs[:, j], p.b[:, j])
+            assert rr <= 1.05 * TOL, (q, j, rr)
+        ref = oracle.dense_solve(p.dense(), p.b)
+        assert np.linalg.norm(xs - ref) / np.linalg.norm(ref) <= 1e-8, q
+
+
+def test_batched_serial_matches_per_system_references_in_fewer_sweeps(small_batch):
+    bt = small_batch
+    s, B, X, infos, st = _solve(bt, layout="serial")
+    assert st == binding.OK
+    _check_against_dense(bt, X, infos)
+    ps = s.profile()
+    s0, B0, X0, infos0, st0 = _solve(bt)
+    p0 = s0.profile()
+    assert ps["inner_sweeps"] < 0.8 * p0["inner_sweeps"], (ps["inner_sweeps"], p0["inner_sweeps"])
+    assert ps["precision_sweeps"] < p0["precision_sweeps"]
+
+
+def test_batched_serial_colours_are_the_oracles(small_batch):
+    bt = small_batch
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV, layout="serial")
+    col, k = s.colours()
+    ref = oracle.greedy_colouring(int(bt.sys_row_off[-1]), bt.row_ptr, bt.col)
+    np.testing.assert_array_equal(col, ref)
+    assert k == int(ref.max()) + 1
+
+
+def test_batched_serial_odd_systems_and_replay():
+    # long rows (a star larger than a tile's chunk), a tree, isolated nodes,
+    # a one-node system and an uneven grid, with 1..9 right-hand sides
+    probs = [workloads.star_problem(3000, 1), workloads.random_tree(500, 2),
+             workloads.er_problem(700, 2, 3, ratio=1.3), workloads.from_dense(np.array([[3.0]]), np.ones(1)),
+             workloads.grid2d_problem(13, 7, 4), workloads.er_problem(2000, 10, 5, ratio=1.05)]
+    bt = workloads.batch_of(probs, [3, 9, 1, 2, 5, 8], seed=21)
+    s, B, X, infos, st = _solve(bt, layout="serial")
+    assert st == binding.OK
+    _check_against_dense(bt, X, infos)
+    x1 = X.cpu().numpy().copy()
+    X2, infos2, st2 = s.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=20000, X=X)
+    np.testing.assert_array_equal(X2.cpu().numpy(), x1)
+    assert [i["sweeps"] for i in infos2] == [i["sweeps"] for i in infos]
+
+
+def test_batched_serial_groups_not_dividing_the_workgroup():
+    rng = np.random.default_rng(13)
+    probs, ks = [], []
+    for q in range(400):
+        probs.append(workloads.grid2d_problem(int(rng.integers(8, 13)), int(rng.integers(8, 13)), 7000 + q,
+                                              ratio=1.3))
+        ks.append(int(rng.choice([3, 5, 6, 7])))
+    bt = workloads.batch_of(probs, ks, seed=14)
+    s, B, X, infos, st = _solve(bt, layout="serial")
+    assert st == binding.OK
+    _check_against_dense(bt, X, infos, every=9)
+
+
+def test_batched_rejects_other_layouts(small_batch):
+    bt = small_batch
+    with pytest.raises(binding.GabpError):
+        g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV, layout="compact")

@@ -58,6 +58,26 @@ def test_full_batch_every_system_converges_and_samples_match_dense(batch_full):
         assert np.linalg.norm(xs - ref) / np.linalg.norm(ref) <= 1e-8, q
 
 
+def test_full_batch_serial_schedule_converges_with_independent_residuals(batch_full):
+    bt = batch_full
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV, layout="serial")
+    B = torch.from_numpy(bt.B).to(DEV)
+    X, infos, st = s.solve(bt.nrhs, bt.rhs_off, B, tol=1e-10, max_iter=100000)
+    assert st == binding.OK
+    assert all(i["converged"] == 1 and i["rel_residual"] <= 1e-10 for i in infos)
+    Xh = X.cpu().numpy()
+    del X, B
+    s.close()
+    worst = 0.0
+    for q in range(bt.num_sys):
+        p = bt.system(q)
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        r = np.linalg.norm(p.b - p.scipy() @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
+        worst = max(worst, float(r.max()))
+    assert worst <= 1.05e-10, worst
+
+
 def test_full_grid3d_adjoint_residuals_and_sampled_gradient():
     p = workloads.config4()
     t = p.extra["target"]
