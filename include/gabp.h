@@ -228,7 +228,10 @@ gabp_status gabp_backward(gabp_handle h, const double *x, const double *grad_x,
  *   row_ptr, col_idx, vals   device CSR of the block-diagonal matrix of all
  *                systems with GLOBAL column indices; an entry outside its
  *                system's block is GABP_E_ARG
- *   opts, stream, out        as gabp_create (precision must be FP32_REFINE)
+ *   opts, stream, out        as gabp_create (precision must be FP32_REFINE;
+ *                layout 0 = synchronous sweeps, 4 = colour-serial sweeps inside
+ *                each system, colours by first fit in global row order as for
+ *                gabp_get_colours; other layouts are GABP_E_ARG)
  */
 gabp_status gabp_create_batched(int32_t num_sys, const int32_t *sys_row_off,
                                 const int32_t *row_ptr, const int32_t *col_idx,
@@ -281,6 +284,8 @@ gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile *out);
  *                row i takes the smallest colour held by none of its stored
  *                neighbours j < i, so no two neighbours share a colour.
  *   num_colours  HOST (output, nullable): number of classes
+ * Batched layout-4 handles: the colour of every global row (each system is
+ * coloured on its own) and the largest number of classes of a system.
  * GABP_E_ARG for other handles.
  */
 gabp_status gabp_get_colours(gabp_handle h, int32_t *colour, int32_t *num_colours);
