@@ -109,6 +109,15 @@ typedef struct {
  * The handle uses the compact layout. */
 #define GABP_FLAG_SINGLE_LOOP 4
 
+/* Keep the caller's row order.  Without the flag, gabp_create of layouts 0-3
+ * may renumber the rows internally (the caller never sees it) into 8 parts of
+ * equal work.  The parts are grown breadth-first and refined by label
+ * propagation, and part x is swept by the workgroups of XCD x, so that more
+ * neighbour gathers hit that XCD's L2.  This is done only when the parts keep
+ * clearly more edges inside than the caller's order does.  The iteration and
+ * the results are unchanged up to the summation order of the residual norm. */
+#define GABP_FLAG_NATURAL_ORDER 8
+
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
   int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */
@@ -129,7 +138,8 @@ typedef struct {
   int32_t layout;           /* 1 = reverse-slot index, 2 = node broadcast,*/
                             /* 3 = compact node broadcast, 4 = colour-    */
                             /* serial                                     */
-  int32_t pad;
+  int32_t xcd_parts;        /* 8 if the rows were renumbered into XCD     */
+                            /* parts (GABP_FLAG_NATURAL_ORDER), else 0    */
   int32_t num_blocks;       /* workgroups per sweep launch                */
   int32_t max_degree;       /* largest off-diagonal row length            */
   int32_t precision;        /* gabp_precision                             */

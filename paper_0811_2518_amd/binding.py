@@ -25,6 +25,7 @@ FP64, FP32_REFINE = 0, 1
 FLAG_REUSE_PRECISION = 1
 FLAG_TIME_SWEEPS = 2
 FLAG_SINGLE_LOOP = 4
+FLAG_NATURAL_ORDER = 8
 LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 
 # every entry point declared in include/gabp.h
@@ -52,7 +53,7 @@ class Info(ctypes.Structure):
 
 class Props(ctypes.Structure):
     _fields_ = [("n", c_i64), ("num_offdiag", c_i64), ("edges_per_block", c_i32), ("layout", c_i32),
-                ("pad", c_i32), ("num_blocks", c_i32), ("max_degree", c_i32), ("precision", c_i32),
+                ("xcd_parts", c_i32), ("num_blocks", c_i32), ("max_degree", c_i32), ("precision", c_i32),
                 ("device_bytes", c_i64), ("rho_lo", c_f64), ("rho_hi", c_f64), ("gamma", c_f64)]
 
 
@@ -156,7 +157,7 @@ class Solver:
     def __init__(self, row_ptr, col, val, *, precision="fp64", check_every=1, edges_per_block=0,
                  gamma=0.0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
                  reuse_precision=True, time_sweeps=False, layout="auto", single_loop=False, damping=0.5,
-                 device="cuda", stream=None):
+                 natural_order=False, device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
         self.stream, sh = _stream_handle(stream)
@@ -171,7 +172,7 @@ class Solver:
             max_outer=max_outer, layout=LAYOUTS[layout],
             damping=damping,
             flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0)
-            | (FLAG_SINGLE_LOOP if single_loop else 0))
+            | (FLAG_SINGLE_LOOP if single_loop else 0) | (FLAG_NATURAL_ORDER if natural_order else 0))
         h = ctypes.c_void_p()
         st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
                                ctypes.byref(self.opts), sh, ctypes.byref(h))

@@ -77,6 +77,8 @@ gabp_status alloc_solver(Ctx* c) {
     TRY(dev_alloc(c, &c->agg_d[0], 2 * elt * n));
     TRY(dev_alloc(c, &c->bstate_d, 2 * elt * E));
     TRY(dev_alloc(c, (void**)&c->lsum_d, sizeof(double) * n));
+  }
+  if (c->perm_d) {  // rows renumbered: b, x and the variances in internal order
     TRY(dev_alloc(c, (void**)&c->bperm_d, sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->xperm_d, sizeof(double) * n));
     TRY(dev_alloc(c, (void**)&c->vperm_d, sizeof(double) * n));
@@ -179,6 +181,7 @@ gabp_status gabp_create(int32_t n, const int32_t* row_ptr, const int32_t* col_id
   if (r == GABP_OK) r = common_setup(c);
   if (r == GABP_OK && n > 0) r = ingest(c, row_ptr, col_idx, vals, nullptr, 0);
   if (r == GABP_OK && n > 0 && c->opts.layout == kLayoutSerial) r = apply_colour_order(c, nullptr, 0);
+  else if (r == GABP_OK && n > 0 && !(c->opts.flags & GABP_FLAG_NATURAL_ORDER)) r = apply_xcd_order(c);
   if (r == GABP_OK && n > 0) r = alloc_solver(c);
   if (r == GABP_OK && n > 0) r = autotune(c);
   if (r == GABP_OK && n > 0) release_unused_layout(c);
@@ -211,8 +214,10 @@ gabp_status gabp_solve(gabp_handle h, const double* b, double* x, double* var, d
   if (var && !plain_mode(c)) return fail(c, GABP_E_ARG, "variances are only available in plain FP64 mode");
   if (!plain_mode(c) && !(single_loop_mode(c) && c->opts.precision == GABP_FP64) && !(tol > 0.0))
     return fail(c, GABP_E_ARG, "the correction loop needs tol > 0");
-  // colour-ordered handles solve in their internal numbering
+  // renumbered handles solve in their internal numbering
   const bool perm = c->perm_d != nullptr;
+  if (perm && !(c->bperm_d && c->xperm_d && c->vperm_d))
+    return fail(c, GABP_E_ARG, "internal order buffers missing");
   if (perm) GABP_HIP(c, launch_gather(b, c->inv_d, c->bperm_d, c->n, c->stream));
   const double* bi = perm ? c->bperm_d : b;
   double* xi = perm ? c->xperm_d : x;
@@ -238,6 +243,13 @@ gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
     return fail(c, GABP_E_ARG, "no FP64 messages from a fixed-sweep solve (tol <= 0) are held");
   if (c->E == 0) return GABP_OK;
   if (!P || !hm) return fail(c, GABP_E_ARG, "NULL output");
+  double* Pc = P;  // caller's outputs
+  double* hc = hm;
+  if (c->slot_of_d) {  // rows renumbered: messages in internal slot order first
+    if (!c->msg_tmp_d) TRY(dev_alloc(c, (void**)&c->msg_tmp_d, 2 * sizeof(double) * (size_t)c->E));
+    P = c->msg_tmp_d;
+    hm = c->msg_tmp_d + c->E;
+  }
   if (c->last_msg_round == 0) {  // round 0: every message is zero (initial state of Alg. 2)
     GABP_HIP(c, launch_fill(P, c->E, 0.0, c->stream));
     GABP_HIP(c, launch_fill(hm, c->E, 0.0, c->stream));
@@ -251,6 +263,10 @@ gabp_status gabp_messages(gabp_handle h, double* P, double* hm) {
     GABP_HIP(c, launch_split_out(c->bstate_d, P, hm, c->E, c->stream));
   } else {
     GABP_HIP(c, launch_split_pairs(c->msg_d[c->last_msg_round & 1], P, hm, c->E, c->stream));
+  }
+  if (c->slot_of_d) {
+    GABP_HIP(c, launch_scatter_slots(P, c->slot_of_d, Pc, c->E, c->stream));
+    GABP_HIP(c, launch_scatter_slots(hm, c->slot_of_d, hc, c->E, c->stream));
   }
   GABP_HIP(c, hipStreamSynchronize(c->stream));
   return GABP_OK;
@@ -267,6 +283,7 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
   if (!x || !grad_x || !grad_b) return fail(c, GABP_E_ARG, "NULL x, grad_x or grad_b");
   // A is symmetric: the adjoint system A^T lambda = dL/dx is a second GaBP solve against A
   const bool perm = c->perm_d != nullptr;
+  if (perm && !(c->bperm_d && c->xperm_d)) return fail(c, GABP_E_ARG, "internal order buffers missing");
   if (perm) GABP_HIP(c, launch_gather(grad_x, c->inv_d, c->bperm_d, c->n, c->stream));
   const double* gi = perm ? c->bperm_d : grad_x;
   double* li = perm ? c->xperm_d : grad_b;
@@ -366,7 +383,7 @@ gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
   p->edges_per_block = c->K * kBlock;
   p->num_blocks = c->nblk;
   p->layout = c->layout;
-  p->pad = 0;
+  p->xcd_parts = c->nparts;
   p->rho_lo = c->rho_lo;
   p->rho_hi = c->rho_hi;
   p->gamma = c->gamma_used;

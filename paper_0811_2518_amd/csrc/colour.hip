@@ -29,13 +29,15 @@ namespace {
   } while (0)
 
 // One lane per new row p: copy the slots of caller row inv[p], with the
-// columns renumbered (the slot order inside the row is kept).
+// columns renumbered (the slot order inside the row is kept), and record the
+// caller's slot of every new slot (nullable).
 __global__ void k_permute_rows(int32_t n, const int32_t* __restrict__ inv, const int32_t* __restrict__ perm,
                                const int32_t* __restrict__ old_ptr, const int32_t* __restrict__ old_col,
                                const double* __restrict__ old_a64, const float* __restrict__ old_a32,
                                const double* __restrict__ old_d64, const int32_t* __restrict__ new_ptr,
                                int32_t* __restrict__ new_col, double* __restrict__ new_a64,
-                               float* __restrict__ new_a32, double* __restrict__ new_d64) {
+                               float* __restrict__ new_a32, double* __restrict__ new_d64,
+                               int32_t* __restrict__ slot_of) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
     const int32_t r = inv[p];
     int32_t k = new_ptr[p];
@@ -43,12 +45,89 @@ __global__ void k_permute_rows(int32_t n, const int32_t* __restrict__ inv, const
       new_col[k] = perm[old_col[s]];
       new_a64[k] = old_a64[s];
       new_a32[k] = old_a32[s];
+      if (slot_of) slot_of[k] = s;
     }
     new_d64[p] = old_d64[r];
   }
 }
 
+// old2new[slot_of[k]] = k
+__global__ void k_invert_slots(int64_t E, const int32_t* __restrict__ slot_of, int32_t* __restrict__ old2new) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < E; k += (int64_t)gridDim.x * blockDim.x)
+    old2new[slot_of[k]] = (int32_t)k;
+}
+
+// reverse-slot index in the new numbering
+__global__ void k_remap_rev(int64_t E, const int32_t* __restrict__ slot_of, const int32_t* __restrict__ old2new,
+                            const int32_t* __restrict__ old_rev, int32_t* __restrict__ new_rev) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < E; k += (int64_t)gridDim.x * blockDim.x)
+    new_rev[k] = old2new[old_rev[slot_of[k]]];
+}
+
 }  // namespace
+
+gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep_slots) {
+  hipStream_t s = c->stream;
+  const int32_t n = c->n;
+  const int64_t E = c->E;
+  const std::vector<int32_t>& op = c->off_ptr_h;
+  std::vector<int32_t> new_ptr((size_t)n + 1, 0);
+  for (int32_t p = 0; p < n; ++p) {
+    const int32_t r = perm_inv[n + p];
+    new_ptr[p + 1] = new_ptr[p] + (op[r + 1] - op[r]);
+  }
+  void* pi = nullptr;
+  GABP_TRY_STATUS(dev_alloc(c, &pi, sizeof(int32_t) * 2 * (size_t)n));
+  c->perm_d = (int32_t*)pi;
+  c->inv_d = c->perm_d + n;
+  int32_t* nptr_d = nullptr;
+  int32_t* ncol_d = nullptr;
+  double* na64_d = nullptr;
+  float* na32_d = nullptr;
+  double* nd64_d = nullptr;
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&nptr_d, sizeof(int32_t) * ((size_t)n + 1)));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&ncol_d, sizeof(int32_t) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&na64_d, sizeof(double) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&na32_d, sizeof(float) * (size_t)E));
+  GABP_TRY_STATUS(dev_alloc(c, (void**)&nd64_d, sizeof(double) * (size_t)n));
+  if (keep_slots) GABP_TRY_STATUS(dev_alloc(c, (void**)&c->slot_of_d, sizeof(int32_t) * (size_t)E));
+  GABP_HIP(c, hipMemcpyAsync(c->perm_d, perm_inv.data(), sizeof(int32_t) * 2 * (size_t)n, hipMemcpyHostToDevice, s));
+  GABP_HIP(c, hipMemcpyAsync(nptr_d, new_ptr.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_permute_rows, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n, c->inv_d,
+                       c->perm_d, c->off_ptr_d, c->off_col_d, c->a64_d, c->a32_d, c->d64_d, nptr_d, ncol_d, na64_d,
+                       na32_d, nd64_d, c->slot_of_d);
+    GABP_HIP(c, hipGetLastError());
+  }
+  int32_t* nrev_d = nullptr;
+  if (keep_slots && E > 0) {  // the reverse-slot index follows the slots
+    int32_t* old2new_d = nullptr;
+    GABP_TRY_STATUS(dev_alloc(c, (void**)&old2new_d, sizeof(int32_t) * (size_t)E));
+    GABP_TRY_STATUS(dev_alloc(c, (void**)&nrev_d, sizeof(int32_t) * (size_t)E));
+    const int blocks = (int)std::min<int64_t>((E + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_invert_slots, dim3(blocks), dim3(256), 0, s, E, c->slot_of_d, old2new_d);
+    GABP_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_remap_rev, dim3(blocks), dim3(256), 0, s, E, c->slot_of_d, old2new_d, c->rev_d, nrev_d);
+    GABP_HIP(c, hipGetLastError());
+    GABP_HIP(c, hipStreamSynchronize(s));
+    dev_free(c, old2new_d);
+  }
+  GABP_HIP(c, hipStreamSynchronize(s));
+  dev_free(c, c->off_ptr_d);
+  dev_free(c, c->off_col_d);
+  dev_free(c, c->a64_d);
+  dev_free(c, c->a32_d);
+  dev_free(c, c->d64_d);
+  dev_free(c, c->rev_d);
+  c->rev_d = nrev_d;
+  c->off_ptr_d = nptr_d;
+  c->off_col_d = ncol_d;
+  c->a64_d = na64_d;
+  c->a32_d = na32_d;
+  c->d64_d = nd64_d;
+  c->off_ptr_h = std::move(new_ptr);
+  return GABP_OK;
+}
 
 gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys) {
   hipStream_t s = c->stream;
@@ -102,49 +181,7 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
   }
   c->cls_base[S] = (int32_t)c->cls_row.size();
   if (!sys_row_off) c->colour_start = c->cls_row;
-  std::vector<int32_t> new_ptr((size_t)n + 1, 0);
-  for (int32_t p = 0; p < n; ++p) {
-    const int32_t r = perm_inv[n + p];
-    new_ptr[p + 1] = new_ptr[p] + (op[r + 1] - op[r]);
-  }
-
-  void* pi = nullptr;
-  GABP_TRY_STATUS(dev_alloc(c, &pi, sizeof(int32_t) * 2 * (size_t)n));
-  c->perm_d = (int32_t*)pi;
-  c->inv_d = c->perm_d + n;
-  int32_t* nptr_d = nullptr;
-  int32_t* ncol_d = nullptr;
-  double* na64_d = nullptr;
-  float* na32_d = nullptr;
-  double* nd64_d = nullptr;
-  GABP_TRY_STATUS(dev_alloc(c, (void**)&nptr_d, sizeof(int32_t) * ((size_t)n + 1)));
-  GABP_TRY_STATUS(dev_alloc(c, (void**)&ncol_d, sizeof(int32_t) * (size_t)E));
-  GABP_TRY_STATUS(dev_alloc(c, (void**)&na64_d, sizeof(double) * (size_t)E));
-  GABP_TRY_STATUS(dev_alloc(c, (void**)&na32_d, sizeof(float) * (size_t)E));
-  GABP_TRY_STATUS(dev_alloc(c, (void**)&nd64_d, sizeof(double) * (size_t)n));
-  GABP_HIP(c, hipMemcpyAsync(c->perm_d, perm_inv.data(), sizeof(int32_t) * 2 * (size_t)n, hipMemcpyHostToDevice, s));
-  GABP_HIP(c, hipMemcpyAsync(nptr_d, new_ptr.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
-  if (n > 0) {
-    hipLaunchKernelGGL(k_permute_rows, dim3(std::min((n + 255) / 256, 4096)), dim3(256), 0, s, n, c->inv_d,
-                       c->perm_d, c->off_ptr_d, c->off_col_d, c->a64_d, c->a32_d, c->d64_d, nptr_d, ncol_d, na64_d,
-                       na32_d, nd64_d);
-    GABP_HIP(c, hipGetLastError());
-  }
-  GABP_HIP(c, hipStreamSynchronize(s));
-  dev_free(c, c->off_ptr_d);
-  dev_free(c, c->off_col_d);
-  dev_free(c, c->a64_d);
-  dev_free(c, c->a32_d);
-  dev_free(c, c->d64_d);
-  dev_free(c, c->rev_d);  // the serial sweeps pull through aggregates only
-  c->rev_d = nullptr;
-  c->off_ptr_d = nptr_d;
-  c->off_col_d = ncol_d;
-  c->a64_d = na64_d;
-  c->a32_d = na32_d;
-  c->d64_d = nd64_d;
-  c->off_ptr_h = std::move(new_ptr);
-  return GABP_OK;
+  return permute_rows(c, perm_inv, false);  // the serial sweeps pull through aggregates only
 }
 
 }  // namespace gabp

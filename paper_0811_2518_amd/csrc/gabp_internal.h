@@ -248,6 +248,10 @@ struct Ctx {
   std::vector<int32_t> cls_base;      // [systems + 1] start of each system's list in cls_row
   std::vector<int32_t> colour_blk;    // [ncol+1] first workgroup of each class
   std::vector<int32_t> colour_h;      // [n] colour of each caller row
+  int32_t* slot_of_d = nullptr;       // [E] caller slot of each internal slot (XCD order only)
+  double* msg_tmp_d = nullptr;        // [2E] exported messages in internal slot order (XCD order only)
+  int32_t nparts = 0;                 // XCD order: parts (row ranges part_start[p] .. part_start[p+1])
+  std::vector<int32_t> part_start;
   int32_t* perm_d = nullptr;          // [n] caller row -> internal row, then [n] internal -> caller
   int32_t* inv_d = nullptr;
   double* bperm_d = nullptr;          // right-hand side, x and variances in internal order
@@ -281,6 +285,12 @@ gabp_status set_partition(Ctx* c, int K);
 // colour.hip: first-fit colouring in row order and the colour-ordered
 // renumbering of the off-diagonal CSR (colour-serial layout)
 gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys);  // host offsets, nullable
+// renumber the rows of the off-diagonal CSR: perm_inv = [perm | inv] (caller row
+// -> internal row, internal -> caller); keep_slots keeps the caller slot of every
+// internal slot and the reverse-slot index
+gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep_slots);
+// partition.hip: XCD-aware row order (8 slot-balanced parts, part x on XCD x)
+gabp_status apply_xcd_order(Ctx* c);
 
 // ---- kernels (sweep.hip) ---------------------------------------------------
 template <typename T>
@@ -349,6 +359,7 @@ template <typename T>
 hipError_t launch_serial_prior_x(int32_t n, const T* diag, const T* rhs, T* x, T* pt, hipStream_t s);
 size_t serial_lds_bytes(int K, int elt);
 hipError_t launch_gather(const double* src, const int32_t* idx, double* dst, int32_t n, hipStream_t s);
+hipError_t launch_scatter_slots(const double* src, const int32_t* idx, double* dst, int64_t E, hipStream_t s);
 size_t bcast_state_bytes(int elt);
 size_t bcast_coef_bytes(int elt);
 size_t bcast_lds_bytes(int K, int elt);

@@ -234,8 +234,8 @@ gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const dou
 
 // Greedy packing of whole rows into workgroups of at most 256*K slots and 256
 // rows; a row longer than 256*K gets a workgroup of its own (handled by the
-// sweep kernel's long-row path).  With colour classes, no workgroup spans two
-// classes.
+// sweep kernel's long-row path).  With colour classes or XCD parts, no
+// workgroup spans two of them.
 gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
   const int64_t cap = (int64_t)kBlock * K;
   blk_row.clear();
@@ -243,12 +243,13 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
   int64_t slots = 0;
   int32_t rows = 0;
   const auto& op = c->off_ptr_h;
-  size_t next_class = 1;  // index into colour_start of the next class boundary
+  const std::vector<int32_t>& breaks = c->nparts > 0 ? c->part_start : c->colour_start;
+  size_t next_class = 1;  // index into breaks of the next boundary
   for (int32_t r = 0; r < c->n; ++r) {
     const int64_t d = op[r + 1] - op[r];
     bool boundary = false;
-    while (next_class < c->colour_start.size() && c->colour_start[next_class] <= r) {
-      boundary = boundary || c->colour_start[next_class] == r;
+    while (next_class < breaks.size() && breaks[next_class] <= r) {
+      boundary = boundary || breaks[next_class] == r;
       ++next_class;
     }
     if (rows > 0 && (boundary || slots + d > cap || rows == kMaxRowsPerBlock)) {
@@ -271,6 +272,26 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
 gabp_status set_partition(Ctx* c, int K) {
   std::vector<int32_t> br;
   build_partition(c, K, br);
+  if (c->nparts > 0) {
+    // XCD parts: every part gets the same number of workgroups (the short ones
+    // padded with empty workgroups at the part's end), so that the XCD-aware
+    // workgroup map sends part x to XCD x
+    std::vector<int32_t> cnt(c->nparts, 0);
+    for (size_t i = 0; i + 1 < br.size(); ++i) {
+      const int p = (int)(std::upper_bound(c->part_start.begin(), c->part_start.end(), br[i]) -
+                          c->part_start.begin()) - 1;
+      ++cnt[p];
+    }
+    const int32_t q = *std::max_element(cnt.begin(), cnt.end());
+    std::vector<int32_t> padded;
+    size_t i = 0;
+    for (int p = 0; p < c->nparts; ++p) {
+      for (int32_t k = 0; k < cnt[p]; ++k) padded.push_back(br[i++]);
+      for (int32_t k = cnt[p]; k < q; ++k) padded.push_back(c->part_start[p + 1]);
+    }
+    padded.push_back(c->n);
+    br.swap(padded);
+  }
   const int32_t nb = (int32_t)br.size() - 1;
   // first rows, then first slots, of the workgroups: [2 (nb + 1)]
   for (int32_t i = 0; i <= nb; ++i) br.push_back(c->off_ptr_h[br[i]]);

@@ -321,6 +321,12 @@ __global__ void k_gather(const double* __restrict__ src, const int32_t* __restri
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[idx[i]];
 }
 
+__global__ void k_scatter_slots(const double* __restrict__ src, const int32_t* __restrict__ idx,
+                                double* __restrict__ dst, int64_t E) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x)
+    dst[idx[i]] = src[i];
+}
+
 template <typename T, int K>
 hipError_t launch_sk(const SerialArgs<T>& a, bool resid, hipStream_t s) {
   const uint32_t lds = (uint32_t)sr_lds(K, sizeof(T));
@@ -356,6 +362,13 @@ hipError_t launch_serial_prior_x(int32_t n, const T* diag, const T* rhs, T* x, T
 template hipError_t launch_serial_prior_x<double>(int32_t, const double*, const double*, double*, double*,
                                                   hipStream_t);
 template hipError_t launch_serial_prior_x<float>(int32_t, const float*, const float*, float*, float*, hipStream_t);
+
+hipError_t launch_scatter_slots(const double* src, const int32_t* idx, double* dst, int64_t E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_slots, dim3((unsigned)std::min<int64_t>((E + 255) / 256, 8192)), dim3(256), 0, s, src,
+                     idx, dst, E);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather(const double* src, const int32_t* idx, double* dst, int32_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -491,3 +491,48 @@ def test_automatic_loading_is_zero_for_walk_summable():
     assert pr["rho_hi"] < 1.0 and pr["gamma"] == 0.0
     x, info = s.solve(dev(p.b), tol=TOL, max_iter=5000)
     assert info["converged"] == 1 and info["gamma"] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# XCD-aware row order: an internal renumbering that changes no result
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_xcd_order_changes_no_result(layout):
+    p = workloads.er_problem(20000, 8, 93)
+    s = solver(p, layout=layout, edges_per_block=512)
+    s0 = solver(p, layout=layout, edges_per_block=512, natural_order=True)
+    assert s.props()["xcd_parts"] == 8 and s0.props()["xcd_parts"] == 0
+    for T in (0, 1, 3, 10):
+        x, _, v = s.solve(dev(p.b), tol=0, max_iter=T, var=True)
+        x0, _, v0 = s0.solve(dev(p.b), tol=0, max_iter=T, var=True)
+        np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+        np.testing.assert_array_equal(v.cpu().numpy(), v0.cpu().numpy())
+        P, hm = s.messages()
+        P0, hm0 = s0.messages()
+        np.testing.assert_array_equal(P.cpu().numpy(), P0.cpu().numpy())
+        np.testing.assert_array_equal(hm.cpu().numpy(), hm0.cpu().numpy())
+    x, i = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+    x0, i0 = s0.solve(dev(p.b), tol=TOL, max_iter=2000)
+    assert i["sweeps"] == i0["sweeps"]
+    np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000)
+    assert i["sweeps"] == ref["sweeps"] and rel(x, ref["x"]) <= TOL
+    gb, gv, _ = s.backward(x, x, tol=1e-12)
+    gb0, gv0, _ = s0.backward(x0, x0, tol=1e-12)
+    np.testing.assert_array_equal(gb.cpu().numpy(), gb0.cpu().numpy())
+    np.testing.assert_array_equal(gv.cpu().numpy(), gv0.cpu().numpy())
+
+
+def test_xcd_order_fp32_refinement_and_grids():
+    p = workloads.er_problem(30000, 8, 94)
+    s = solver(p, precision="fp32", layout="compact", edges_per_block=512)
+    s0 = solver(p, precision="fp32", layout="compact", edges_per_block=512, natural_order=True)
+    assert s.props()["xcd_parts"] == 8
+    x, i = s.solve(dev(p.b), tol=TOL, max_iter=5000)
+    x0, i0 = s0.solve(dev(p.b), tol=TOL, max_iter=5000)
+    assert i["converged"] == 1 and i0["converged"] == 1
+    np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+    # a naturally ordered grid already keeps its edges inside 8 row ranges
+    q = workloads.grid3d_problem(24, 95)
+    assert solver(q).props()["xcd_parts"] == 0
