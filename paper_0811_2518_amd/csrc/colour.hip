@@ -155,9 +155,15 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
     ncol = std::max(ncol, k + 1);
   }
 
+  // a single system may also split every class by XCD part (the order inside
+  // a class does not change the iteration)
+  std::vector<int32_t> part;
+  const bool parts = !sys_row_off && !(c->opts.flags & GABP_FLAG_NATURAL_ORDER) && xcd_parts(c, col, part);
+
   // classes as contiguous ranges inside each system, caller order inside a
-  // class; cls_row lists every system's class starts (global rows) followed
-  // by its end, cls_base[s] where system s's list begins
+  // class (inside a class's part with XCD parts); cls_row lists every
+  // system's class starts (global rows) followed by its end, cls_base[s]
+  // where system s's list begins
   c->ncol = ncol;
   const int32_t S = sys_row_off ? num_sys : 1;
   c->cls_base.assign(S + 1, 0);
@@ -172,6 +178,22 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
     std::partial_sum(start.begin(), start.end(), start.begin());
     c->cls_base[q] = (int32_t)c->cls_row.size();
     for (int32_t k = 0; k <= nc; ++k) c->cls_row.push_back(r0 + start[k]);
+    if (parts) {  // (class, part) sub-ranges, 8 per class
+      const int np = 8;
+      std::vector<int32_t> sub((size_t)nc * np + 1, 0);
+      for (int32_t i = r0; i < r1; ++i) ++sub[(size_t)colour[i] * np + part[i] + 1];
+      std::partial_sum(sub.begin(), sub.end(), sub.begin());
+      c->nparts = np;
+      c->part_start.assign(sub.size(), 0);
+      for (size_t k = 0; k < sub.size(); ++k) c->part_start[k] = r0 + sub[k];
+      std::vector<int32_t> next(sub.begin(), sub.end() - 1);
+      for (int32_t i = r0; i < r1; ++i) {
+        const int32_t p = r0 + next[(size_t)colour[i] * np + part[i]]++;
+        perm_inv[i] = p;
+        perm_inv[n + p] = i;
+      }
+      continue;
+    }
     std::vector<int32_t> next(start.begin(), start.end() - 1);
     for (int32_t i = r0; i < r1; ++i) {
       const int32_t p = r0 + next[colour[i]]++;

@@ -250,8 +250,9 @@ struct Ctx {
   std::vector<int32_t> colour_h;      // [n] colour of each caller row
   int32_t* slot_of_d = nullptr;       // [E] caller slot of each internal slot (XCD order only)
   double* msg_tmp_d = nullptr;        // [2E] exported messages in internal slot order (XCD order only)
-  int32_t nparts = 0;                 // XCD order: parts (row ranges part_start[p] .. part_start[p+1])
-  std::vector<int32_t> part_start;
+  int32_t nparts = 0;                 // XCD order: parts per group (8), else 0
+  std::vector<int32_t> part_start;    // XCD order: first row of every part of every group, then n
+                                      // (one group; colour-serial: one group per colour class)
   int32_t* perm_d = nullptr;          // [n] caller row -> internal row, then [n] internal -> caller
   int32_t* inv_d = nullptr;
   double* bperm_d = nullptr;          // right-hand side, x and variances in internal order
@@ -289,7 +290,9 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
 // -> internal row, internal -> caller); keep_slots keeps the caller slot of every
 // internal slot and the reverse-slot index
 gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep_slots);
-// partition.hip: XCD-aware row order (8 slot-balanced parts, part x on XCD x)
+// partition.hip: XCD-aware row order (8 slot-balanced parts, part x on XCD x).
+// xcd_parts fills part[caller row] and says whether the parts pay off.
+bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& part);
 gabp_status apply_xcd_order(Ctx* c);
 
 // ---- kernels (sweep.hip) ---------------------------------------------------

@@ -272,23 +272,31 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
 gabp_status set_partition(Ctx* c, int K) {
   std::vector<int32_t> br;
   build_partition(c, K, br);
+  std::vector<int32_t> group_blk;  // XCD parts: first workgroup of every group of parts
   if (c->nparts > 0) {
-    // XCD parts: every part gets the same number of workgroups (the short ones
-    // padded with empty workgroups at the part's end), so that the XCD-aware
-    // workgroup map sends part x to XCD x
-    std::vector<int32_t> cnt(c->nparts, 0);
+    // XCD parts: inside a group (the whole matrix, or one colour class), every
+    // part gets the same number of workgroups, the short ones padded with
+    // empty workgroups at the part's end, so that the XCD-aware workgroup map
+    // of a launch over the group sends part x to XCD x
+    const size_t nsub = c->part_start.size() - 1;
+    const int np = c->nparts;
+    std::vector<int32_t> cnt(nsub, 0);
     for (size_t i = 0; i + 1 < br.size(); ++i) {
-      const int p = (int)(std::upper_bound(c->part_start.begin(), c->part_start.end(), br[i]) -
-                          c->part_start.begin()) - 1;
+      const size_t p = (size_t)(std::upper_bound(c->part_start.begin(), c->part_start.end(), br[i]) -
+                                c->part_start.begin()) - 1;
       ++cnt[p];
     }
-    const int32_t q = *std::max_element(cnt.begin(), cnt.end());
     std::vector<int32_t> padded;
     size_t i = 0;
-    for (int p = 0; p < c->nparts; ++p) {
-      for (int32_t k = 0; k < cnt[p]; ++k) padded.push_back(br[i++]);
-      for (int32_t k = cnt[p]; k < q; ++k) padded.push_back(c->part_start[p + 1]);
+    for (size_t g = 0; g * np < nsub; ++g) {
+      group_blk.push_back((int32_t)padded.size());
+      const int32_t q = *std::max_element(cnt.begin() + g * np, cnt.begin() + (g + 1) * np);
+      for (size_t p = g * np; p < (g + 1) * np; ++p) {
+        for (int32_t k = 0; k < cnt[p]; ++k) padded.push_back(br[i++]);
+        for (int32_t k = cnt[p]; k < q; ++k) padded.push_back(c->part_start[p + 1]);
+      }
     }
+    group_blk.push_back((int32_t)padded.size());
     padded.push_back(c->n);
     br.swap(padded);
   }
@@ -307,7 +315,9 @@ gabp_status set_partition(Ctx* c, int K) {
   GABP_HIP(c, hipStreamSynchronize(c->stream));
   c->K = K;
   c->nblk = nb;
-  if (c->ncol > 0) {  // first workgroup of each colour class
+  if (c->ncol > 0 && c->nparts > 0) {  // a colour class is a group of XCD parts
+    c->colour_blk = group_blk;
+  } else if (c->ncol > 0) {  // first workgroup of each colour class
     c->colour_blk.assign(c->ncol + 1, nb);
     for (int32_t k = c->ncol - 1; k >= 0; --k)
       c->colour_blk[k] = (int32_t)(std::lower_bound(br.begin(), br.begin() + nb + 1, c->colour_start[k]) - br.begin());

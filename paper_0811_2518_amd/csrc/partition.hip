@@ -48,15 +48,11 @@ double inside_fraction(const std::vector<int32_t>& op, const std::vector<int32_t
 
 }  // namespace
 
-gabp_status apply_xcd_order(Ctx* c) {
+bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& part) {
   const int32_t n = c->n;
   const int64_t E = c->E;
-  if (E < kMinSlots || n < 4 * kParts) return GABP_OK;
-  hipStream_t s = c->stream;
+  if (E < kMinSlots || n < 4 * kParts) return false;
   const std::vector<int32_t>& op = c->off_ptr_h;
-  std::vector<int32_t> col((size_t)E);
-  GABP_HIP(c, hipMemcpyAsync(col.data(), c->off_col_d, sizeof(int32_t) * E, hipMemcpyDeviceToHost, s));
-  GABP_HIP(c, hipStreamSynchronize(s));
 
   std::vector<int64_t> w(n);
   int64_t total = 0;
@@ -75,7 +71,7 @@ gabp_status apply_xcd_order(Ctx* c) {
 
   // 1. breadth-first growth, the parts taking turns; a part whose frontier
   //    runs dry restarts at the lowest unassigned node
-  std::vector<int32_t> part(n, -1);
+  part.assign(n, -1);
   std::vector<int64_t> load(kParts, 0);
   std::vector<std::deque<int32_t>> front(kParts);
   int32_t scan = 0;
@@ -149,7 +145,19 @@ gabp_status apply_xcd_order(Ctx* c) {
     if (moved == 0) break;
   }
 
-  if (inside_fraction(op, col, part) < inside_fraction(op, col, natural) + kMinGain) return GABP_OK;
+  return inside_fraction(op, col, part) >= inside_fraction(op, col, natural) + kMinGain;
+}
+
+gabp_status apply_xcd_order(Ctx* c) {
+  const int32_t n = c->n;
+  const int64_t E = c->E;
+  if (E < kMinSlots || n < 4 * kParts) return GABP_OK;
+  hipStream_t s = c->stream;
+  std::vector<int32_t> col((size_t)E);
+  GABP_HIP(c, hipMemcpyAsync(col.data(), c->off_col_d, sizeof(int32_t) * E, hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  std::vector<int32_t> part;
+  if (!xcd_parts(c, col, part)) return GABP_OK;
 
   // 3. rows part by part, caller order inside a part
   c->nparts = kParts;

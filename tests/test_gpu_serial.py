@@ -279,3 +279,24 @@ def test_full_er_serial_converges_with_independent_residual(er_full):
         r = p.b - A @ x.cpu().numpy()
         assert np.linalg.norm(r) / np.linalg.norm(p.b) <= 1.05 * TOL
         s.close()
+
+
+def test_serial_xcd_parts_change_no_result():
+    # the rows of every colour class split by XCD part: same colouring, same
+    # iteration, bit for bit
+    p = workloads.er_problem(20000, 8, 96)
+    s = serial(p, edges_per_block=512)
+    s0 = serial(p, edges_per_block=512, natural_order=True)
+    assert s.props()["xcd_parts"] == 8 and s0.props()["xcd_parts"] == 0
+    np.testing.assert_array_equal(s.colours()[0], s0.colours()[0])
+    for T in (0, 1, 2, 9):
+        x, _, v = s.solve(dev(p.b), tol=0, max_iter=T, var=True)
+        x0, _, v0 = s0.solve(dev(p.b), tol=0, max_iter=T, var=True)
+        np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+        np.testing.assert_array_equal(v.cpu().numpy(), v0.cpu().numpy())
+    x, i = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+    x0, i0 = s0.solve(dev(p.b), tol=TOL, max_iter=2000)
+    assert i["sweeps"] == i0["sweeps"]
+    np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+    ref = oracle.serial_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000)
+    assert i["sweeps"] == ref["sweeps"] and rel(x, ref["x"]) <= TOL
