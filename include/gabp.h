@@ -300,6 +300,36 @@ gabp_status gabp_get_batch_profile(gabp_handle h, gabp_batch_profile *out);
  */
 gabp_status gabp_get_colours(gabp_handle h, int32_t *colour, int32_t *num_colours);
 
+/* Row plan of a handle (host struct), see gabp_plan_rows. */
+typedef struct {
+  int32_t num_colours;  /* colour classes (layout 4), else 0                 */
+  int32_t xcd_parts;    /* 8 if the rows are renumbered into XCD parts, else 0 */
+  int32_t num_blocks;   /* workgroups of a sweep over all rows                */
+  int32_t pad;
+} gabp_plan;
+
+/*
+ * gabp_plan_rows -- the row plan gabp_create would make for this pattern
+ * and these options, computed on the host, without a GPU.  That is the
+ * colouring of layout 4 (serial scheduling, Ch. 2 Sec. 2.3), the XCD parts,
+ * the internal row order and the workgroup partition.
+ *   n, row_ptr, col_idx  HOST full CSR pattern (as gabp_create; values unused)
+ *   opts       host, nullable: layout, flags and edges_per_block (0 = 512)
+ *   perm       HOST int32 [n] (output, nullable): internal row of each row
+ *   colour     HOST int32 [n] (output, nullable): colour of each row (layout 4)
+ *   blk_row    HOST int32 [blk_cap] (output, nullable): the first internal
+ *              row of every workgroup, then n (num_blocks + 1 entries; empty
+ *              workgroups pad every XCD part of a group to the same count)
+ *   class_blk  HOST int32 [num_colours + 1] (output, nullable, layout 4):
+ *              the first workgroup of every colour class's launch, then
+ *              num_blocks
+ *   plan       HOST (output, nullable)
+ * GABP_E_ARG for a malformed pattern (as gabp_create) or blk_cap too small.
+ */
+gabp_status gabp_plan_rows(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                           const gabp_opts *opts, int32_t *perm, int32_t *colour,
+                           int32_t *blk_row, int32_t blk_cap, int32_t *class_blk, gabp_plan *plan);
+
 /* gabp_props -- static properties of a handle (host output). */
 gabp_status gabp_get_props(gabp_handle h, gabp_props *props);
 

@@ -31,7 +31,7 @@ LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
            "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
-           "gabp_get_props",
+           "gabp_plan_rows", "gabp_get_props",
            "gabp_destroy", "gabp_last_error")
 
 
@@ -102,6 +102,9 @@ def lib():
     L.gabp_get_batch_profile.restype = c_i32
     L.gabp_get_colours.argtypes = [c_void_p, c_void_p, P(c_i32)]
     L.gabp_get_colours.restype = c_i32
+    L.gabp_plan_rows.argtypes = [c_i32, c_void_p, c_void_p, P(Opts), c_void_p, c_void_p, c_void_p, c_i32, c_void_p,
+                                 P(Plan)]
+    L.gabp_plan_rows.restype = c_i32
     L.gabp_get_props.argtypes = [c_void_p, P(Props)]
     L.gabp_get_props.restype = c_i32
     L.gabp_destroy.argtypes = [c_void_p]
@@ -110,6 +113,34 @@ def lib():
     L.gabp_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("num_colours", c_i32), ("xcd_parts", c_i32), ("num_blocks", c_i32), ("pad", c_i32)]
+
+
+def plan_rows(row_ptr, col, *, layout="auto", natural_order=False, edges_per_block=0):
+    """The row plan gabp_create would make, computed on the host (no GPU):
+    dict with perm, colour, blk_row (NumPy int32) and the plan's counts."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+    cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    n = len(rp) - 1
+    opts = default_opts(layout=LAYOUTS[layout], edges_per_block=edges_per_block,
+                        flags=FLAG_REUSE_PRECISION | (FLAG_NATURAL_ORDER if natural_order else 0))
+    perm = np.zeros(max(n, 1), np.int32)
+    colour = np.zeros(max(n, 1), np.int32)
+    cap = 8 * n + 16  # padding at most multiplies the workgroups of a group by 8
+    blk = np.zeros(cap, np.int32)
+    cls = np.zeros(n + 2, np.int32)
+    pl = Plan()
+    st = lib().gabp_plan_rows(n, rp.ctypes.data_as(c_void_p), cl.ctypes.data_as(c_void_p), ctypes.byref(opts),
+                              perm.ctypes.data_as(c_void_p), colour.ctypes.data_as(c_void_p),
+                              blk.ctypes.data_as(c_void_p), cap, cls.ctypes.data_as(c_void_p), ctypes.byref(pl))
+    if st != OK:
+        raise _err(None, st, "gabp_plan_rows")
+    return {"perm": perm[:n], "colour": colour[:n], "blk_row": blk[:pl.num_blocks + 1],
+            "class_blk": cls[:pl.num_colours + 1] if pl.num_colours else cls[:0],
+            "num_colours": pl.num_colours, "xcd_parts": pl.xcd_parts, "num_blocks": pl.num_blocks}
 
 
 def default_opts(**kw) -> Opts:

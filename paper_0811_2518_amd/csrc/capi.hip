@@ -375,6 +375,68 @@ gabp_status gabp_get_colours(gabp_handle h, int32_t* colour, int32_t* num_colour
   return GABP_OK;
 }
 
+gabp_status gabp_plan_rows(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const gabp_opts* opts,
+                           int32_t* perm, int32_t* colour, int32_t* blk_row, int32_t blk_cap, int32_t* class_blk,
+                           gabp_plan* plan) {
+  if (n < 0 || (n > 0 && (!row_ptr || !col_idx))) return fail(nullptr, GABP_E_ARG, "n < 0 or NULL CSR array");
+  gabp_ctx c;
+  c.n = n;
+  if (opts) c.opts = *opts;
+  else gabp_default_opts(&c.opts);
+  if (check_opts(&c, c.opts) != GABP_OK) return fail(nullptr, GABP_E_ARG, c.err);
+  // the off-diagonal pattern, checked as gabp_create checks it
+  if (n > 0 && (row_ptr[0] != 0 || row_ptr[n] < n)) return fail(nullptr, GABP_E_ARG, "row_ptr");
+  c.off_ptr_h.assign((size_t)n + 1, 0);
+  std::vector<int32_t> col;
+  for (int32_t r = 0; r < n; ++r) {
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(nullptr, GABP_E_ARG, "row pointers decrease");
+    int32_t prev = -1, ndiag = 0;
+    for (int32_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      const int32_t j = col_idx[e];
+      if (j < 0 || j >= n || j <= prev) return fail(nullptr, GABP_E_ARG, "columns unsorted, duplicated or out of range");
+      prev = j;
+      if (j == r) ++ndiag;
+      else col.push_back(j);
+    }
+    if (ndiag != 1) return fail(nullptr, GABP_E_ZERO_DIAG, "a diagonal entry is missing");
+    c.off_ptr_h[r + 1] = (int32_t)col.size();
+    c.max_degree = std::max(c.max_degree, c.off_ptr_h[r + 1] - c.off_ptr_h[r]);
+  }
+  c.E = (int64_t)col.size();
+  std::vector<int32_t> perm_inv;
+  bool renumbered = false;
+  if (n > 0 && c.opts.layout == kLayoutSerial) {
+    plan_colour_order(&c, col, nullptr, 0, perm_inv);
+    renumbered = true;
+  } else if (n > 0 && !(c.opts.flags & GABP_FLAG_NATURAL_ORDER)) {
+    renumbered = plan_xcd_order(&c, col, perm_inv);
+  }
+  if (renumbered) c.off_ptr_h = permuted_ptr(c.off_ptr_h, perm_inv, n);
+  std::vector<int32_t> br, group_blk;
+  if (n > 0) build_blocks(&c, c.opts.edges_per_block ? c.opts.edges_per_block / kBlock : 2, br, group_blk);
+  const int32_t nb = n > 0 ? (int32_t)br.size() - 1 : 0;
+  if (blk_row && blk_cap < nb + 1) return fail(nullptr, GABP_E_ARG, "blk_cap below num_blocks + 1");
+  for (int32_t i = 0; i < n; ++i) {
+    if (perm) perm[i] = renumbered ? perm_inv[i] : i;
+    if (colour) colour[i] = c.colour_h.empty() ? 0 : c.colour_h[i];
+  }
+  if (blk_row) {
+    if (n > 0) std::copy(br.begin(), br.end(), blk_row);
+    else blk_row[0] = 0;
+  }
+  if (class_blk && c.ncol > 0) {
+    const std::vector<int32_t> cb = class_blocks(&c, br, group_blk);
+    std::copy(cb.begin(), cb.end(), class_blk);
+  }
+  if (plan) {
+    plan->num_colours = c.ncol;
+    plan->xcd_parts = c.nparts;
+    plan->num_blocks = nb;
+    plan->pad = 0;
+  }
+  return GABP_OK;
+}
+
 gabp_status gabp_get_props(gabp_handle h, gabp_props* p) {
   if (!h || !p) return fail(h, GABP_E_ARG, "NULL argument");
   Ctx* c = h;

@@ -66,16 +66,20 @@ __global__ void k_remap_rev(int64_t E, const int32_t* __restrict__ slot_of, cons
 
 }  // namespace
 
-gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep_slots) {
-  hipStream_t s = c->stream;
-  const int32_t n = c->n;
-  const int64_t E = c->E;
-  const std::vector<int32_t>& op = c->off_ptr_h;
+std::vector<int32_t> permuted_ptr(const std::vector<int32_t>& op, const std::vector<int32_t>& perm_inv, int32_t n) {
   std::vector<int32_t> new_ptr((size_t)n + 1, 0);
   for (int32_t p = 0; p < n; ++p) {
     const int32_t r = perm_inv[n + p];
     new_ptr[p + 1] = new_ptr[p] + (op[r + 1] - op[r]);
   }
+  return new_ptr;
+}
+
+gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep_slots) {
+  hipStream_t s = c->stream;
+  const int32_t n = c->n;
+  const int64_t E = c->E;
+  std::vector<int32_t> new_ptr = permuted_ptr(c->off_ptr_h, perm_inv, n);
   void* pi = nullptr;
   GABP_TRY_STATUS(dev_alloc(c, &pi, sizeof(int32_t) * 2 * (size_t)n));
   c->perm_d = (int32_t*)pi;
@@ -129,15 +133,10 @@ gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep
   return GABP_OK;
 }
 
-gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys) {
-  hipStream_t s = c->stream;
+void plan_colour_order(Ctx* c, const std::vector<int32_t>& col, const int32_t* sys_row_off, int32_t num_sys,
+                       std::vector<int32_t>& perm_inv) {
   const int32_t n = c->n;
-  const int64_t E = c->E;
   const std::vector<int32_t>& op = c->off_ptr_h;
-  std::vector<int32_t> col((size_t)E);
-  if (E > 0)
-    GABP_HIP(c, hipMemcpyAsync(col.data(), c->off_col_d, sizeof(int32_t) * E, hipMemcpyDeviceToHost, s));
-  GABP_HIP(c, hipStreamSynchronize(s));
 
   // first fit in row order
   std::vector<int32_t>& colour = c->colour_h;
@@ -168,7 +167,7 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
   const int32_t S = sys_row_off ? num_sys : 1;
   c->cls_base.assign(S + 1, 0);
   c->cls_row.clear();
-  std::vector<int32_t> perm_inv(2 * (size_t)n);  // [perm | inv]
+  perm_inv.assign(2 * (size_t)n, 0);  // [perm | inv]
   for (int32_t q = 0; q < S; ++q) {
     const int32_t r0 = sys_row_off ? sys_row_off[q] : 0, r1 = sys_row_off ? sys_row_off[q + 1] : n;
     int32_t nc = r1 > r0 ? 1 : 0;
@@ -203,6 +202,16 @@ gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_s
   }
   c->cls_base[S] = (int32_t)c->cls_row.size();
   if (!sys_row_off) c->colour_start = c->cls_row;
+}
+
+gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys) {
+  hipStream_t s = c->stream;
+  std::vector<int32_t> col((size_t)c->E);
+  if (c->E > 0)
+    GABP_HIP(c, hipMemcpyAsync(col.data(), c->off_col_d, sizeof(int32_t) * c->E, hipMemcpyDeviceToHost, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
+  std::vector<int32_t> perm_inv;
+  plan_colour_order(c, col, sys_row_off, num_sys, perm_inv);
   return permute_rows(c, perm_inv, false);  // the serial sweeps pull through aggregates only
 }
 

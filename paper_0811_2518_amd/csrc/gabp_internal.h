@@ -281,11 +281,22 @@ gabp_status dev_alloc(Ctx* c, void** p, size_t bytes);
 // ---- ingest (ingest.hip) ---------------------------------------------------
 gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const double* vals,
                    const int32_t* sys_row_off_d, int32_t num_sys);
-gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row);
+gabp_status build_partition(const Ctx* c, int K, std::vector<int32_t>& blk_row);
 gabp_status set_partition(Ctx* c, int K);
+// host part of set_partition: workgroup starts (then n) and, with XCD parts,
+// the first workgroup of every group of parts (then the count)
+void build_blocks(const Ctx* c, int K, std::vector<int32_t>& blk_row, std::vector<int32_t>& group_blk);
+// first workgroup of every colour class, then the count (colour-serial)
+std::vector<int32_t> class_blocks(const Ctx* c, const std::vector<int32_t>& blk_row,
+                                  const std::vector<int32_t>& group_blk);
 // colour.hip: first-fit colouring in row order and the colour-ordered
 // renumbering of the off-diagonal CSR (colour-serial layout)
 gabp_status apply_colour_order(Ctx* c, const int32_t* sys_row_off, int32_t num_sys);  // host offsets, nullable
+// host part: colours, class (and XCD part) ranges and perm_inv from the
+// caller's off-diagonal pattern (c->off_ptr_h, col)
+void plan_colour_order(Ctx* c, const std::vector<int32_t>& col, const int32_t* sys_row_off, int32_t num_sys,
+                       std::vector<int32_t>& perm_inv);
+std::vector<int32_t> permuted_ptr(const std::vector<int32_t>& op, const std::vector<int32_t>& perm_inv, int32_t n);
 // renumber the rows of the off-diagonal CSR: perm_inv = [perm | inv] (caller row
 // -> internal row, internal -> caller); keep_slots keeps the caller slot of every
 // internal slot and the reverse-slot index
@@ -293,6 +304,7 @@ gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep
 // partition.hip: XCD-aware row order (8 slot-balanced parts, part x on XCD x).
 // xcd_parts fills part[caller row] and says whether the parts pay off.
 bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& part);
+bool plan_xcd_order(Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& perm_inv);
 gabp_status apply_xcd_order(Ctx* c);
 
 // ---- kernels (sweep.hip) ---------------------------------------------------

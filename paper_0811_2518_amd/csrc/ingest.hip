@@ -236,7 +236,7 @@ gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const dou
 // rows; a row longer than 256*K gets a workgroup of its own (handled by the
 // sweep kernel's long-row path).  With colour classes or XCD parts, no
 // workgroup spans two of them.
-gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
+gabp_status build_partition(const Ctx* c, int K, std::vector<int32_t>& blk_row) {
   const int64_t cap = (int64_t)kBlock * K;
   blk_row.clear();
   blk_row.push_back(0);
@@ -269,10 +269,9 @@ gabp_status build_partition(Ctx* c, int K, std::vector<int32_t>& blk_row) {
   return GABP_OK;
 }
 
-gabp_status set_partition(Ctx* c, int K) {
-  std::vector<int32_t> br;
+void build_blocks(const Ctx* c, int K, std::vector<int32_t>& br, std::vector<int32_t>& group_blk) {
   build_partition(c, K, br);
-  std::vector<int32_t> group_blk;  // XCD parts: first workgroup of every group of parts
+  group_blk.clear();
   if (c->nparts > 0) {
     // XCD parts: inside a group (the whole matrix, or one colour class), every
     // part gets the same number of workgroups, the short ones padded with
@@ -300,7 +299,23 @@ gabp_status set_partition(Ctx* c, int K) {
     padded.push_back(c->n);
     br.swap(padded);
   }
+}
+
+std::vector<int32_t> class_blocks(const Ctx* c, const std::vector<int32_t>& br, const std::vector<int32_t>& group_blk) {
+  if (c->ncol <= 0) return {};
+  if (c->nparts > 0) return group_blk;  // a colour class is a group of XCD parts
   const int32_t nb = (int32_t)br.size() - 1;
+  std::vector<int32_t> out(c->ncol + 1, nb);
+  for (int32_t k = c->ncol - 1; k >= 0; --k)
+    out[k] = (int32_t)(std::lower_bound(br.begin(), br.begin() + nb + 1, c->colour_start[k]) - br.begin());
+  return out;
+}
+
+gabp_status set_partition(Ctx* c, int K) {
+  std::vector<int32_t> br, group_blk;  // XCD parts: first workgroup of every group of parts
+  build_blocks(c, K, br, group_blk);
+  const int32_t nb = (int32_t)br.size() - 1;
+  std::vector<int32_t> cls_blk = class_blocks(c, br, group_blk);  // before br is extended below
   // first rows, then first slots, of the workgroups: [2 (nb + 1)]
   for (int32_t i = 0; i <= nb; ++i) br.push_back(c->off_ptr_h[br[i]]);
   if (c->blk_row_d == nullptr || nb > c->nblk_capacity) {
@@ -315,13 +330,7 @@ gabp_status set_partition(Ctx* c, int K) {
   GABP_HIP(c, hipStreamSynchronize(c->stream));
   c->K = K;
   c->nblk = nb;
-  if (c->ncol > 0 && c->nparts > 0) {  // a colour class is a group of XCD parts
-    c->colour_blk = group_blk;
-  } else if (c->ncol > 0) {  // first workgroup of each colour class
-    c->colour_blk.assign(c->ncol + 1, nb);
-    for (int32_t k = c->ncol - 1; k >= 0; --k)
-      c->colour_blk[k] = (int32_t)(std::lower_bound(br.begin(), br.begin() + nb + 1, c->colour_start[k]) - br.begin());
-  }
+  c->colour_blk.swap(cls_blk);
   if (c->partials_d == nullptr || nb > c->partials_capacity) {
     void* p = nullptr;
     GABP_TRY(dev_alloc(c, &p, sizeof(double) * (nb + 1024)));

@@ -372,6 +372,11 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
   const int ce = std::max(1, cfg.check_every);
   auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
   const double tol = exact ? -1.0 : cfg.tol;
+  // the class launches must tile the workgroup partition exactly
+  bool tiled = (int)c->colour_blk.size() == c->ncol + 1 && (int)c->colour_start.size() == c->ncol + 1 &&
+               c->ncol > 0 && c->colour_blk[0] == 0 && c->colour_blk[c->ncol] == c->nblk;
+  for (int q = 0; tiled && q < c->ncol; ++q) tiled = c->colour_blk[q] <= c->colour_blk[q + 1];
+  if (!tiled) return fail(c, GABP_E_ARG, "colour classes do not tile the workgroup partition");
 
   SerialArgs<T> a{};
   a.blk_row = c->blk_row_d;

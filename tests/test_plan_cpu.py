@@ -1,0 +1,134 @@
+"""The create-time row plan (colouring, XCD parts, row order, workgroup
+partition), computed by the library on the host -- no GPU needed.
+
+The colouring is checked bit for bit against the oracle's first fit.  The
+XCD order and the partition are checked on the properties the sweep kernels
+rely on.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_0811_2518_amd import binding
+
+KBLOCK, MAXROWS, XCDS = 256, 256, 8
+
+
+def blocks_ok(p, plan, epb):
+    """Workgroups in order, covering every row, at most 256 rows and epb slots
+    (or one long row each)."""
+    br = plan["blk_row"]
+    assert br[0] == 0 and br[-1] == p.n and np.all(np.diff(br) >= 0)
+    inv = np.empty(p.n, np.int64)
+    inv[plan["perm"]] = np.arange(p.n)
+    deg = (np.diff(p.row_ptr) - 1)[inv]  # off-diagonal degree in internal order
+    ptr = np.concatenate([[0], np.cumsum(deg)])
+    for lo, hi in zip(br[:-1], br[1:]):
+        assert hi - lo <= MAXROWS
+        assert ptr[hi] - ptr[lo] <= epb or hi - lo == 1
+
+
+def internal_edges(p, owner_of_internal_row):
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    off = rows != p.col
+    return np.mean(owner_of_internal_row[np.asarray(p.perm_rows)[rows[off]]] ==
+                   owner_of_internal_row[np.asarray(p.perm_rows)[p.col[off]]])
+
+
+def xcd_of_rows(plan, groups):
+    """XCD of every internal row: group g's 8q workgroups go to XCD w // q."""
+    br = plan["blk_row"]
+    owner = np.empty(br[-1], np.int64)
+    for g0, g1 in groups:
+        q = (g1 - g0) // XCDS
+        assert (g1 - g0) % XCDS == 0
+        for w in range(g0, g1):
+            owner[br[w]:br[w + 1]] = (w - g0) // q
+    return owner
+
+
+@pytest.mark.parametrize("epb", [512, 2048])
+def test_xcd_order_on_a_random_graph(epb):
+    p = workloads.er_problem(20000, 8, 93)
+    plan = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb)
+    assert plan["xcd_parts"] == 8 and plan["num_colours"] == 0
+    assert sorted(plan["perm"]) == list(range(p.n))
+    blocks_ok(p, plan, epb)
+    owner = xcd_of_rows(plan, [(0, plan["num_blocks"])])
+    # every XCD gets an equal share of the work, and far more of its rows'
+    # edges stay inside it than for 8 ranges of the caller's order
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    off = rows != p.col
+    r, c = plan["perm"][rows[off]], plan["perm"][p.col[off]]
+    inside = np.mean(owner[r] == owner[c])
+    natural = np.mean((rows[off] * 8 // p.n) == (p.col[off] * 8 // p.n))
+    assert inside >= natural + 0.10, (inside, natural)
+    work = np.bincount(owner[plan["perm"]], weights=np.diff(p.row_ptr).astype(float), minlength=8)
+    assert work.max() <= 1.05 * work.mean()
+    # without the XCD order: the caller's rows, no padding
+    nat = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb, natural_order=True)
+    assert nat["xcd_parts"] == 0 and np.array_equal(nat["perm"], np.arange(p.n))
+    blocks_ok(p, nat, epb)
+
+
+def test_grids_keep_the_caller_order():
+    for p in (workloads.config1(), workloads.grid3d_problem(24, 95)):
+        plan = binding.plan_rows(p.row_ptr, p.col)
+        assert plan["xcd_parts"] == 0 and np.array_equal(plan["perm"], np.arange(p.n))
+        blocks_ok(p, plan, 512)
+
+
+@pytest.mark.parametrize("name", ["er", "grid", "tree", "star", "small_er"])
+def test_serial_plan_colouring_is_the_oracles(name):
+    p = {"er": workloads.er_problem(20000, 8, 96), "grid": workloads.grid2d_problem(40, 31, 3),
+         "tree": workloads.random_tree(900, 5), "star": workloads.star_problem(3000, 2),
+         "small_er": workloads.er_problem(300, 5, 7)}[name]
+    plan = binding.plan_rows(p.row_ptr, p.col, layout="serial")
+    ref = oracle.greedy_colouring(p.n, p.row_ptr, p.col)
+    np.testing.assert_array_equal(plan["colour"], ref)
+    assert plan["num_colours"] == int(ref.max()) + 1
+    blocks_ok(p, plan, 512)
+    # classes are contiguous internal ranges in colour order, caller order
+    # inside a class (inside a class's XCD part when there are parts)
+    col_int = np.empty(p.n, np.int64)
+    col_int[plan["perm"]] = ref
+    assert np.all(np.diff(col_int) >= 0)
+    # no workgroup spans two classes
+    br = plan["blk_row"]
+    for lo, hi in zip(br[:-1], br[1:]):
+        if hi > lo:
+            assert col_int[lo] == col_int[hi - 1]
+    if plan["xcd_parts"]:
+        assert name == "er"
+        # every class launch is a group of 8q workgroups holding exactly the
+        # class's rows, part x's rows in its x-th eighth
+        cb = plan["class_blk"]
+        assert cb[0] == 0 and cb[-1] == plan["num_blocks"]
+        for k in range(plan["num_colours"]):
+            g0, g1 = cb[k], cb[k + 1]
+            assert (g1 - g0) % XCDS == 0
+            assert br[g0] == np.searchsorted(col_int, k) and br[g1] == np.searchsorted(col_int, k + 1)
+    else:
+        cb = plan["class_blk"]
+        assert cb[0] == 0 and cb[-1] == plan["num_blocks"] and np.all(np.diff(cb) > 0)
+        for k in range(plan["num_colours"]):
+            assert br[cb[k]] == np.searchsorted(col_int, k)
+
+
+def test_plan_rejects_malformed_patterns():
+    p = workloads.config1()
+    col = p.col.copy()
+    col[5], col[6] = col[6], col[5]  # unsorted row
+    with pytest.raises(binding.GabpError):
+        binding.plan_rows(p.row_ptr, col)
+    rp = p.row_ptr.copy()
+    rp[3] = rp[4] + 1  # decreasing pointers
+    with pytest.raises(binding.GabpError):
+        binding.plan_rows(rp, p.col)
+    # a row without its diagonal entry (the pattern alone decides)
+    with pytest.raises(binding.GabpError):
+        binding.plan_rows(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32))
+    # out-of-range column
+    with pytest.raises(binding.GabpError):
+        binding.plan_rows(np.array([0, 2, 4], np.int32), np.array([0, 2, 0, 1], np.int32))
