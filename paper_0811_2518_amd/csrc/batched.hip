@@ -789,6 +789,15 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off) 
       c->cls_base.resize(num_sys + 1);
       for (int s = 0; s <= num_sys; ++s) c->cls_base[s] = s;
     }
+    // every system's class list runs from its first row to its end, in order
+    bool ok = (int32_t)c->cls_base.size() == num_sys + 1;
+    for (int s = 0; ok && s < num_sys; ++s) {
+      const int32_t b0 = c->cls_base[s], b1 = c->cls_base[s + 1];
+      ok = b1 > b0 && b1 <= (int32_t)c->cls_row.size() && c->cls_row[b0] == sys_row_off[s] &&
+           c->cls_row[b1 - 1] == sys_row_off[s + 1];
+      for (int32_t k = b0; ok && k + 1 < b1; ++k) ok = c->cls_row[k] <= c->cls_row[k + 1];
+    }
+    if (!ok) return fail(c, GABP_E_ARG, "internal: invalid colour class lists");
     GABP_HIP(c, hipMalloc((void**)&bs->cls_row_d, sizeof(int32_t) * c->cls_row.size()));
     GABP_HIP(c, hipMemcpyAsync(bs->cls_row_d, c->cls_row.data(), sizeof(int32_t) * c->cls_row.size(),
                                hipMemcpyHostToDevice, c->stream));

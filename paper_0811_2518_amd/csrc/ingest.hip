@@ -315,6 +315,15 @@ gabp_status set_partition(Ctx* c, int K) {
   std::vector<int32_t> br, group_blk;  // XCD parts: first workgroup of every group of parts
   build_blocks(c, K, br, group_blk);
   const int32_t nb = (int32_t)br.size() - 1;
+  // what the sweep kernels assume of every workgroup: rows in order covering
+  // 0..n, at most 256 rows, at most 256 K slots unless it is one long row
+  bool ok = nb >= 1 && br[0] == 0 && br[nb] == c->n;
+  for (int32_t i = 0; ok && i < nb; ++i) {
+    const int32_t rows = br[i + 1] - br[i];
+    const int64_t slots = (int64_t)c->off_ptr_h[br[i + 1]] - c->off_ptr_h[br[i]];
+    ok = rows >= 0 && rows <= kMaxRowsPerBlock && (slots <= (int64_t)kBlock * K || rows == 1);
+  }
+  if (!ok) return fail(c, GABP_E_ARG, "internal: invalid workgroup partition");
   std::vector<int32_t> cls_blk = class_blocks(c, br, group_blk);  // before br is extended below
   // first rows, then first slots, of the workgroups: [2 (nb + 1)]
   for (int32_t i = 0; i <= nb; ++i) br.push_back(c->off_ptr_h[br[i]]);
