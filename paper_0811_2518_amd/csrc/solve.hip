@@ -815,10 +815,10 @@ std::string tune_key(const Ctx* c) {
   while ((1LL << (nb + 1)) <= (long long)std::max(1, c->n)) ++nb;
   const double avg = c->n ? (double)c->E / c->n : 0.0;
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d-L%d-epb%d",
+  std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d-L%d-epb%d-x%d",
                 c->opts.precision == GABP_FP32_REFINE ? 32 : 64, nb, (int)std::lround(avg),
                 c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256), c->opts.layout,
-                c->opts.edges_per_block);
+                c->opts.edges_per_block, c->nparts);
   return buf;
 }
 
