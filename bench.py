@@ -363,6 +363,34 @@ def suite_grid(torch, g, workloads):
     return out
 
 
+def suite_powerlaw(torch, g, workloads):
+    """The heavy-tailed degree shape of the web and social graphs the thesis
+    runs on, at the headline size: hub rows of up to 1.4e5 slots are swept in
+    chunks of one workgroup each."""
+    p = workloads.powerlaw_config()
+    deg = np.diff(p.row_ptr) - 1
+    b = torch.from_numpy(p.b).to("cuda")
+    out = {"workload": "power-law random graph, n=1048576, 4n edges, degree exponent 2.1, A_ii = 1.1 sum|A_ij|",
+           "n": p.n, "E": p.num_offdiag, "max_degree": int(deg.max()),
+           "slots_in_rows_over_512": float(deg[deg > 512].sum() / deg.sum())}
+    for name, kw in (("fp64", {}), ("fp32_refine", {"precision": "fp32"}), ("serial_fp64", {"layout": "serial"}),
+                     ("serial_fp32_refine", {"layout": "serial", "precision": "fp32"})):
+        s = g.Solver(p.row_ptr, p.col, p.val, reuse_precision=False, **kw)
+        s.solve(b, tol=TOL, max_iter=2000)
+        dt, (x, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=2000), reps=5)
+        res = float(np.linalg.norm(p.b - p.scipy() @ x.cpu().numpy()) / np.linalg.norm(p.b))
+        pr = s.props()
+        out[name] = {"time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "outer_iters": info["outer_iters"],
+                     "rel_residual": res, "layout": LAYOUT_NAMES.get(pr["layout"], pr["layout"]),
+                     "edges_per_block": pr["edges_per_block"]}
+        if name == "fp64":
+            out[name]["edge_updates_per_s"] = p.num_offdiag * info["sweeps"] / dt
+        s.close()
+    out["fp64"]["sweep_ms"] = sweep_period(torch, g, p, b)
+    out["serial_fp64"]["sweep_ms"] = sweep_period(torch, g, p, b, layout="serial")
+    return out
+
+
 def suite_adjoint(torch, g, workloads):
     p = workloads.config4()
     b = torch.from_numpy(p.b).to("cuda")
@@ -684,6 +712,7 @@ def main():
     suite = {}
     if not args.no_suite:
         for name, fn in (("grid32_fp64", lambda: suite_grid(torch, g, workloads)),
+                         ("powerlaw_n2e20", lambda: suite_powerlaw(torch, g, workloads)),
                          ("adjoint_grid3d_64", lambda: suite_adjoint(torch, g, workloads)),
                          ("convfix_btb", lambda: suite_convfix(torch, g, workloads)),
                          ("batched_4096", lambda: suite_batched(torch, g, workloads))):

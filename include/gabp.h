@@ -305,7 +305,9 @@ typedef struct {
   int32_t num_colours;  /* colour classes (layout 4), else 0                 */
   int32_t xcd_parts;    /* 8 if the rows are renumbered into XCD parts, else 0 */
   int32_t num_blocks;   /* workgroups of a sweep over all rows                */
-  int32_t pad;
+  int32_t num_chunks;   /* extra workgroups of a compact or colour-serial
+                           sweep: a row with more than edges_per_block slots
+                           is swept in chunks of edges_per_block slots       */
 } gabp_plan;
 
 /*

@@ -116,7 +116,7 @@ def lib():
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("num_colours", c_i32), ("xcd_parts", c_i32), ("num_blocks", c_i32), ("pad", c_i32)]
+    _fields_ = [("num_colours", c_i32), ("xcd_parts", c_i32), ("num_blocks", c_i32), ("num_chunks", c_i32)]
 
 
 def plan_rows(row_ptr, col, *, layout="auto", natural_order=False, edges_per_block=0):
@@ -140,7 +140,8 @@ def plan_rows(row_ptr, col, *, layout="auto", natural_order=False, edges_per_blo
         raise _err(None, st, "gabp_plan_rows")
     return {"perm": perm[:n], "colour": colour[:n], "blk_row": blk[:pl.num_blocks + 1],
             "class_blk": cls[:pl.num_colours + 1] if pl.num_colours else cls[:0],
-            "num_colours": pl.num_colours, "xcd_parts": pl.xcd_parts, "num_blocks": pl.num_blocks}
+            "num_colours": pl.num_colours, "xcd_parts": pl.xcd_parts, "num_blocks": pl.num_blocks,
+            "num_chunks": pl.num_chunks}
 
 
 def default_opts(**kw) -> Opts:

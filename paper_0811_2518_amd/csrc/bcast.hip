@@ -195,7 +195,6 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[kBlock / 64];
   __shared__ T s_redT[kBlock / 64];
-  __shared__ T s_bc[2];
   if (A.st->done) return;
 
   const int tid = threadIdx.x;
@@ -284,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
       own(r0 + tid, P, h);
       s_AoP[tid] = P;
       s_Aoh[tid] = h;
-      for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) s_row[j] = (uint8_t)tid;
+      fill_row_ids(s_row, s_ptr[tid], s_ptr[tid + 1], tid);
     }
     __syncthreads();
 
@@ -310,16 +309,14 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
         Agg<T> an;
         an.P = A.diag[r];
         an.h = A.rhs[r];
-        for (int j = lo; j < hi; ++j) {
-          an.P += s_Pn[j];
-          an.h += s_hn[j];
-        }
+        an.P = lds_row_sum(an.P, s_Pn, lo, hi);
+        an.h = lds_row_sum(an.h, s_hn, lo, hi);
         ((Agg<T>*)A.anew)[r] = an;
         if (A.xout) A.xout[r] = an.h / an.P;
         if (A.ptout) A.ptout[r] = an.P;
       } else if (MODE == kHOnly) {
         T ht = A.rhs[r];
-        for (int j = lo; j < hi; ++j) ht += s_hn[j];
+        ht = lds_row_sum(ht, s_hn, lo, hi);
         ((T*)A.anew)[r] = ht;
         if (A.xout) A.xout[r] = ht * A.inv_pt[r];
       } else if (MODE == kFreeze) {
@@ -329,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_bcast(BcastArgs<T> A) {
       if (A.zero_in && A.ptout_prev) A.ptout_prev[r] = s_AoP[tid];
       if (A.check) {
         double acc = (double)A.rhs[r] - (double)A.diag[r] * (double)own_x(r, s_AoP[tid], s_Aoh[tid]);
-        for (int j = lo; j < hi; ++j) acc -= (double)s_ax[j];
+        acc = lds_row_sub(acc, s_ax, lo, hi);
         res2 = acc * acc;
       }
     }

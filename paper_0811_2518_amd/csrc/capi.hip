@@ -432,7 +432,14 @@ gabp_status gabp_plan_rows(int32_t n, const int32_t* row_ptr, const int32_t* col
     plan->num_colours = c.ncol;
     plan->xcd_parts = c.nparts;
     plan->num_blocks = nb;
-    plan->pad = 0;
+    plan->num_chunks = 0;
+    if (n > 0) {
+      std::vector<LongRow> lr;
+      std::vector<ChunkRef> xc;
+      std::vector<int32_t> xb;
+      plan_long_rows(c.off_ptr_h, br, nb, c.opts.edges_per_block ? c.opts.edges_per_block / kBlock : 2, lr, xc, xb);
+      plan->num_chunks = (int32_t)xc.size();
+    }
   }
   return GABP_OK;
 }

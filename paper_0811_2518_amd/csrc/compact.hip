@@ -183,6 +183,102 @@ __device__ __forceinline__ void compute_slot(const CnodeArgs<T>& A, int s, const
   }
 }
 
+// Prior potential of round t: b, or with the single-loop feedback
+// b + Gamma ((1 - s) x^(t-2) + s x^(t-1)), Gamma = diag - chk_diag.
+template <typename T, int MODE>
+__device__ __forceinline__ T cn_prior_h(const CnodeArgs<T>& A, int r, T br, Msg<T> o1, Msg<T> o2) {
+  if (MODE != kJoint || !A.feedback) return br;
+  const T x1 = o1.h / o1.P;
+  const T x2 = A.first ? T(0) : o2.h / o2.P;
+  return br + (A.diag[r] - A.chk_diag[r]) * ((T(1) - A.damp) * x2 + A.damp * x1);
+}
+
+// Diagonal of the checked system.
+template <typename T>
+__device__ __forceinline__ T cn_chk_d(const CnodeArgs<T>& A, int r, T dr) {
+  return A.chk_diag ? A.chk_diag[r] : dr;
+}
+
+// Row epilogue: publish the aggregates (P, h) of round t, the means and, on
+// the first sweep, the round-0 means.
+template <typename T, int MODE>
+__device__ __forceinline__ void cn_publish(const CnodeArgs<T>& A, int r, Msg<T> o1, T P, T h) {
+  if (MODE == kJoint) {
+    vec2<T> v;
+    v.x = P;
+    v.y = h;
+    ((vec2<T>*)A.anew)[r] = v;
+    if (A.xout) A.xout[r] = h / P;
+    if (A.ptout) A.ptout[r] = P;
+  } else if (MODE == kHOnly) {
+    const T ip = A.inv_pt[r];
+    vec2<T> v;
+    v.x = ip;
+    v.y = h;
+    ((vec2<T>*)A.anew)[r] = v;
+    if (A.xout) A.xout[r] = h * ip;
+  } else if (MODE == kFreeze) {
+    A.inv_pt_out[r] = T(1) / o1.P;
+  }
+  if (A.first && A.xout_prev) A.xout_prev[r] = mean_of<T, MODE>(A, o1);
+  if (A.first && A.ptout_prev) A.ptout_prev[r] = o1.P;
+}
+
+// One chunk (at most 256 K slots) of a long row: the slots' new messages, and
+// the chunk's partial sums of P, h and the residual terms in lpart.
+template <typename T, int K, int MODE>
+__device__ __forceinline__ void cnode_chunk(const CnodeArgs<T>& A, const LongRow& L, int ci, double* s_red,
+                                            T* s_redT) {
+  constexpr int S = kBlock * K;
+  const int tid = threadIdx.x;
+  const int r = L.row;
+  const int e0 = L.e0 + ci * S;
+  const int ne = min(S, L.ne - ci * S);
+  const bool need_o2 = (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) && !A.first;
+  SlotIn<T> in[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) load_slot<T, MODE>(A, e0 + i, in[k]);
+  }
+  const Msg<T> o1 = ld_agg<T>(A.agg1, r);
+  const Msg<T> o2 = need_o2 ? ld_agg<T>(A.agg2, r) : Msg<T>{0, 0};
+  Msg<T> g[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) g[k] = ld_agg<T>(A.agg1, in[k].c);
+  }
+  T pP = 0, ph = 0;
+  double pax = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) {
+      T Pn, hn, ax;
+      compute_slot<T, MODE>(A, e0 + i, in[k], g[k], o1, o2, Pn, hn, ax);
+      pP += Pn;
+      ph += hn;
+      pax += (double)ax;
+      if (MODE != kResid) bad |= !(isfinite(Pn) && isfinite(hn));
+    }
+  }
+  if (bad) {
+    atomicOr(&A.st->error, kErrNonfinite);
+    atomicExch(&A.st->done, 1);
+  }
+  pP = bsum_c(pP, s_redT);
+  ph = bsum_c(ph, s_redT);
+  pax = bsum_c(pax, s_red);
+  if (tid == 0) {
+    double* q = A.lpart + 4 * (size_t)(L.cbase + ci);
+    q[0] = (double)pP;
+    q[1] = (double)ph;
+    q[2] = pax;
+  }
+}
+
 template <typename T, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
   constexpr int S = kBlock * K;
@@ -190,79 +286,25 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
   __shared__ double s_red[kBlock / 64];
   __shared__ T s_redT[kBlock / 64];
   if (A.st->done) return;
+  if ((int)blockIdx.x >= A.nblk) {  // a chunk of a long row
+    const ChunkRef x = A.xch[blockIdx.x - A.nblk];
+    cnode_chunk<T, K, MODE>(A, A.longs[x.li], x.c, s_red, s_redT);
+    return;
+  }
 
   const int tid = threadIdx.x;
   const int b = xcd_remap_c(blockIdx.x, A.nblk);
   const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
   const int e0 = A.blk_e0[b], ne = A.blk_e0[b + 1] - e0;
   const int nrow = r1 - r0;
+  // a long row is swept by its chunk workgroups and finished by k_cnode_long
+  if (ne > S) return;
   // own-aggregate records: o1 = round t-1 (T), o2 = round t-2 (T-1)
   const bool need_o2 = (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) && !A.first;
   double res2 = 0.0;
   bool bad = false;
 
-  // prior potential of round t: b, or with the single-loop feedback
-  // b + Gamma ((1 - s) x^(t-2) + s x^(t-1)), Gamma = diag - chk_diag
-  auto prior_h = [&](int r, T br, Msg<T> o1, Msg<T> o2) -> T {
-    if (MODE != kJoint || !A.feedback) return br;
-    const T x1 = o1.h / o1.P;
-    const T x2 = A.first ? T(0) : o2.h / o2.P;
-    return br + (A.diag[r] - A.chk_diag[r]) * ((T(1) - A.damp) * x2 + A.damp * x1);
-  };
-  // diagonal of the checked system
-  auto chk_d = [&](int r, T dr) -> T { return A.chk_diag ? A.chk_diag[r] : dr; };
-  // per-row epilogue: publish the aggregates (P, h) of round t, the means
-  // and, on the first sweep, the round-0 means
-  auto publish = [&](int r, Msg<T> o1, T P, T h) {
-    if (MODE == kJoint) {
-      vec2<T> v;
-      v.x = P;
-      v.y = h;
-      ((vec2<T>*)A.anew)[r] = v;
-      if (A.xout) A.xout[r] = h / P;
-      if (A.ptout) A.ptout[r] = P;
-    } else if (MODE == kHOnly) {
-      const T ip = A.inv_pt[r];
-      vec2<T> v;
-      v.x = ip;
-      v.y = h;
-      ((vec2<T>*)A.anew)[r] = v;
-      if (A.xout) A.xout[r] = h * ip;
-    } else if (MODE == kFreeze) {
-      A.inv_pt_out[r] = T(1) / o1.P;
-    }
-    if (A.first && A.xout_prev) A.xout_prev[r] = mean_of<T, MODE>(A, o1);
-    if (A.first && A.ptout_prev) A.ptout_prev[r] = o1.P;
-  };
-
-  if (ne > S) {  // one long row: strided slots, block reductions
-    const Msg<T> o1 = ld_agg<T>(A.agg1, r0);
-    const Msg<T> o2 = need_o2 ? ld_agg<T>(A.agg2, r0) : Msg<T>{0, 0};
-    T pP = 0, ph = 0;
-    double pax = 0.0;
-    for (int i = tid; i < ne; i += kBlock) {
-      SlotIn<T> in;
-      load_slot<T, MODE>(A, e0 + i, in);
-      const Msg<T> g = ld_agg<T>(A.agg1, in.c);
-      T Pn, hn, ax;
-      compute_slot<T, MODE>(A, e0 + i, in, g, o1, o2, Pn, hn, ax);
-      pP += Pn;
-      ph += hn;
-      pax += (double)ax;
-      if (MODE != kResid) bad |= !(isfinite(Pn) && isfinite(hn));
-    }
-    pP = bsum_c(pP, s_redT);
-    ph = bsum_c(ph, s_redT);
-    pax = bsum_c(pax, s_red);
-    if (tid == 0) {
-      publish(r0, o1, A.diag[r0] + pP, prior_h(r0, A.rhs[r0], o1, o2) + ph);
-      if (A.check) {
-        const double acc =
-            (double)A.rhs[r0] - (double)chk_d(r0, A.diag[r0]) * (double)mean_of<T, MODE>(A, o1) - pax;
-        res2 = acc * acc;
-      }
-    }
-  } else {
+  {
     T* s_Pn = (T*)smem;
     T* s_hn = s_Pn + S;
     T* s_ax = s_hn + S;
@@ -309,8 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     }
     if (tid == 0) s_ptr[nrow] = ne;
     __syncthreads();
-    if (tid < nrow)
-      for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) s_row[j] = (uint8_t)tid;
+    if (tid < nrow) fill_row_ids(s_row, s_ptr[tid], s_ptr[tid + 1], tid);
     __syncthreads();
 
     // 4. slot arithmetic
@@ -334,16 +375,13 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     // 5. row sums: diagonal first, then the slots in CSR order
     if (tid < nrow) {
       const int lo = s_ptr[tid], hi = s_ptr[tid + 1];
-      T P = dr, h = prior_h(r, br, o1, o2);
-      if (MODE == kJoint || MODE == kHOnly)
-        for (int j = lo; j < hi; ++j) {
-          if (MODE == kJoint) P += s_Pn[j];
-          h += s_hn[j];
-        }
-      publish(r, o1, P, h);
+      T P = dr, h = cn_prior_h<T, MODE>(A, r, br, o1, o2);
+      if (MODE == kJoint) P = lds_row_sum(P, s_Pn, lo, hi);
+      if (MODE == kJoint || MODE == kHOnly) h = lds_row_sum(h, s_hn, lo, hi);
+      cn_publish<T, MODE>(A, r, o1, P, h);
       if (A.check) {
-        double acc = (double)br - (double)chk_d(r, dr) * (double)mean_of<T, MODE>(A, o1);
-        for (int j = lo; j < hi; ++j) acc -= (double)s_ax[j];
+        double acc = (double)br - (double)cn_chk_d(A, r, dr) * (double)mean_of<T, MODE>(A, o1);
+        acc = lds_row_sub(acc, s_ax, lo, hi);
         res2 = acc * acc;
       }
     }
@@ -358,16 +396,59 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
   }
 }
 
+// Finish of the long rows, one wave each: the chunks' partial sums are added
+// in a fixed order (lane-strided, then a butterfly), and the row epilogue of
+// the sweep follows, including the row's squared residual in the partial of
+// the partition workgroup that holds the row.
+template <typename T, int MODE>
+__global__ __launch_bounds__(64) void k_cnode_long(CnodeArgs<T> A) {
+  if (A.st->done) return;
+  const LongRow L = A.longs[blockIdx.x];
+  const int lane = threadIdx.x;
+  T sP = 0, sh = 0;
+  double sax = 0.0;
+  for (int j = lane; j < L.nch; j += 64) {
+    const double* q = A.lpart + 4 * (size_t)(L.cbase + j);
+    sP += (T)q[0];
+    sh += (T)q[1];
+    sax += q[2];
+  }
+  sP = wsum_c(sP);
+  sh = wsum_c(sh);
+  sax = wsum_c(sax);
+  if (lane == 0) {
+    const int r = L.row;
+    const bool need_o2 = (MODE == kJoint || MODE == kHOnly || MODE == kFreeze) && !A.first;
+    const Msg<T> o1 = ld_agg<T>(A.agg1, r);
+    const Msg<T> o2 = need_o2 ? ld_agg<T>(A.agg2, r) : Msg<T>{0, 0};
+    const T dr = A.diag[r], br = A.rhs[r];
+    cn_publish<T, MODE>(A, r, o1, dr + sP, cn_prior_h<T, MODE>(A, r, br, o1, o2) + sh);
+    if (A.check) {
+      const double acc = (double)br - (double)cn_chk_d(A, r, dr) * (double)mean_of<T, MODE>(A, o1) - sax;
+      A.partials[L.blk] = acc * acc;
+    }
+  }
+}
+
 template <typename T, int K>
 hipError_t launch_ck(int mode, const CnodeArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const uint32_t lds = (uint32_t)cn_lds(K, sizeof(T));
-  const dim3 grid(a.nblk), block(kBlock);
+  const dim3 grid(a.nblk + a.nxch), block(kBlock);
   switch (mode) {
     case kJoint: hipExtLaunchKernelGGL((k_cnode<T, K, kJoint>), grid, block, lds, s, ev0, ev1, 0, a); break;
     case kHOnly: hipExtLaunchKernelGGL((k_cnode<T, K, kHOnly>), grid, block, lds, s, ev0, ev1, 0, a); break;
     case kFreeze: hipExtLaunchKernelGGL((k_cnode<T, K, kFreeze>), grid, block, lds, s, ev0, ev1, 0, a); break;
     case kResid: hipExtLaunchKernelGGL((k_cnode<T, K, kResid>), grid, block, lds, s, ev0, ev1, 0, a); break;
     default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nlong == 0) return e;
+  const dim3 lg(a.nlong), lb(64);
+  switch (mode) {
+    case kJoint: hipLaunchKernelGGL((k_cnode_long<T, kJoint>), lg, lb, 0, s, a); break;
+    case kHOnly: hipLaunchKernelGGL((k_cnode_long<T, kHOnly>), lg, lb, 0, s, a); break;
+    case kFreeze: hipLaunchKernelGGL((k_cnode_long<T, kFreeze>), lg, lb, 0, s, a); break;
+    case kResid: hipLaunchKernelGGL((k_cnode_long<T, kResid>), lg, lb, 0, s, a); break;
   }
   return hipGetLastError();
 }

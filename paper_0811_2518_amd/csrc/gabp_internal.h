@@ -99,6 +99,58 @@ struct BcastArgs {
   int32_t honly_nodes;     // residual-only launch after frozen-precision sweeps
 };
 
+// The local row index of each of a row's slots, s_row[lo .. hi) = row.  The
+// bounds are passed in registers: read from LDS inside the loop, they would be
+// reloaded after every byte store (the stores might alias them).
+__device__ __forceinline__ void fill_row_ids(uint8_t* s_row, int lo, int hi, int row) {
+  for (int j = lo; j < hi; ++j) s_row[j] = (uint8_t)row;
+}
+
+// Row sums over a lane's slots in LDS, added in slot order (the rounding of
+// the plain loop) with the loads of eight slots issued ahead of their
+// additions: a lane summing a row of hundreds of slots otherwise waits out
+// one LDS round trip per slot.
+template <typename Acc, typename V>
+__device__ __forceinline__ Acc lds_row_sum(Acc acc, const V* s, int lo, int hi) {
+  int j = lo;
+  for (; j + 8 <= hi; j += 8) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = s[j + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (Acc)v[u];
+  }
+  for (; j < hi; ++j) acc += (Acc)s[j];
+  return acc;
+}
+// The same for acc - s[lo] - s[lo + 1] - ...
+template <typename Acc, typename V>
+__device__ __forceinline__ Acc lds_row_sub(Acc acc, const V* s, int lo, int hi) {
+  int j = lo;
+  for (; j + 8 <= hi; j += 8) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = s[j + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc -= (Acc)v[u];
+  }
+  for (; j < hi; ++j) acc -= (Acc)s[j];
+  return acc;
+}
+
+// A row with more slots than one workgroup takes (256 K) is swept in chunks
+// of 256 K slots, one workgroup each, launched after the partition's
+// workgroups; a finish kernel then adds the chunks' partial row sums in a
+// fixed order.  The partition's own workgroup of such a row does nothing.
+struct LongRow {
+  int32_t row, blk;    // the row, and the partition workgroup that holds it
+  int32_t e0, ne;      // its slots
+  int32_t cbase, nch;  // its chunks: partial-sum records cbase .. cbase + nch - 1
+};
+struct ChunkRef {
+  int32_t li, c;       // long row, chunk of it
+};
+
 // Arguments of one compact node-broadcast sweep launch (compact.hip).
 template <typename T>
 struct CnodeArgs {
@@ -128,6 +180,10 @@ struct CnodeArgs {
                            //   ((1 - s) x^(t-2) + s x^(t-1)), joint sweeps only
   double* partials;
   DevStatus* st;
+  const LongRow* longs;    // [nlong] rows swept in chunks (nullable)
+  const ChunkRef* xch;     // [nxch] chunk workgroups, launched after the nblk partition workgroups
+  double* lpart;           // [chunks][4] partial row sums of the chunks
+  int32_t nlong, nxch;
   int32_t nblk;
   int32_t first;           // t == 1 (freeze: T == 0): no outgoing message yet
   int32_t second;          // t == 2 (freeze: T == 1): the incoming messages of round t-2 are zero
@@ -154,6 +210,10 @@ struct SerialArgs {
   T* ptout;                // [n] P~ of this sweep (nullable)
   double* partials;        // [all workgroups] squared residual sums
   DevStatus* st;
+  const LongRow* longs;    // rows swept in chunks (nullable)
+  const ChunkRef* xch;     // chunk workgroups of all classes
+  double* lpart;           // [chunks][4] partial sums of the chunks
+  int32_t xch0, nxch;      // this launch's chunk workgroups: xch[xch0 .. xch0 + nxch)
   int32_t blk0;            // first workgroup of the class
   int32_t nblk;            // workgroups of the class
   int32_t lo, hi;          // rows of the class
@@ -203,6 +263,15 @@ struct Ctx {
   int32_t* blk_e0_d = nullptr;  // first slot of each workgroup (same allocation as blk_row_d)
   int32_t nblk_capacity = 0;
   int32_t partials_capacity = 0;
+  // rows longer than one workgroup's slots, swept in chunks (compact and
+  // colour-serial layouts)
+  std::vector<LongRow> longs_h;
+  std::vector<int32_t> long_xch0;  // colour-serial: first chunk workgroup of each class ([ncol + 1])
+  LongRow* longs_d = nullptr;
+  ChunkRef* xch_d = nullptr;
+  double* lpart_d = nullptr;
+  int32_t nlong = 0, nxch = 0;
+  int32_t longs_capacity = 0, xch_capacity = 0;
   std::vector<int32_t> off_ptr_h;
 
   // message buffers (double-buffered), frozen precisions
@@ -282,6 +351,9 @@ gabp_status dev_alloc(Ctx* c, void** p, size_t bytes);
 gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const double* vals,
                    const int32_t* sys_row_off_d, int32_t num_sys);
 gabp_status build_partition(const Ctx* c, int K, std::vector<int32_t>& blk_row);
+gabp_status set_long_rows(Ctx* c, int K, const std::vector<int32_t>& br);
+void plan_long_rows(const std::vector<int32_t>& op, const std::vector<int32_t>& br, int32_t nb, int K,
+                    std::vector<LongRow>& lr, std::vector<ChunkRef>& xc, std::vector<int32_t>& xch_of_blk);
 gabp_status set_partition(Ctx* c, int K);
 // host part of set_partition: workgroup starts (then n) and, with XCD parts,
 // the first workgroup of every group of parts (then the count)

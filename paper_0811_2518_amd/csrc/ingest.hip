@@ -346,6 +346,64 @@ gabp_status set_partition(Ctx* c, int K) {
     c->partials_d = (double*)p;
     c->partials_capacity = nb;
   }
+  return set_long_rows(c, K, br);
+}
+
+// The long rows of a partition (more than 256 K slots, a workgroup of their
+// own) and their chunk workgroups, in workgroup order, so that the chunks of
+// one colour class's long rows are a contiguous range.  br: the first rows of
+// the nb + 1 workgroups; op: the off-diagonal row pointers in that order.
+// xch_of_blk[i]: chunk workgroups before workgroup i.
+void plan_long_rows(const std::vector<int32_t>& op, const std::vector<int32_t>& br, int32_t nb, int K,
+                    std::vector<LongRow>& lr, std::vector<ChunkRef>& xc, std::vector<int32_t>& xch_of_blk) {
+  const int64_t S = (int64_t)kBlock * K;
+  lr.clear();
+  xc.clear();
+  xch_of_blk.assign((size_t)nb + 1, 0);
+  int32_t chunks = 0;
+  for (int32_t i = 0; i < nb; ++i) {
+    xch_of_blk[i] = (int32_t)xc.size();
+    const int32_t e0 = op[br[i]], e1 = op[br[i + 1]];
+    if (e1 - e0 <= S) continue;
+    LongRow L{br[i], i, e0, e1 - e0, chunks, (int32_t)((e1 - e0 + S - 1) / S)};
+    for (int32_t k = 0; k < L.nch; ++k) xc.push_back(ChunkRef{(int32_t)lr.size(), k});
+    chunks += L.nch;
+    lr.push_back(L);
+  }
+  xch_of_blk[nb] = (int32_t)xc.size();
+}
+
+gabp_status set_long_rows(Ctx* c, int K, const std::vector<int32_t>& br) {
+  std::vector<LongRow> lr;
+  std::vector<ChunkRef> xc;
+  std::vector<int32_t> xch_of_blk;
+  plan_long_rows(c->off_ptr_h, br, c->nblk, K, lr, xc, xch_of_blk);
+  c->long_xch0.clear();
+  for (int32_t b : c->colour_blk) c->long_xch0.push_back(xch_of_blk[b]);
+  c->nlong = (int32_t)lr.size();
+  c->nxch = (int32_t)xc.size();
+  if (!lr.empty()) {
+    if (c->longs_d == nullptr || c->nlong > c->longs_capacity) {
+      void* p = nullptr;
+      GABP_TRY(dev_alloc(c, &p, sizeof(LongRow) * lr.size()));
+      c->longs_d = (LongRow*)p;
+      c->longs_capacity = c->nlong;
+    }
+    if (c->xch_d == nullptr || c->nxch > c->xch_capacity) {
+      void* p = nullptr;
+      GABP_TRY(dev_alloc(c, &p, sizeof(ChunkRef) * xc.size()));
+      c->xch_d = (ChunkRef*)p;
+      GABP_TRY(dev_alloc(c, &p, 4 * sizeof(double) * xc.size()));
+      c->lpart_d = (double*)p;
+      c->xch_capacity = c->nxch;
+    }
+    GABP_HIP(c, hipMemcpyAsync(c->longs_d, lr.data(), sizeof(LongRow) * lr.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    GABP_HIP(c, hipMemcpyAsync(c->xch_d, xc.data(), sizeof(ChunkRef) * xc.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    GABP_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  c->longs_h.swap(lr);
   return GABP_OK;
 }
 

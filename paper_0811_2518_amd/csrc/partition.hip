@@ -4,7 +4,8 @@
 // aggregates at random.  When the rows one XCD processes have many of their
 // neighbours among themselves, those gathers stay in that XCD's L2.  So at
 // create time:
-//   1. The nodes are split into 8 parts of equal work (slots + rows).  The
+//   1. The nodes are split into 8 parts of equal work (slots + rows; a long
+//      row, swept in chunks spread over all XCDs, counts as a row).  The
 //      parts are grown breadth-first from 8 seeds, then refined by label
 //      propagation: a node moves to the part holding most of its neighbours,
 //      within a 2% balance margin, until a pass moves fewer than 0.1% of
@@ -34,6 +35,7 @@ constexpr double kBalance = 0.02;  // allowed deviation of a part's work from th
 constexpr int kRefine = 8;         // label-propagation passes
 constexpr int64_t kMinSlots = 4096;
 constexpr double kMinGain = 0.10;  // required rise of the fraction of edges inside the parts
+constexpr int64_t kLongRow = 2 * kBlock;  // slots of the smallest workgroup budget
 
 double inside_fraction(const std::vector<int32_t>& op, const std::vector<int32_t>& col,
                        const std::vector<int32_t>& part) {
@@ -55,9 +57,15 @@ bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_
   if (E < kMinSlots || n < 4 * kParts) return false;
   const std::vector<int32_t>& op = c->off_ptr_h;
 
+  // work of a row: its slots and itself; a row longer than the smallest
+  // workgroup budget is swept by chunk workgroups spread over every XCD, so
+  // it weighs as one row in its part
   std::vector<int64_t> w(n);
   int64_t total = 0;
-  for (int32_t i = 0; i < n; ++i) total += (w[i] = op[i + 1] - op[i] + 1);
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t d = op[i + 1] - op[i];
+    total += (w[i] = (d > kLongRow ? 0 : d) + 1);
+  }
   const double target = (double)total / kParts;
 
   // the caller's order cut into 8 ranges of equal work

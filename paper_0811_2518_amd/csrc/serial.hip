@@ -109,6 +109,162 @@ __host__ __device__ constexpr size_t sr_lds(int K, int elt) {
          sizeof(int32_t) * (kMaxRowsPerBlock + 4);
 }
 
+// Pass 1 over one chunk (at most 256 K slots) of a long row: the pulled
+// messages, kept in their slots until pass 2, and the chunk's partial sums of
+// P, h and the two residual parts (earlier and later classes) in lpart.
+template <typename T, int K, bool RESID>
+__device__ __forceinline__ void serial_chunk(const SerialArgs<T>& A, const LongRow& L, int ci, double* s_red,
+                                             T* s_redT) {
+  constexpr int S = kBlock * K;
+  const int tid = threadIdx.x;
+  const int e0 = L.e0 + ci * S;
+  const int ne = min(S, L.ne - ci * S);
+  const bool check = RESID || A.check;
+  int c[K];
+  T av[K];
+  Msg<T> m[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    c[k] = 0;
+    av[k] = 0;
+    m[k] = Msg<T>{0, 0};
+    if (i < ne) {
+      c[k] = __builtin_nontemporal_load(A.col + e0 + i);
+      av[k] = __builtin_nontemporal_load(A.a + e0 + i);
+      if (!RESID && !A.first) m[k] = ld_pair_nt<T>(A.out, e0 + i);
+    }
+  }
+  Msg<T> g[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) g[k] = ld_pair<T>(A.agg, c[k]);
+  }
+  T pP = 0, ph = 0;
+  double pl = 0.0, pu = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) {
+      const bool lower = c[k] < A.lo;
+      if (!RESID) {
+        Msg<T> in{0, 0};
+        if (!A.first || lower) in = pass<T>(av[k], g[k], m[k]);
+        st_pair_nt<T>(A.out, e0 + i, in.P, in.h);
+        pP += in.P;
+        ph += in.h;
+        bad |= !(isfinite(in.P) && isfinite(in.h));
+      }
+      if (lower ? (!RESID && A.wl) : check) {
+        const double ax = (double)(av[k] * (g[k].h / g[k].P));
+        if (lower) pl += ax;
+        else pu += ax;
+      }
+    }
+  }
+  if (bad) {
+    atomicOr(&A.st->error, kErrNonfinite);
+    atomicExch(&A.st->done, 1);
+  }
+  pP = bsum_s(pP, s_redT);
+  ph = bsum_s(ph, s_redT);
+  pl = bsum_s(pl, s_red);
+  pu = bsum_s(pu, s_red);
+  if (tid == 0) {
+    double* q = A.lpart + 4 * (size_t)(L.cbase + ci);
+    q[0] = (double)pP;
+    q[1] = (double)ph;
+    q[2] = pl;
+    q[3] = pu;
+  }
+}
+
+// Finish and pass 2 of the long rows, one workgroup per chunk.  Every
+// workgroup of a row adds the row's chunk sums in the same fixed order
+// (lane-strided, then a butterfly), so all hold the same new aggregate.  The
+// chunk-0 workgroup publishes it and the residual term of the previous sweep;
+// every workgroup then replaces the pulled messages of its chunk by the
+// outgoing ones, out_{j->i} = F(agg_j, in_{i->j}).
+template <typename T, int K, bool RESID>
+__global__ __launch_bounds__(kBlock) void k_serial_long(SerialArgs<T> A) {
+  constexpr int S = kBlock * K;
+  __shared__ double s_tot[4];
+  if (A.st->done) return;
+  const int tid = threadIdx.x;
+  const ChunkRef x = A.xch[A.xch0 + blockIdx.x];
+  const LongRow L = A.longs[x.li];
+  const int r = L.row;
+  const bool check = RESID || A.check;
+  // the row's aggregate and earlier-class residual part of the previous sweep,
+  // loaded before the barrier below, so that they have arrived before this
+  // workgroup overwrites them
+  Msg<T> o{1, 0};
+  double lold = 0.0;
+  if (x.c == 0 && tid == 0) {
+    if (check) o = ld_pair<T>(A.agg, r);
+    if (!RESID && A.check) lold = A.lsum[r];
+  }
+  if (tid < 64) {
+    T sP = 0, sh = 0;
+    double sl = 0.0, su = 0.0;
+    for (int j = tid; j < L.nch; j += 64) {
+      const double* q = A.lpart + 4 * (size_t)(L.cbase + j);
+      sP += (T)q[0];
+      sh += (T)q[1];
+      sl += q[2];
+      su += q[3];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      sP += __shfl_xor(sP, off, 64);
+      sh += __shfl_xor(sh, off, 64);
+      sl += __shfl_xor(sl, off, 64);
+      su += __shfl_xor(su, off, 64);
+    }
+    if (tid == 0) {
+      s_tot[0] = (double)sP;
+      s_tot[1] = (double)sh;
+      s_tot[2] = sl;
+      s_tot[3] = su;
+    }
+  }
+  __syncthreads();
+  const T dr = A.diag[r], br = A.rhs[r];
+  const Msg<T> an{dr + (T)s_tot[0], br + (T)s_tot[1]};
+  if (x.c == 0 && tid == 0) {
+    if (!RESID) {
+      st_pair<T>(A.agg, r, an.P, an.h);
+      if (A.xout) A.xout[r] = an.h / an.P;
+      if (A.ptout) A.ptout[r] = an.P;
+      if (A.wl) A.lsum[r] = s_tot[2];
+    }
+    if (check) {
+      const double acc = (double)br - (double)dr * (double)(o.h / o.P) - lold - s_tot[3];
+      A.partials[L.blk] = acc * acc;
+    }
+  }
+  if (RESID) return;
+  const int e0 = L.e0 + x.c * S;
+  const int ne = min(S, L.ne - x.c * S);
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = tid + k * kBlock;
+    if (i < ne) {
+      const Msg<T> in = ld_pair_nt<T>(A.out, e0 + i);
+      const Msg<T> out = pass<T>(__builtin_nontemporal_load(A.a + e0 + i), an, in);
+      st_pair_nt<T>(A.out, e0 + i, out.P, out.h);
+      bad |= !(isfinite(out.P) && isfinite(out.h));
+    }
+  }
+  if (bad) {
+    atomicOr(&A.st->error, kErrNonfinite);
+    atomicExch(&A.st->done, 1);
+  }
+}
+
 // RESID: residual of the current means only (every node at the same sweep),
 // all workgroups, no update.
 template <typename T, int K, bool RESID>
@@ -118,6 +274,11 @@ __global__ __launch_bounds__(kBlock) void k_serial(SerialArgs<T> A) {
   __shared__ double s_red[kBlock / 64];
   __shared__ T s_redT[kBlock / 64];
   if (A.st->done) return;
+  if ((int)blockIdx.x >= A.nblk) {  // a chunk of a long row
+    const ChunkRef x = A.xch[A.xch0 + blockIdx.x - A.nblk];
+    serial_chunk<T, K, RESID>(A, A.longs[x.li], x.c, s_red, s_redT);
+    return;
+  }
 
   const int tid = threadIdx.x;
   const int b = A.blk0 + xcd_remap_s(blockIdx.x, A.nblk);
@@ -128,63 +289,9 @@ __global__ __launch_bounds__(kBlock) void k_serial(SerialArgs<T> A) {
   double res2 = 0.0;
   bool bad = false;
 
-  if (ne > S) {  // one long row: strided slots, block reductions, two passes
-    const Msg<T> o = ld_pair<T>(A.agg, r0);
-    const T dr = A.diag[r0], br = A.rhs[r0];
-    T pP = 0, ph = 0;
-    double pl = 0.0, pu = 0.0;
-    for (int i = tid; i < ne; i += kBlock) {
-      const int s = e0 + i;
-      const int c = A.col[s];
-      const T av = A.a[s];
-      const Msg<T> g = ld_pair<T>(A.agg, c);
-      const bool lower = c < A.lo;
-      if (!RESID) {
-        Msg<T> in{0, 0};
-        if (!A.first || lower) in = pass<T>(av, g, A.first ? Msg<T>{0, 0} : ld_pair_nt<T>(A.out, s));
-        pP += in.P;
-        ph += in.h;
-        bad |= !(isfinite(in.P) && isfinite(in.h));
-      }
-      if (lower ? (!RESID && A.wl) : check) {
-        const double ax = (double)(av * (g.h / g.P));
-        if (lower) pl += ax;
-        else pu += ax;
-      }
-    }
-    pu = bsum_s(pu, s_red);
-    if (!RESID) {
-      pP = bsum_s(pP, s_redT);
-      ph = bsum_s(ph, s_redT);
-      pl = bsum_s(pl, s_red);
-      const Msg<T> an{dr + pP, br + ph};
-      if (tid == 0) {
-        st_pair<T>(A.agg, r0, an.P, an.h);
-        if (A.xout) A.xout[r0] = an.h / an.P;
-        if (A.ptout) A.ptout[r0] = an.P;
-        if (A.wl) A.lsum[r0] = pl;
-      }
-      // second pass: the same slots, the pulled messages recomputed
-      for (int i = tid; i < ne; i += kBlock) {
-        const int s = e0 + i;
-        const int c = A.col[s];
-        const T av = A.a[s];
-        const bool lower = c < A.lo;
-        Msg<T> in{0, 0};
-        if (!A.first || lower) {
-          const Msg<T> g = ld_pair<T>(A.agg, c);
-          in = pass<T>(av, g, A.first ? Msg<T>{0, 0} : ld_pair_nt<T>(A.out, s));
-        }
-        const Msg<T> out = pass<T>(av, an, in);
-        st_pair_nt<T>(A.out, s, out.P, out.h);
-        bad |= !(isfinite(out.P) && isfinite(out.h));
-      }
-    }
-    if (tid == 0 && check) {
-      const double acc = (double)br - (double)dr * (double)(o.h / o.P) - (RESID ? 0.0 : A.lsum[r0]) - pu;
-      res2 = acc * acc;
-    }
-  } else {
+  // a long row is swept by its chunk workgroups and finished by k_serial_long
+  if (ne > S) return;
+  {
     T* s_Pn = (T*)smem;
     T* s_hn = s_Pn + S;
     double* s_ax = (double*)(s_hn + S);
@@ -233,8 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_serial(SerialArgs<T> A) {
     if (tid < nrow) s_ptr[tid] = rp;
     if (tid == 0) s_ptr[nrow] = ne;
     __syncthreads();
-    if (tid < nrow)
-      for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) s_row[j] = (uint8_t)tid;
+    if (tid < nrow) fill_row_ids(s_row, s_ptr[tid], s_ptr[tid + 1], tid);
 
     // 4. pulled messages and residual terms
     Msg<T> in[K];
@@ -259,17 +365,31 @@ __global__ __launch_bounds__(kBlock) void k_serial(SerialArgs<T> A) {
     // 5. row sums: diagonal first, then the slots in CSR order
     if (tid < nrow) {
       const int lo = s_ptr[tid], hi = s_ptr[tid + 1];
+      // the earlier and the later classes' terms, each added in slot order,
+      // eight slots loaded ahead
       double L = 0.0, U = 0.0;
-      for (int j = lo; j < hi; ++j) {
+      int j = lo;
+      for (; j + 8 <= hi; j += 8) {
+        double v[8];
+        uint8_t w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          v[u] = s_ax[j + u];
+          w[u] = s_low[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (w[u]) L += v[u];
+          else U += v[u];
+        }
+      }
+      for (; j < hi; ++j) {
         if (s_low[j]) L += s_ax[j];
         else U += s_ax[j];
       }
       if (!RESID) {
-        T P = dr, h = br;
-        for (int j = lo; j < hi; ++j) {
-          P += s_Pn[j];
-          h += s_hn[j];
-        }
+        T P = lds_row_sum(dr, s_Pn, lo, hi);
+        T h = lds_row_sum(br, s_hn, lo, hi);
         st_pair<T>(A.agg, r, P, h);
         if (A.xout) A.xout[r] = h / P;
         if (A.ptout) A.ptout[r] = P;
@@ -330,8 +450,13 @@ __global__ void k_scatter_slots(const double* __restrict__ src, const int32_t* _
 template <typename T, int K>
 hipError_t launch_sk(const SerialArgs<T>& a, bool resid, hipStream_t s) {
   const uint32_t lds = (uint32_t)sr_lds(K, sizeof(T));
-  if (resid) hipLaunchKernelGGL((k_serial<T, K, true>), dim3(a.nblk), dim3(kBlock), lds, s, a);
-  else hipLaunchKernelGGL((k_serial<T, K, false>), dim3(a.nblk), dim3(kBlock), lds, s, a);
+  const dim3 grid(a.nblk + a.nxch);
+  if (resid) hipLaunchKernelGGL((k_serial<T, K, true>), grid, dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL((k_serial<T, K, false>), grid, dim3(kBlock), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nxch == 0) return e;
+  if (resid) hipLaunchKernelGGL((k_serial_long<T, K, true>), dim3(a.nxch), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_serial_long<T, K, false>), dim3(a.nxch), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

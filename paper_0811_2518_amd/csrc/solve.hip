@@ -284,6 +284,16 @@ void* cin_buf(const Ctx* c, int parity) {
   return (char*)c->bstate_d + (parity & 1) * 2 * sizeof(T) * (size_t)c->E;
 }
 
+// The partition's long rows and their chunk workgroups.
+template <typename T>
+void set_long_rows(const Ctx* c, CnodeArgs<T>& k) {
+  k.longs = c->longs_d;
+  k.xch = c->xch_d;
+  k.lpart = c->lpart_d;
+  k.nlong = c->nlong;
+  k.nxch = c->nxch;
+}
+
 // Compact node layout: like run_node, sweep t publishes round t and checks
 // round t-1; rounds 1..M, then a residual-only launch for round M.
 template <typename T>
@@ -307,6 +317,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   a.partials = c->partials_d;
   a.st = cfg.st;
   a.nblk = c->nblk;
+  set_long_rows<T>(c, a);
   a.honly_nodes = cfg.honly ? 1 : 0;
   a.feedback = cfg.feedback ? 1 : 0;
   a.damp = (T)cfg.damp;
@@ -376,6 +387,10 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
   bool tiled = (int)c->colour_blk.size() == c->ncol + 1 && (int)c->colour_start.size() == c->ncol + 1 &&
                c->ncol > 0 && c->colour_blk[0] == 0 && c->colour_blk[c->ncol] == c->nblk;
   for (int q = 0; tiled && q < c->ncol; ++q) tiled = c->colour_blk[q] <= c->colour_blk[q + 1];
+  // and the classes' chunk workgroups the chunk list
+  tiled = tiled && (int)c->long_xch0.size() == c->ncol + 1 && c->long_xch0[0] == 0 &&
+          c->long_xch0[c->ncol] == c->nxch;
+  for (int q = 0; tiled && q < c->ncol; ++q) tiled = c->long_xch0[q] <= c->long_xch0[q + 1];
   if (!tiled) return fail(c, GABP_E_ARG, "colour classes do not tile the workgroup partition");
 
   SerialArgs<T> a{};
@@ -391,6 +406,9 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
   a.lsum = c->lsum_d;
   a.partials = c->partials_d;
   a.st = cfg.st;
+  a.longs = c->longs_d;
+  a.xch = c->xch_d;
+  a.lpart = c->lpart_d;
   GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
 
   if (M == 0) {  // the prior means b_i / P_ii
@@ -401,6 +419,8 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
       SerialArgs<T> k = a;
       k.blk0 = 0;
       k.nblk = c->nblk;
+      k.xch0 = 0;
+      k.nxch = c->nxch;
       k.check = 1;
       GABP_HIP(c, launch_serial<T>(k, c->K, true, s));
       GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, 0, nullptr, true, s));
@@ -422,6 +442,8 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
         SerialArgs<T> k = a;
         k.blk0 = 0;
         k.nblk = c->nblk;
+        k.xch0 = 0;
+        k.nxch = c->nxch;
         k.check = 1;
         GABP_HIP(c, launch_serial<T>(k, c->K, true, s));
       } else {
@@ -436,6 +458,8 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
           SerialArgs<T> k = a;
           k.blk0 = c->colour_blk[q];
           k.nblk = c->colour_blk[q + 1] - c->colour_blk[q];
+          k.xch0 = c->long_xch0[q];
+          k.nxch = c->long_xch0[q + 1] - c->long_xch0[q];
           k.lo = c->colour_start[q];
           k.hi = c->colour_start[q + 1];
           k.first = (t == 1);
@@ -532,6 +556,7 @@ gabp_status freeze(Ctx* c, int round, const void* diag, const void* rhs, int pre
     k.partials = c->partials_d;
     k.st = st;
     k.nblk = c->nblk;
+    set_long_rows<T>(c, k);
     GABP_HIP(c, launch_cnode<T>(kFreeze, c->K, k, c->stream));
   } else if (c->layout == kLayoutNode) {
     BcastArgs<T> k{};

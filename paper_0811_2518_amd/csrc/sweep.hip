@@ -301,11 +301,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
       if (MODE != kResid) {
         T Pt = kJointLike ? A.diag[r] : T(0);
         T ht = A.rhs[r];
-        for (int j = lo; j < hi; ++j) {
-          if (kJointLike) Pt += s_P[j];
-          ht += s_h[j];
-          s_row[j] = (uint8_t)tid;
-        }
+        fill_row_ids(s_row, lo, hi, tid);
+        if (kJointLike) Pt = lds_row_sum(Pt, s_P, lo, hi);
+        ht = lds_row_sum(ht, s_h, lo, hi);
         const T xr = (MODE == kHOnly) ? ht * A.inv_pt[r] : ht / Pt;
         s_ht[tid] = ht;
         s_Pt[tid] = Pt;
@@ -316,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs<T> A) {
       }
       if (A.check) {
         double acc = (double)A.rhs[r] - (double)A.diag[r] * (double)A.xchk[r];
-        for (int j = lo; j < hi; ++j) acc -= (double)s_ax[j];
+        acc = lds_row_sub(acc, s_ax, lo, hi);
         res2 = acc * acc;
       }
     }
@@ -450,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
     if (tid < nrow) {
       const int r = r0 + tid;
       double res = A.b[r] - A.diag[r] * x[r];
-      for (int j = s_ptr[tid]; j < s_ptr[tid + 1]; ++j) res -= s_ax[j];
+      res = lds_row_sub(res, s_ax, s_ptr[tid], s_ptr[tid + 1]);
       if (A.rin32) A.rin32[r] = (float)res;
       if (A.rin64) A.rin64[r] = res;
       res2 = res * res;

@@ -185,6 +185,23 @@ def test_batched_serial_odd_systems_and_replay():
     assert [i["sweeps"] for i in infos2] == [i["sweeps"] for i in infos]
 
 
+@pytest.mark.parametrize("layout", ["auto", "serial"])
+def test_batched_powerlaw_systems(layout):
+    # heavy-tailed degrees: hub rows longer than a tile's chunk, isolated
+    # nodes, and (serial) two to three dozen colour classes per system
+    probs = [workloads.powerlaw_problem(n, 8, 300 + i, beta=2.1)
+             for i, n in enumerate([3000, 1200, 2500, 400, 1800])]
+    bt = workloads.batch_of(probs, [4, 1, 11, 2, 7], seed=31)
+    s, B, X, infos, st = _solve(bt, layout=layout)
+    assert st == binding.OK
+    _check_against_dense(bt, X, infos)
+    if layout == "serial":
+        col, k = s.colours()
+        ref = oracle.greedy_colouring(int(bt.sys_row_off[-1]), bt.row_ptr, bt.col)
+        np.testing.assert_array_equal(col, ref)
+        assert k >= 20
+
+
 def test_batched_serial_groups_not_dividing_the_workgroup():
     rng = np.random.default_rng(13)
     probs, ks = [], []

@@ -85,6 +85,9 @@ CASES = {
     "grid3d_10": lambda: workloads.grid3d_problem(10, 79),
     "tree": lambda: workloads.random_tree(777, 80),
     "star_long_row": lambda: workloads.star_problem(5000, 81),
+    # heavy-tailed degrees: rows longer than a workgroup's slot budget (up to
+    # 2113 slots) scattered through the row order, and isolated nodes
+    "powerlaw": lambda: workloads.powerlaw_problem(8000, 8, 90, beta=2.1),
 }
 
 
@@ -256,7 +259,7 @@ def test_non_walk_summable_diverges_without_loading(layout):
 # FP32 messages with FP64 refinement; diagonal loading (Ch. 5)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["grid32", "er_ragged", "grid3d_10", "star_long_row"])
+@pytest.mark.parametrize("name", ["grid32", "er_ragged", "grid3d_10", "star_long_row", "powerlaw"])
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_fp32_refine_reaches_fp64_accuracy(name, layout):
     p = CASES[name]()

@@ -48,9 +48,11 @@ def xcd_of_rows(plan, groups):
     return owner
 
 
+@pytest.mark.parametrize("graph", ["er", "powerlaw"])
 @pytest.mark.parametrize("epb", [512, 2048])
-def test_xcd_order_on_a_random_graph(epb):
-    p = workloads.er_problem(20000, 8, 93)
+def test_xcd_order_on_a_random_graph(epb, graph):
+    p = (workloads.er_problem(20000, 8, 93) if graph == "er"
+         else workloads.powerlaw_problem(20000, 8, 94, beta=2.1))
     plan = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb)
     assert plan["xcd_parts"] == 8 and plan["num_colours"] == 0
     assert sorted(plan["perm"]) == list(range(p.n))
@@ -64,7 +66,11 @@ def test_xcd_order_on_a_random_graph(epb):
     inside = np.mean(owner[r] == owner[c])
     natural = np.mean((rows[off] * 8 // p.n) == (p.col[off] * 8 // p.n))
     assert inside >= natural + 0.10, (inside, natural)
-    work = np.bincount(owner[plan["perm"]], weights=np.diff(p.row_ptr).astype(float), minlength=8)
+    # (a row longer than 512 slots is swept by chunks spread over every XCD
+    # and weighs as one row)
+    deg = np.diff(p.row_ptr) - 1
+    weight = np.where(deg > 512, 0, deg) + 1.0
+    work = np.bincount(owner[plan["perm"]], weights=weight, minlength=8)
     assert work.max() <= 1.05 * work.mean()
     # without the XCD order: the caller's rows, no padding
     nat = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb, natural_order=True)
@@ -79,11 +85,12 @@ def test_grids_keep_the_caller_order():
         blocks_ok(p, plan, 512)
 
 
-@pytest.mark.parametrize("name", ["er", "grid", "tree", "star", "small_er"])
+@pytest.mark.parametrize("name", ["er", "grid", "tree", "star", "small_er", "powerlaw"])
 def test_serial_plan_colouring_is_the_oracles(name):
     p = {"er": workloads.er_problem(20000, 8, 96), "grid": workloads.grid2d_problem(40, 31, 3),
          "tree": workloads.random_tree(900, 5), "star": workloads.star_problem(3000, 2),
-         "small_er": workloads.er_problem(300, 5, 7)}[name]
+         "small_er": workloads.er_problem(300, 5, 7),
+         "powerlaw": workloads.powerlaw_problem(8000, 8, 90, beta=2.1)}[name]
     plan = binding.plan_rows(p.row_ptr, p.col, layout="serial")
     ref = oracle.greedy_colouring(p.n, p.row_ptr, p.col)
     np.testing.assert_array_equal(plan["colour"], ref)
@@ -100,7 +107,7 @@ def test_serial_plan_colouring_is_the_oracles(name):
         if hi > lo:
             assert col_int[lo] == col_int[hi - 1]
     if plan["xcd_parts"]:
-        assert name == "er"
+        assert name in ("er", "powerlaw")
         # every class launch is a group of 8q workgroups holding exactly the
         # class's rows, part x's rows in its x-th eighth
         cb = plan["class_blk"]
@@ -132,3 +139,26 @@ def test_plan_rejects_malformed_patterns():
     # out-of-range column
     with pytest.raises(binding.GabpError):
         binding.plan_rows(np.array([0, 2, 4], np.int32), np.array([0, 2, 0, 1], np.int32))
+
+
+@pytest.mark.parametrize("layout", ["auto", "serial"])
+@pytest.mark.parametrize("epb", [512, 2048])
+def test_long_rows_are_swept_in_chunks(epb, layout):
+    # a row with more than edges_per_block slots is its partition workgroup's
+    # only row, and is swept by ceil(slots / epb) chunk workgroups
+    p = workloads.powerlaw_problem(20000, 8, 94, beta=2.1)
+    plan = binding.plan_rows(p.row_ptr, p.col, layout=layout, edges_per_block=epb)
+    blocks_ok(p, plan, epb)
+    inv = np.empty(p.n, np.int64)
+    inv[plan["perm"]] = np.arange(p.n)
+    deg = (np.diff(p.row_ptr) - 1)[inv]
+    ptr = np.concatenate([[0], np.cumsum(deg)])
+    br = plan["blk_row"]
+    slots = ptr[br[1:]] - ptr[br[:-1]]
+    long_ = slots > epb
+    assert long_.sum() == np.sum(deg > epb) > 0
+    assert np.all(np.diff(br)[long_] == 1)
+    assert plan["num_chunks"] == int(np.sum(-(-slots[long_] // epb)))
+    # no long rows, no chunks
+    q = workloads.er_problem(5000, 8, 95)
+    assert binding.plan_rows(q.row_ptr, q.col, edges_per_block=epb)["num_chunks"] == 0

@@ -355,6 +355,49 @@ def _assemble(systems):
 # small structured cases used by the edge-case tests
 # ---------------------------------------------------------------------------
 
+def powerlaw_pairs(n, m, rng, beta=2.2):
+    """m distinct undirected pairs with a power-law degree distribution.
+
+    Chung-Lu style: both ends of a pair are drawn with probability proportional
+    to the node weight (i + 1)^(-1 / (beta - 1)), u == v and repeated pairs are
+    rejected, and the node labels are shuffled afterwards so that the heavy
+    rows land anywhere in the row order (as in a crawled web graph).
+    """
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (beta - 1.0))
+    cdf = np.cumsum(w / w.sum())
+    keys = np.empty(0, dtype=np.int64)
+    while len(keys) < m:
+        draw = int((m - len(keys)) * 1.3) + 16
+        u = np.minimum(np.searchsorted(cdf, rng.random(draw)), n - 1)
+        v = np.minimum(np.searchsorted(cdf, rng.random(draw)), n - 1)
+        ok = u != v
+        k = np.minimum(u, v)[ok] * n + np.maximum(u, v)[ok]
+        allk = np.concatenate([keys, k])
+        _, first = np.unique(allk, return_index=True)
+        first.sort()
+        keys = allk[first][:m]
+    label = rng.permutation(n).astype(np.int64)
+    return _sorted_pairs(np.stack([label[keys // n], label[keys % n]], 1))
+
+
+def powerlaw_problem(n, avg_degree, seed, beta=2.2, ratio=1.1, name="powerlaw"):
+    """Power-law random graph (degree exponent ``beta``), N(0,1) off-diagonals,
+    A_ii = ratio * sum|A_ij|, b ~ N(0,1): the heavy-tailed shape of the web and
+    social graphs the thesis runs on."""
+    rng = np.random.default_rng(seed)
+    pairs = powerlaw_pairs(n, (avg_degree * n) // 2, rng, beta)
+    w = rng.standard_normal(len(pairs))
+    rp, col, val = sym_csr_from_pairs(n, pairs[:, 0], pairs[:, 1], w, ratio)
+    b = rng.standard_normal(n)
+    return Problem(n, rp, col, val, b, name=name)
+
+
+def powerlaw_config(n=1 << 20):
+    """Power-law graph at the headline size: n nodes, 4n edges, degree exponent
+    2.1, N(0,1) off-diagonals, A_ii = 1.1 sum|A_ij|."""
+    return powerlaw_problem(n, 8, SEED_BASE + 6, beta=2.1, name=f"powerlaw-n{n}-deg8")
+
+
 def random_tree(n, seed, ratio=None, name="tree"):
     """Random recursive tree (node i attaches to a uniform earlier node).
 
