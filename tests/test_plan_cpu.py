@@ -54,6 +54,12 @@ def test_xcd_order_on_a_random_graph(epb, graph):
     p = (workloads.er_problem(20000, 8, 93) if graph == "er"
          else workloads.powerlaw_problem(20000, 8, 94, beta=2.1))
     plan = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb)
+    if graph == "powerlaw":
+        # the parts reach only about a third of the edges on a power-law
+        # graph, short of the required 25-point gain: the caller's order stays
+        assert plan["xcd_parts"] == 0 and np.array_equal(plan["perm"], np.arange(p.n))
+        blocks_ok(p, plan, epb)
+        return
     assert plan["xcd_parts"] == 8 and plan["num_colours"] == 0
     assert sorted(plan["perm"]) == list(range(p.n))
     blocks_ok(p, plan, epb)
@@ -65,7 +71,7 @@ def test_xcd_order_on_a_random_graph(epb, graph):
     r, c = plan["perm"][rows[off]], plan["perm"][p.col[off]]
     inside = np.mean(owner[r] == owner[c])
     natural = np.mean((rows[off] * 8 // p.n) == (p.col[off] * 8 // p.n))
-    assert inside >= natural + 0.10, (inside, natural)
+    assert inside >= natural + 0.25, (inside, natural)
     # (a row longer than 512 slots is swept by chunks spread over every XCD
     # and weighs as one row)
     deg = np.diff(p.row_ptr) - 1
