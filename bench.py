@@ -109,12 +109,15 @@ LAYOUT_NAMES = {1: "reverse-slot index", 2: "node broadcast", 3: "compact node b
 LAYOUT_KERNELS = {1: ("k_sweep", "k_sweep_fp64_joint"), 2: ("k_bcast", "k_bcast_fp64_joint"),
                   3: ("k_cnode", "k_cnode_fp64_joint"), 4: ("k_serial", "k_serial_fp64")}
 LAYOUT_SRC = {1: "sweep.hip", 2: "bcast.hip", 3: "compact.hip", 4: "serial.hip"}
-# counter entries of profiles/traffic.json: profiler kernel name (512 slots per
-# workgroup, FP64 joint sweep) and source file
-TRAFFIC_KERNELS = {"k_cnode_fp64_joint": ("k_cnode<double, 2, 0>", "compact.hip"),
-                   "k_bcast_fp64_joint": ("k_bcast<double, 2, 0>", "bcast.hip"),
-                   "k_sweep_fp64_joint": ("k_sweep<double, 2, 0>", "sweep.hip"),
-                   "k_serial_fp64": ("k_serial<double, 2, false>", "serial.hip")}
+# counter entries of profiles/traffic.json, one per layout and block size
+# (K = slots per lane, 256 K slots per workgroup): profiler kernel name of the
+# FP64 joint sweep and its source file
+TRAFFIC_KERNELS = {}
+for _K in (2, 4, 8):
+    TRAFFIC_KERNELS[f"k_cnode_fp64_joint_k{_K}"] = (f"k_cnode<double, {_K}, 0>", "compact.hip")
+    TRAFFIC_KERNELS[f"k_bcast_fp64_joint_k{_K}"] = (f"k_bcast<double, {_K}, 0>", "bcast.hip")
+    TRAFFIC_KERNELS[f"k_sweep_fp64_joint_k{_K}"] = (f"k_sweep<double, {_K}, 0>", "sweep.hip")
+    TRAFFIC_KERNELS[f"k_serial_fp64_k{_K}"] = (f"k_serial<double, {_K}, false>", "serial.hip")
 
 
 def kernel_bytes_of(layout, n, E, elt):
@@ -168,7 +171,7 @@ def traffic_from(fetch_dir, write_dir, n):
         idx = [i for i, r in enumerate(f) if kname in r["Kernel_Name"]]
         if not idx:
             continue
-        if tag == "k_serial_fp64":
+        if tag.startswith("k_serial_fp64"):
             # one sweep = one period of the repeating sequence of class grid sizes
             grids = [f[i]["Grid_Size"] for i in idx]
             P = next(p for p in range(1, len(grids) + 1)
@@ -213,13 +216,15 @@ def run_solves(torch, g, p, b, precision, steps, warmup, layout="auto"):
     return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs}
 
 
-def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto"):
+def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto", edges_per_block=0):
     """Per-sweep time of the checked FP64 joint sweep: slope between two
     fixed-length runs (tolerance below reach, so every sweep carries the fused
     check and nothing stops early), each timed with events around the whole
     call.  Includes the one-workgroup finish kernel and the dispatch gaps
-    (for the colour-serial layout: all class launches of a sweep)."""
-    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False, layout=layout)
+    (for the colour-serial layout: all class launches of a sweep).  Pass the
+    layout and block size a timed solve used to time that same kernel."""
+    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False, layout=layout,
+                 edges_per_block=edges_per_block)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     s.solve(b, tol=1e-300, max_iter=n1, x=x)
     best = {}
@@ -581,13 +586,17 @@ def probe(torch, g, workloads, args):
     del src, dst
     p = workloads.config2(args.n)
     b = torch.from_numpy(p.b).to("cuda")
-    for prec, layout in (("fp64", "compact"), ("fp64", "node"), ("fp64", "edge"), ("fp32", "compact"),
-                         ("fp64", "serial")):
+    # every block size of the layouts the autotuner picks for the timed solves,
+    # 512 slots per workgroup for the others
+    runs = [("fp64", "compact", epb) for epb in (512, 1024, 2048)] + \
+           [("fp64", "serial", epb) for epb in (512, 1024, 2048)] + \
+           [("fp64", "node", 512), ("fp64", "edge", 512), ("fp32", "compact", 512)]
+    for prec, layout, epb in runs:
         s = g.Solver(p.row_ptr, p.col, p.val, precision=prec, reuse_precision=False, layout=layout,
-                     edges_per_block=512)
+                     edges_per_block=epb)
         for _ in range(args.steps):
             _, info = s.solve(b, tol=TOL, max_iter=2000)
-        log(f"{prec}/{layout}: {info}")
+        log(f"{prec}/{layout}/{epb}: {info}")
         s.close()
     torch.cuda.synchronize()
 
@@ -635,12 +644,16 @@ def main():
     log("FP32 + FP64 refinement solves")
     r32 = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup)
     log("sweep period (fixed-length runs)")
-    per_launch_ms = sweep_period(torch, g, p, b)
+    # the same kernel the FP64 solves ran: their layout and block size
+    layout_name = {v: k for k, v in g.binding.LAYOUTS.items()}[r64["props"]["layout"]]
+    per_launch_ms = sweep_period(torch, g, p, b, layout=layout_name,
+                                 edges_per_block=r64["props"]["edges_per_block"])
     copy_gbs = copy_rate(torch) / 1e9
     log("colour-serial schedule: FP64 and FP32 + FP64 refinement solves")
     r64s = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, layout="serial")
     r32s = run_solves(torch, g, p, b, "fp32", args.steps, args.warmup, layout="serial")
-    per_serial_ms = sweep_period(torch, g, p, b, layout="serial")
+    per_serial_ms = sweep_period(torch, g, p, b, layout="serial",
+                                 edges_per_block=r64s["props"]["edges_per_block"])
     sc = g.Solver(p.row_ptr, p.col, p.val, layout="serial")
     ncol = sc.colours()[1]
     sc.close()
@@ -659,7 +672,7 @@ def main():
     kernel_bytes = kernel_bytes_of(layout, n, E, 8)
     achieved = alg / (per_launch_ms * 1e-3) / 1e9
     kname, ktag = LAYOUT_KERNELS[layout]
-    traffic = measured_traffic(ktag)
+    traffic = measured_traffic(f"{ktag}_k{r64['props']['edges_per_block'] // 256}")
 
     # the two precisions against each other (both are compared with the FP64
     # oracle's solution below when the CPU baseline runs)
@@ -704,7 +717,7 @@ def main():
                         "speedup_vs_synchronous_fp64": ms_step / ms32s,
                         "vs_oracle": vs_oracle.get("serial_fp32_refine")},
         "sweep": {"avg_sweep_ms": per_serial_ms, "launches_per_sweep": ncol,
-                  "kernel_bytes_per_sweep": kb_s, "traffic": measured_traffic("k_serial_fp64"),
+                  "kernel_bytes_per_sweep": kb_s, "traffic": measured_traffic(f"k_serial_fp64_k{r64s['props']['edges_per_block'] // 256}"),
                   "kernel_frac": kb_s / (per_serial_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                   "alg_frac": alg_sweep_bytes(n, E, 8) / (per_serial_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
