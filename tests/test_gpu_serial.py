@@ -305,3 +305,24 @@ def test_serial_xcd_parts_change_no_result():
     np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
     ref = oracle.serial_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000)
     assert i["sweeps"] == ref["sweeps"] and rel(x, ref["x"]) <= TOL
+
+
+@pytest.mark.parametrize("epb", [512, 1024])
+def test_serial_long_rows_report_the_residual_of_x(epb):
+    # hub rows swept in chunks: the lag-one residual assembled from the
+    # chunks' partial sums is the residual of the returned means, at every
+    # stopping sweep, and repeated solves agree bit for bit
+    p = CASES["powerlaw"]()
+    s = serial(p, edges_per_block=epb)
+    b = dev(p.b)
+    first = None
+    for tol in (1e-6, 1e-8, 1e-10):
+        for rep in range(2):
+            x, info = s.solve(b, tol=tol, max_iter=2000)
+            _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+            assert info["rel_residual"] == pytest.approx(rr, rel=1e-6), (tol, rep, info["rel_residual"], rr)
+            if rep == 0:
+                first = (x.cpu().numpy().copy(), info["rel_residual"], info["sweeps"])
+            else:
+                np.testing.assert_array_equal(x.cpu().numpy(), first[0])
+                assert (info["rel_residual"], info["sweeps"]) == first[1:]

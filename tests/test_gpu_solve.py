@@ -539,3 +539,22 @@ def test_xcd_order_fp32_refinement_and_grids():
     # a naturally ordered grid already keeps its edges inside 8 row ranges
     q = workloads.grid3d_problem(24, 95)
     assert solver(q).props()["xcd_parts"] == 0
+
+
+@pytest.mark.parametrize("epb", [512, 1024])
+def test_long_rows_report_the_residual_of_x(epb):
+    # hub rows swept in chunks and finished by one wave each: the fused check
+    # is the residual of the returned means, and repeated solves agree bit for
+    # bit (without precision reuse, so that each solve starts from zero
+    # messages)
+    p = CASES["powerlaw"]()
+    s = solver(p, layout="compact", edges_per_block=epb, reuse_precision=False)
+    b = dev(p.b)
+    for tol in (1e-6, 1e-10):
+        x1, i1 = s.solve(b, tol=tol, max_iter=2000)
+        x1 = x1.cpu().numpy().copy()
+        x2, i2 = s.solve(b, tol=tol, max_iter=2000)
+        np.testing.assert_array_equal(x2.cpu().numpy(), x1)
+        assert (i2["rel_residual"], i2["sweeps"]) == (i1["rel_residual"], i1["sweeps"])
+        _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x1, p.b)
+        assert i1["rel_residual"] == pytest.approx(rr, rel=1e-6), (tol, i1["rel_residual"], rr)
