@@ -125,3 +125,52 @@ def test_full_btb_convergence_fix(btb_full, mode):
     x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=1e-9, max_iter=1000000)
     assert info["converged"] == 1
     assert relres(p.scipy(), x.cpu().numpy(), p.b) <= 1.05e-9
+
+
+@pytest.fixture(scope="module")
+def powerlaw_full():
+    return workloads.powerlaw_config()
+
+
+def _rel(x, ref):
+    return np.linalg.norm(x - ref) / np.linalg.norm(ref)
+
+
+def test_full_powerlaw_first_rounds_and_converged_solves(powerlaw_full):
+    # the heavy-tailed workload of the bench suite (hub rows up to 140,734
+    # slots, swept in chunks), autotuned handles as the bench creates them
+    p = powerlaw_full
+    A = p.scipy()
+    s = g.Solver(p.row_ptr, p.col, p.val, device=DEV, reuse_precision=False)
+    print(f"power-law: props {s.props()}", flush=True)
+    for T in (1, 3):
+        ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=T)
+        x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=0, max_iter=T)
+        assert _rel(x.cpu().numpy(), ref["x"]) <= 1e-12, T
+    for prec in ("fp64", "fp32"):
+        s = g.Solver(p.row_ptr, p.col, p.val, precision=prec, device=DEV, reuse_precision=False)
+        x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=1e-10, max_iter=2000)
+        assert info["converged"] == 1
+        r = relres(A, x.cpu().numpy(), p.b)
+        assert r <= 1.05e-10, (prec, r)
+        if prec == "fp64":  # the fused check reports the residual of the returned means
+            assert info["rel_residual"] == pytest.approx(r, rel=1e-6)
+        s.close()
+
+
+def test_full_powerlaw_serial_first_sweeps_and_converged_solve(powerlaw_full):
+    p = powerlaw_full
+    s = g.Solver(p.row_ptr, p.col, p.val, device=DEV, layout="serial")
+    col, k = s.colours()
+    ref_col = oracle.greedy_colouring(p.n, p.row_ptr, p.col)
+    np.testing.assert_array_equal(col, ref_col)
+    print(f"power-law serial: {k} colour classes", flush=True)
+    for T in (1, 2):
+        ref = oracle.serial_gabp(p.n, p.row_ptr, p.col, p.val, p.b, colour=ref_col, tol=0, max_sweeps=T)
+        x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=0, max_iter=T)
+        assert _rel(x.cpu().numpy(), ref["x"]) <= 1e-12, T
+    x, info = s.solve(torch.from_numpy(p.b).to(DEV), tol=1e-10, max_iter=2000)
+    assert info["converged"] == 1
+    r = relres(p.scipy(), x.cpu().numpy(), p.b)
+    assert r <= 1.05e-10
+    assert info["rel_residual"] == pytest.approx(r, rel=1e-6)
