@@ -78,6 +78,23 @@ def alg_sweep_bytes(n, E, elt):
     return (5 * elt + 8) * E + (4 + 6 * elt) * n
 
 
+def spmv_bytes(n, E):
+    """Algorithmic bytes of the FP64 residual r = b - A x of a refinement step:
+    per slot A_ij + column + the gathered x_j (8 + 4 + 8), per node row pointer
+    + A_ii + b_i + x_i + r_i (4 + 4 * 8)."""
+    return 20 * E + 36 * n
+
+
+def tol_roofline(ms, sweeps, n, E, elt, spmvs=0):
+    """Time-to-tolerance roofline: every phase's algorithmic bytes (sweeps in
+    precision elt, FP64 residual products) at the 8 TB/s HBM peak, against the
+    measured time."""
+    floor = (sweeps * alg_sweep_bytes(n, E, elt) + spmvs * spmv_bytes(n, E)) / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"floor_ms": floor, "frac": floor / ms, "sweeps": sweeps, "residual_products": spmvs,
+            "model": f"sweeps x {'48 B/slot + 52 B/node' if elt == 8 else '28 B/slot + 28 B/node'}"
+                     + (" + residual products x (20 B/slot + 36 B/node)" if spmvs else "") + " at 8 TB/s"}
+
+
 def node_layout_bytes(n, E, elt, check=True):
     """Bytes the node-broadcast sweep itself moves, each element once: per slot
     column 4 + A_ij elt + the edge pair read and written 8 elt + the gathered
@@ -706,12 +723,14 @@ def main():
     serial = {
         "colours": ncol,
         "fp64": {"time_to_tol_ms": ms64s, "sweeps": i64s["sweeps"],
+                 "tol_roofline": tol_roofline(ms64s, i64s["sweeps"], n, E, 8),
                  "rel_residual": float(np.linalg.norm(p.b - A @ r64s["x"]) / np.linalg.norm(p.b)),
                  "rel_err_vs_synchronous": float(np.linalg.norm(r64s["x"] - r64["x"]) / nr),
                  "edge_updates_per_s": E * i64s["sweeps"] / (ms64s * 1e-3),
                  "speedup_vs_synchronous_fp64": ms_step / ms64s,
                  "vs_oracle": vs_oracle.get("serial_fp64")},
         "fp32_refine": {"time_to_tol_ms": ms32s, "inner_sweeps": i32s["sweeps"],
+                        "tol_roofline": tol_roofline(ms32s, i32s["sweeps"], n, E, 4, i32s["outer_iters"]),
                         "outer_iters": i32s["outer_iters"],
                         "rel_residual": float(np.linalg.norm(p.b - A @ r32s["x"]) / np.linalg.norm(p.b)),
                         "speedup_vs_synchronous_fp64": ms_step / ms32s,
@@ -771,12 +790,14 @@ def main():
         "cpu_baseline": cpu,
         "fp64": {"time_to_tol_ms": ms_step, "sweeps": sweeps64, "rel_residual": res64,
                  "wall_ms_per_step": 1e3 * r64["wall_s"] / args.steps,
+                 "tol_roofline": tol_roofline(ms_step, sweeps64, n, E, 8),
                  "vs_oracle": vs_oracle.get("fp64")},
         "fp32_refine": {"time_to_tol_ms": ms_step32, "inner_sweeps": i32["sweeps"],
                         "outer_iters": i32["outer_iters"], "rel_residual": res32,
                         "rel_err_vs_fp64": err32, "vs_oracle": vs_oracle.get("fp32_refine"),
                         "edge_updates_per_s": E * i32["sweeps"] / (ms_step32 * 1e-3),
-                        "speedup_vs_fp64": ms_step / ms_step32},
+                        "speedup_vs_fp64": ms_step / ms_step32,
+                        "tol_roofline": tol_roofline(ms_step32, i32["sweeps"], n, E, 4, i32["outer_iters"])},
         "serial": serial,
         "kernel_hash": source_hash(LAYOUT_SRC[layout]),
         "suite": suite,
