@@ -89,11 +89,14 @@ __device__ __forceinline__ Msg<T> ld_agg(const void* base, int q) {
   return Msg<T>{v.x, v.y};
 }
 
-__host__ __device__ constexpr size_t cn_lds(int K, int elt) {
-  // s_Pn, s_hn, s_ax [S]; own aggregates of rounds t-1 and t-2 [rows] x 4;
-  // s_ptr [rows+4]; s_row [S]
-  return (size_t)elt * (3 * (size_t)kBlock * K + 4 * kMaxRowsPerBlock) + sizeof(int32_t) * (kMaxRowsPerBlock + 4) +
-         (size_t)kBlock * K;
+// Dynamic LDS of one workgroup: s_Pn, s_hn, s_ax [S]; the rows' own
+// aggregates of round t-2 [rows] x 2, and of round t-1 [rows] x 2 for the
+// freeze only (the other modes use those in the row lane's registers alone);
+// s_ptr [rows+4]; s_row [S].  Leaving out the unused pair lets one more FP64
+// workgroup reside per CU.
+__host__ __device__ constexpr size_t cn_lds(int K, int elt, bool freeze) {
+  return (size_t)elt * (3 * (size_t)kBlock * K + (freeze ? 4 : 2) * kMaxRowsPerBlock) +
+         sizeof(int32_t) * (kMaxRowsPerBlock + 4) + (size_t)kBlock * K;
 }
 
 // Mean of a node from its aggregate record.
@@ -308,11 +311,12 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     T* s_Pn = (T*)smem;
     T* s_hn = s_Pn + S;
     T* s_ax = s_hn + S;
-    T* s_o1P = s_ax + S;
-    T* s_o1h = s_o1P + kMaxRowsPerBlock;
-    T* s_o2P = s_o1h + kMaxRowsPerBlock;
+    constexpr int kO1 = MODE == kFreeze ? kMaxRowsPerBlock : 0;  // round t-1 pair: freeze only
+    T* s_o2P = s_ax + S;
     T* s_o2h = s_o2P + kMaxRowsPerBlock;
-    int32_t* s_ptr = (int32_t*)(s_o2h + kMaxRowsPerBlock);
+    T* s_o1P = s_o2h + kMaxRowsPerBlock;
+    T* s_o1h = s_o1P + kO1;
+    int32_t* s_ptr = (int32_t*)(s_o1h + kO1);
     uint8_t* s_row = (uint8_t*)(s_ptr + kMaxRowsPerBlock + 4);
 
     // 1. every independent load at once: the slots' streamed data, then the
@@ -344,8 +348,10 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
     // 3. row structure and own aggregates into LDS
     if (tid < nrow) {
       s_ptr[tid] = rp;
-      s_o1P[tid] = o1.P;
-      s_o1h[tid] = o1.h;
+      if (kO1) {
+        s_o1P[tid] = o1.P;
+        s_o1h[tid] = o1.h;
+      }
       s_o2P[tid] = o2.P;
       s_o2h[tid] = o2.h;
     }
@@ -360,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_cnode(CnodeArgs<T> A) {
       const int i = tid + k * kBlock;
       if (i < ne) {
         const int lr = s_row[i];
-        const Msg<T> q1{s_o1P[lr], s_o1h[lr]};
+        const Msg<T> q1 = kO1 ? Msg<T>{s_o1P[lr], s_o1h[lr]} : Msg<T>{0, 0};
         const Msg<T> q2{s_o2P[lr], s_o2h[lr]};
         T Pn, hn, ax;
         compute_slot<T, MODE>(A, e0 + i, in[k], g[k], q1, q2, Pn, hn, ax);
@@ -432,7 +438,7 @@ __global__ __launch_bounds__(64) void k_cnode_long(CnodeArgs<T> A) {
 
 template <typename T, int K>
 hipError_t launch_ck(int mode, const CnodeArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  const uint32_t lds = (uint32_t)cn_lds(K, sizeof(T));
+  const uint32_t lds = (uint32_t)cn_lds(K, sizeof(T), mode == kFreeze);
   const dim3 grid(a.nblk + a.nxch), block(kBlock);
   switch (mode) {
     case kJoint: hipExtLaunchKernelGGL((k_cnode<T, K, kJoint>), grid, block, lds, s, ev0, ev1, 0, a); break;
@@ -490,7 +496,7 @@ __global__ void k_cnode_prior(int32_t n, const T* __restrict__ first, const T* _
 
 }  // namespace
 
-size_t cnode_lds_bytes(int K, int elt) { return cn_lds(K, elt); }
+size_t cnode_lds_bytes(int K, int elt) { return cn_lds(K, elt, true); }
 
 template <typename T>
 hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s) {
