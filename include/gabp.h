@@ -63,7 +63,9 @@ typedef struct {
   int32_t precision;        /* gabp_precision                                       */
   int32_t check_every;      /* residual check period in sweeps (>= 1)               */
   int32_t edges_per_block;  /* message slots per 256-lane workgroup: 512, 1024 or   */
-                            /* 2048; 0 = pick by timing at create (autotuner)       */
+                            /* 2048; 0 = pick by timing at create (autotuner).  A   */
+                            /* longer row gets a workgroup of its own (layouts 1,   */
+                            /* 2) or is split over several (layouts 3, 4)           */
   int32_t inner_max_iter;   /* cap on inner sweeps per outer step                   */
   int32_t max_outer;        /* cap on outer steps (refinement / loading loop)       */
   int32_t flags;            /* GABP_FLAG_* bits                                     */
