@@ -233,8 +233,9 @@ gabp_status ingest(Ctx* c, const int32_t* row_ptr, const int32_t* col, const dou
 }
 
 // Greedy packing of whole rows into workgroups of at most 256*K slots and 256
-// rows; a row longer than 256*K gets a workgroup of its own (handled by the
-// sweep kernel's long-row path).  With colour classes or XCD parts, no
+// rows; a row longer than 256*K gets a workgroup of its own (the edge and node
+// sweeps loop over it; the compact and colour-serial sweeps split it into the
+// chunk workgroups of set_long_rows).  With colour classes or XCD parts, no
 // workgroup spans two of them.
 gabp_status build_partition(const Ctx* c, int K, std::vector<int32_t>& blk_row) {
   const int64_t cap = (int64_t)kBlock * K;
