@@ -310,6 +310,24 @@ def test_single_loop_matches_oracle_rounds_and_converges(s):
     assert rel(x, np.linalg.solve(p.dense(), p.b)) <= 1e-7
 
 
+def test_single_loop_feedback_on_long_rows():
+    # the feedback prior of the single loop, applied by the long-row finish
+    # kernel to hub rows swept in chunks (512 slots per workgroup: eight rows
+    # of the power-law case are longer)
+    p = CASES["powerlaw"]()
+    gam, s = 0.3, 0.5
+    Gamma = gam * p.scipy().diagonal()
+    sv = solver(p, gamma=gam, single_loop=True, damping=s, edges_per_block=512)
+    for T in (1, 2, 5, 20):
+        x, info = sv.solve(dev(p.b), tol=0, max_iter=T)
+        ref = oracle.convfix_single_loop(p.n, p.row_ptr, p.col, p.val, p.b, Gamma, s=s, tol=0, max_sweeps=T)
+        assert rel(x, ref["x"]) <= 1e-12, (T, rel(x, ref["x"]))
+    x, info = sv.solve(dev(p.b), tol=1e-10, max_iter=20000)
+    assert info["converged"] == 1
+    _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+    assert rr <= 1.05e-10
+
+
 def test_single_loop_with_automatic_loading_and_adjoint():
     p = workloads.config5(n=2000, rows=4000)
     sv = solver(p, gamma=-1.0, single_loop=True)
