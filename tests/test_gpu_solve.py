@@ -395,6 +395,21 @@ def test_backward_matches_dense_gradient_and_fd(layout):
         assert gv[e].item() == pytest.approx(fd, rel=1e-6, abs=1e-8)
 
 
+@pytest.mark.parametrize("layout", ["compact", "serial"])
+def test_backward_on_long_rows_matches_dense_gradient(layout):
+    # adjoint solves through hub rows swept in chunks (two rows of about 800
+    # slots at 512 slots per workgroup), against the dense oracle gradient
+    p = workloads.powerlaw_problem(2000, 8, 95, beta=2.0)
+    t = np.random.default_rng(5).standard_normal(p.n)
+    s = solver(p, layout=layout, edges_per_block=512)
+    x, info = s.solve(dev(p.b), tol=1e-13, max_iter=5000)
+    gb, gv, binfo = s.backward(x, x - dev(t), tol=1e-13, max_iter=5000)
+    assert info["converged"] == 1 and binfo["converged"] == 1
+    xr, lam, gvals = oracle.adjoint_gradient(p.dense(), p.b, t, p.row_ptr, p.col)
+    assert rel(gb, lam) <= TOL
+    assert rel(gv, gvals) <= TOL
+
+
 def test_autograd_function():
     p = workloads.config4(p=6)
     t = torch.from_numpy(p.extra["target"]).to(DEV)
