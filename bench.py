@@ -585,7 +585,16 @@ def suite_batched(torch, g, workloads, sample=48):
             "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
             "E": int(E_s.sum()), "generate_s": gen_s, "time_to_tol_ms": 1e3 * dt, "status": st,
             "converged_systems": nconv, "worst_rel_residual": worst,
-            "slot_rhs_updates_per_s": slot_rhs / dt, "load_balance": prof, "serial": serial,
+            "slot_rhs_updates_per_s": slot_rhs / dt,
+            # one FP32 h-only update of a (slot, right-hand side): the h message
+            # read and written and the neighbour's h~ gathered, 12 B; precision
+            # sweeps and per-node terms left out
+            "roofline": {"bound": "hbm", "alg_bytes_per_update": 12,
+                         "achieved_GBs": 12 * slot_rhs / dt / 1e9,
+                         "frac": 12 * slot_rhs / dt / 1e9 / HBM_PEAK_GBS,
+                         "note": "HBM-equivalent: the working set of a work item (up to about 1e5 slots "
+                                 "x 8 right-hand sides) largely stays in its CU's share of L2"},
+            "load_balance": prof, "serial": serial,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
                                 "speedup": loop_s / sub_s},
