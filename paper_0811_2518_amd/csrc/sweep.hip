@@ -87,13 +87,24 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
                                                                int gate_on_done) {
   __shared__ double s_red[kFinishBlock / 64];
   if (gate_on_done && st->done) return;
+  // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
+  // v1, each in increasing j.  Sixteen loads are issued before their
+  // additions (one L2 round trip per sixteen, not per two); a missing element
+  // counts as +0.0, which leaves a sum of squares bit for bit unchanged.
   double v0 = 0.0, v1 = 0.0;
-  int i = threadIdx.x;
-  for (; i + kFinishBlock < nblk; i += 2 * kFinishBlock) {
-    v0 += partials[i];
-    v1 += partials[i + kFinishBlock];
+  for (int j0 = 0; j0 * kFinishBlock < nblk; j0 += 16) {
+    double p[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = threadIdx.x + (j0 + u) * kFinishBlock;
+      p[u] = i < nblk ? partials[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      v0 += p[u];
+      v1 += p[u + 1];
+    }
   }
-  if (i < nblk) v0 += partials[i];
   double v = wave_sum(v0 + v1);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
   __syncthreads();
