@@ -160,7 +160,7 @@ def measured_traffic(kernel_tag):
     return ent.get("bytes_per_launch")
 
 
-def traffic_from(fetch_dir, write_dir, n):
+def traffic_from(fetch_dir, write_dir, n, out_path=None):
     """profiles/traffic.json from two rocprofv3 --pmc runs of `bench.py --probe`
     (FETCH_SIZE, then WRITE_SIZE): per-dispatch medians of the sweep kernels,
     scaled so that the probe's 1 GiB copy reads 1 GiB and writes 1 GiB.  The
@@ -206,7 +206,7 @@ def traffic_from(fetch_dir, write_dir, n):
                     "fetch_kib": fk, "write_kib": wk, "fetch_scale": fs, "write_scale": ws,
                     "bytes_per_launch": b, "source_file": src, "source_sha": source_hash(src)}
         print(f"| `{kname}` | {len(units)} | {fk:.1f} | {wk:.1f} | {b / 1e6:.1f} | {unit} |")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
 
 
