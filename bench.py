@@ -13,7 +13,9 @@ from __future__ import annotations
 
 import os
 
-# the CPU baseline is the single-threaded oracle: pin BLAS/OpenMP pools first
+# the CPU baseline is the oracle on one core: its NumPy element-wise
+# operations, bincount and SciPy sparse products run on one thread; thread
+# pools not sized by the environment are kept at one thread as well
 for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ.setdefault(_v, "1")
 
