@@ -16,6 +16,8 @@ Application" (arXiv:0811.2518):
 * ``broadcast_gabp`` -- Alg. 2 (Ch. 3, Sec. "GaBP Broadcast Variant"),
   vectorised over the directed edges, synchronous (two message buffers,
   Ch. 2 end of Sec. "The Gaussian BP Algorithm").
+* ``aitken_extrapolate`` / ``aitken_gabp`` -- Aitken's extrapolation of the
+  means over three successive rounds (Ch. 3 Sec. "Convergence Acceleration").
 * ``fixpoint_violation`` -- the message equations of Alg. 2 evaluated on
   converged messages.
 * ``is_strictly_dd``, ``walk_rho``, ``rate_bound`` -- the sufficient conditions

@@ -34,6 +34,7 @@ __all__ = [
     "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
     "convfix_gabp", "convfix_single_loop", "adjoint_gradient", "fd_gradient", "loss",
     "greedy_colouring", "serial_gabp", "naive_serial_gabp",
+    "aitken_extrapolate", "aitken_gabp",
 ]
 
 
@@ -225,6 +226,87 @@ def broadcast_gabp(n, row_ptr, col, val, b, tol=1e-10, max_sweeps=2000,
         out["history"] = hist
     if return_messages:
         out.update(graph=g, P=P, mu=mu)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Aitken's extrapolation of the means (Ch. 3 Sec. 3.2, convergence
+# acceleration): node-local, from three successive rounds; the iteration
+# itself is left unchanged
+# ---------------------------------------------------------------------------
+
+def aitken_extrapolate(x0, x1, x2):
+    """Aitken's delta-squared step applied node by node to three successive means.
+
+    y = x0 - (x1 - x0)^2 / (x2 - 2 x1 + x0) for rounds n, n+1, n+2 (Ch. 3
+    Sec. 3.2).  Reading: where the second difference is zero or the
+    correction is not finite (the formula is undefined there, e.g. a mean
+    that has stopped moving), y is the newest mean x2.
+    """
+    x0 = np.asarray(x0, dtype=np.float64)
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    d1 = x1 - x0
+    den = x2 - 2.0 * x1 + x0
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        corr = d1 * d1 / den
+    ok = (den != 0.0) & np.isfinite(corr)
+    return np.where(ok, x0 - corr, x2)
+
+
+def aitken_gabp(n, row_ptr, col, val, b, tol=1e-10, max_sweeps=2000, check_every=1, history=False):
+    """Synchronous Alg. 2 whose output is Aitken's extrapolation of its means.
+
+    The messages follow Alg. 2 exactly as in ``broadcast_gabp``; after round
+    t >= 2 the estimate y_t = aitken_extrapolate(x_{t-2}, x_{t-1}, x_t) is
+    formed (Ch. 3 Sec. 3.2: every node uses its own history only).  Stop rule
+    as in the module docstring, applied to y_t on rounds t >= 2 with
+    t % check_every == 0 or t == max_sweeps; tol <= 0 runs exactly
+    ``max_sweeps`` (>= 2) rounds and returns y_{max_sweeps}.  A non-finite
+    relative residual of y_t ends the run unconverged.  Returns a dict with
+    ``y``, ``x`` (the means of the same round), ``sweeps``, ``converged``,
+    ``rel_residual`` and, on request, the (round, residual) history.
+    """
+    if max_sweeps < 2:
+        raise ValueError("Aitken's step needs three rounds (max_sweeps >= 2)")
+    b = np.asarray(b, dtype=np.float64)
+    g = edge_graph(n, row_ptr, col, val)
+    Pii = g.diag
+    muii = b / g.diag
+    P = np.zeros(g.num_edges)
+    mu = np.zeros(g.num_edges)
+    means = []                        # x_{t-2}, x_{t-1}, x_t
+    hist = []
+    t = 0
+    y = None
+    rel = float("nan")
+    converged = False
+    while True:
+        Pt, x = _broadcast(g, Pii, muii, P, mu)
+        means = (means + [x])[-3:]
+        if t >= 2:
+            last = t == max_sweeps
+            if tol <= 0:
+                if last:
+                    y = aitken_extrapolate(*means)
+            elif t % check_every == 0 or last:
+                y = aitken_extrapolate(*means)
+                _, rel = residual(n, row_ptr, col, val, y, b)
+                hist.append((t, rel))
+                if rel <= tol:
+                    converged = True
+                    break
+                if not np.isfinite(rel):
+                    break
+        if t >= max_sweeps:
+            break
+        P, mu = _internal_scalars(g, Pt, x, P, mu)
+        t += 1
+    if tol <= 0:
+        _, rel = residual(n, row_ptr, col, val, y, b)
+    out = {"y": y, "x": means[-1], "sweeps": t, "converged": converged, "rel_residual": rel}
+    if history:
+        out["history"] = hist
     return out
 
 

@@ -380,6 +380,90 @@ def test_single_loop_converges_where_plain_gabp_diverges(s):
 
 
 # ---------------------------------------------------------------------------
+# Aitken's extrapolation (Ch. 3 Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def _check_geometric(extrapolate):
+    """Closed form: for x_n = x* + c a^n, |a| < 1, Aitken's step returns x* exactly."""
+    rng = np.random.default_rng(7)
+    m = 400
+    xs = rng.normal(size=m)
+    c = rng.normal(size=m)
+    a = rng.uniform(-0.95, 0.95, size=m)
+    a[np.abs(a) < 0.05] = 0.5
+    for n0 in (0, 3, 11):
+        x0, x1, x2 = (xs + c * a ** (n0 + k) for k in range(3))
+        y = extrapolate(x0, x1, x2)
+        err = np.abs(y - xs)
+        # rounding of three terms of size |x*| + |c| a^n0, amplified by 1/(1 - a)^2
+        bound = 64 * np.finfo(float).eps * (np.abs(xs) + np.abs(c)) / (1 - np.abs(a)) ** 2
+        assert np.all(err <= bound), float(np.max(err / bound))
+        # and the step is a real improvement on the newest mean
+        assert np.all(err <= np.abs(x2 - xs) + bound)
+
+
+def test_aitken_exact_on_geometric_sequences():
+    _check_geometric(oracle.aitken_extrapolate)
+
+
+@pytest.mark.parametrize("variant", ["plus_sign", "newest_base", "first_difference_late", "den_sign"])
+def test_aitken_planted_mistakes_are_caught(variant):
+    def bad(x0, x1, x2):
+        d1, den = x1 - x0, x2 - 2 * x1 + x0
+        if variant == "plus_sign":
+            return x0 + d1 * d1 / den
+        if variant == "newest_base":
+            return x2 - d1 * d1 / den
+        if variant == "first_difference_late":
+            return x0 - (x2 - x1) ** 2 / den
+        return x0 - d1 * d1 / (x2 + 2 * x1 - x0)
+    with pytest.raises(AssertionError):
+        _check_geometric(bad)
+
+
+def test_aitken_undefined_step_keeps_newest_mean():
+    # zero second difference (a constant or a linear sequence): the newest mean
+    x0 = np.array([1.0, 1.0, 0.0, 5.0])
+    x1 = np.array([1.0, 2.0, -1.0, 4.0])
+    x2 = np.array([1.0, 3.0, -2.0, 3.5])
+    y = oracle.aitken_extrapolate(x0, x1, x2)
+    np.testing.assert_array_equal(y[:3], x2[:3])
+    assert y[3] == 5.0 - 1.0 / 0.5       # geometric with ratio 1/2: limit 3
+    # an overflowing correction also falls back to the newest mean
+    y = oracle.aitken_extrapolate(np.array([0.0]), np.array([1e200]), np.array([1e200 + 1e185]))
+    assert y[0] == 1e200 + 1e185
+
+
+def test_aitken_gabp_uses_three_successive_rounds():
+    p = workloads.grid2d_problem(9, 7, seed=5)
+    for M in (2, 3, 17):
+        r = oracle.aitken_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=M)
+        xs = [oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=t)["x"]
+              for t in (M - 2, M - 1, M)]
+        assert r["sweeps"] == M
+        np.testing.assert_array_equal(r["x"], xs[2])
+        np.testing.assert_array_equal(r["y"], oracle.aitken_extrapolate(*xs))
+    with pytest.raises(ValueError):
+        oracle.aitken_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=1)
+
+
+def test_aitken_gabp_on_poisson_converges_sooner_to_the_solution():
+    # Ch. 4 Sec. 4.3: on the 2-D Poisson example the parallel iteration with
+    # Aitken's extrapolation needs a small fraction of the plain rounds, and
+    # its region of convergence (hence its limit) is unchanged (Ch. 3 Sec. 3.2)
+    p = workloads.poisson2d(10)
+    xstar = oracle.dense_solve(p.dense(), p.b)
+    for tol in (1e-6, 1e-10):
+        plain = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=tol, max_sweeps=5000)
+        ait = oracle.aitken_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=tol, max_sweeps=5000)
+        assert ait["converged"] and plain["converged"]
+        assert 2 * ait["sweeps"] <= plain["sweeps"]
+        A = p.dense()
+        assert np.linalg.norm(p.b - A @ ait["y"]) <= tol * np.linalg.norm(p.b)
+        assert np.linalg.norm(ait["y"] - xstar) <= 10 * tol * np.linalg.cond(A) * np.linalg.norm(xstar)
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: each plausible slip in the broadcast oracle fails a pin
 # ---------------------------------------------------------------------------
 
