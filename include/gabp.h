@@ -120,6 +120,21 @@ typedef struct {
  * the results are unchanged up to the summation order of the residual norm. */
 #define GABP_FLAG_NATURAL_ORDER 8
 
+/* Aitken's extrapolation of the means (Ch. 3 Sec. 3.2, convergence
+ * acceleration).  Plain FP64 only (precision FP64, gamma 0, no single loop);
+ * the handle uses the compact layout (layout 0 or 3, else GABP_E_ARG).  The
+ * sweeps are those of Alg. 2, unchanged; after sweep t >= 2 every node forms
+ *   y_t = x_{t-2} - (x_{t-1} - x_{t-2})^2 / (x_t - 2 x_{t-1} + x_{t-2})
+ * from its own last three means, or y_t = x_t where that second difference is
+ * zero or the correction is not finite.  gabp_solve and gabp_backward return
+ * y instead of x: the stop rule is applied to y_t on sweeps t >= 2 with
+ * t % check_every == 0 or t == max_iter (tol <= 0: exactly max_iter >= 2
+ * sweeps, y_{max_iter} returned), gabp_info.sweeps = t, and var (when asked
+ * for) holds the variances of sweep t.  A large residual of y_t is not taken
+ * for divergence (a node whose second difference nears zero can jump far for
+ * one round); a NaN still is.  No precision messages are frozen for reuse. */
+#define GABP_FLAG_AITKEN 16
+
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
   int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */

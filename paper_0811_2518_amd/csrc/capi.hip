@@ -46,6 +46,12 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
   if (!(o.damping > 0.0 && o.damping <= 1.0)) return fail(c, GABP_E_ARG, "damping must lie in (0, 1]");
   if ((o.flags & GABP_FLAG_SINGLE_LOOP) && o.layout != 0 && o.layout != kLayoutCompact)
     return fail(c, GABP_E_ARG, "the single loop needs the compact layout");
+  if (o.flags & GABP_FLAG_AITKEN) {
+    if (o.layout != 0 && o.layout != kLayoutCompact)
+      return fail(c, GABP_E_ARG, "Aitken's extrapolation needs the compact layout");
+    if (o.precision != GABP_FP64 || o.gamma != 0.0 || (o.flags & GABP_FLAG_SINGLE_LOOP))
+      return fail(c, GABP_E_ARG, "Aitken's extrapolation applies to the plain FP64 iteration");
+  }
   return GABP_OK;
 }
 

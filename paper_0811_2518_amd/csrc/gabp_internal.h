@@ -319,6 +319,8 @@ struct Ctx {
   std::vector<int32_t> colour_h;      // [n] colour of each caller row
   int32_t* slot_of_d = nullptr;       // [E] caller slot of each internal slot (XCD order only)
   double* msg_tmp_d = nullptr;        // [2E] exported messages in internal slot order (XCD order only)
+  double* ait_y_d = nullptr;          // [n] Aitken estimate (GABP_FLAG_AITKEN)
+  double* ait_hist_d = nullptr;       // [n] x_{t-2} for the next Aitken step
   int32_t nparts = 0;                 // XCD order: parts per group (8), else 0
   std::vector<int32_t> part_start;    // XCD order: first row of every part of every group, then n
                                       // (one group; colour-serial: one group per colour class)
@@ -422,7 +424,14 @@ struct OuterArgs {
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
-                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s);
+                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s,
+                               double diverge_limit = kDivergeLimit);
+// Aitken step after the sweep of round t (Ch. 3 Sec. 3.2): with make_y,
+// y = hist - (x1 - hist)^2 / (x2 - 2 x1 + hist), or x2 where undefined; then
+// hist = x1.  x1 and x2 are the means of rounds t-1 and t, hist those of
+// round t-2.  Returns at once once the status is done.
+hipError_t launch_aitken(const double* x1, const double* x2, double* hist, double* y, const DevStatus* st,
+                         int make_y, int32_t n, hipStream_t s);
 hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam,
                             const double* x, double* gv, int32_t n, hipStream_t s);
 hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n,

@@ -31,6 +31,11 @@ struct RunCfg {
   bool feedback = false;
   double damp = 0.5;
   const void* chk_diag = nullptr;     // T [n]
+  // Aitken's extrapolation (compact layout, FP64): every round's means are
+  // written, the fused check is off, and after the sweep of round t the
+  // estimate y_t is formed and its residual checked in its place
+  double* ait_y = nullptr;            // [n] nullable: plain checks
+  double* ait_hist = nullptr;         // [n]
 };
 
 template <typename T>
@@ -303,6 +308,20 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const int M = cfg.max_iter;
   const int ce = std::max(1, cfg.check_every);
   auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+  const bool ait = cfg.ait_y != nullptr;
+  if (ait && sizeof(T) != 8) return fail(c, GABP_E_ARG, "Aitken's extrapolation runs in FP64");
+  const int lag = ait ? 0 : 1;  // sweep t checks round t (Aitken) or t-1 (fused)
+  OuterArgs ra{};               // residual of the Aitken estimate
+  ra.blk_row = c->blk_row_d;
+  ra.off_ptr = c->off_ptr_d;
+  ra.off_col = c->off_col_d;
+  ra.a = c->a64_d;
+  ra.diag = c->d64_d;
+  ra.b = (const double*)cfg.rhs;
+  ra.xnew = cfg.ait_y;
+  ra.partials = c->partials_d;
+  ra.nblk = c->nblk;
+  ra.n = c->n;
 
   CnodeArgs<T> a{};
   a.blk_row = c->blk_row_d;
@@ -332,12 +351,13 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const int last = M + 1;
   Poller poll;
   ChunkPlan plan;
-  int t = 1, chunk = plan.first(1, ce);
+  int t = 1, chunk = plan.first(lag, ce);
   bool stop = false;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
     for (; t <= tend; ++t) {
       const int mode = (t <= M) ? main_mode : kResid;
+      if (ait && mode == kResid) continue;
       CnodeArgs<T> k = a;
       k.first = (t == 1);
       k.second = (t == 2);
@@ -346,15 +366,15 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       k.agg2 = c->agg_d[(t + 1) % 3];  // round t-2
       k.anew = c->agg_d[t % 3];
       if (mode != kResid) {
-        const bool wx = exact ? t == M : in_set(t);
+        const bool wx = ait || (exact ? t == M : in_set(t));
         k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
         k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
       }
-      if (t == 1 && (exact ? M == 0 : in_set(0))) {
+      if (t == 1 && (ait || (exact ? M == 0 : in_set(0)))) {
         k.xout_prev = (T*)cfg.x2[0];
         k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
       }
-      const bool ck = exact ? (t == M + 1) : in_set(t - 1);
+      const bool ck = !ait && (exact ? (t == M + 1) : in_set(t - 1));
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
       hipEvent_t e0, e1;
@@ -364,9 +384,20 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       if (ck)
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
                                         true, s));
+      if (ait) {
+        // means of rounds t-2 (history), t-1 and t; y_t on the checked rounds
+        const bool wy = t >= 2 && (exact ? t == M : in_set(t));
+        GABP_HIP(c, launch_aitken((const double*)cfg.x2[(t - 1) & 1], (const double*)cfg.x2[t & 1],
+                                  cfg.ait_hist, cfg.ait_y, cfg.st, wy ? 1 : 0, c->n, s));
+        if (wy && !exact) {
+          GABP_HIP(c, launch_outer_only(c->K, ra, s));
+          GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t, nullptr, true,
+                                          s, INFINITY));
+        }
+      }
     }
     stop = poll.step(c, cfg.st);
-    chunk = plan.next(poll, t - 1, 1, ce, exact ? -1.0 : cfg.tol);
+    chunk = plan.next(poll, t - 1, lag, ce, exact ? -1.0 : cfg.tol);
   }
   return finish_run(c, poll);
 }
@@ -611,8 +642,18 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
                         gabp_info* info, bool allow_reuse) {
   hipStream_t s = c->stream;
   const bool exact = tol <= 0.0;
+  const bool ait = (c->opts.flags & GABP_FLAG_AITKEN) != 0;
   const bool honly = allow_reuse && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) && c->frozen_valid &&
-                     c->frozen_prec == GABP_FP64 && !exact;
+                     c->frozen_prec == GABP_FP64 && !exact && !ait;
+  if (ait) {
+    if (c->layout != kLayoutCompact) return fail(c, GABP_E_ARG, "Aitken's extrapolation needs the compact layout");
+    if (max_iter < 2) return fail(c, GABP_E_ARG, "Aitken's extrapolation needs max_iter >= 2");
+    for (double** p : {&c->ait_y_d, &c->ait_hist_d})
+      if (!*p) {
+        gabp_status e = dev_alloc(c, (void**)p, sizeof(double) * c->n);
+        if (e != GABP_OK) return e;
+      }
+  }
   reset_timing(c);
   GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
   RunCfg cfg;
@@ -630,11 +671,16 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     cfg.pt2[1] = c->pt64_d[1];
   }
   cfg.st = c->st_d;
+  if (ait) {
+    cfg.ait_y = c->ait_y_d;
+    cfg.ait_hist = c->ait_hist_d;
+  }
   gabp_status rs = run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
   const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
   const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
   GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
+  if (ait) GABP_HIP(c, hipMemcpyAsync(x, c->ait_y_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   if (var && honly) GABP_HIP(c, hipMemcpyAsync(var, c->inv_pt_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   DevStatus st;
   gabp_status r = read_status(c, c->st_d, &st);
@@ -651,7 +697,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     report_timing(c, info);
   }
   c->last_msg_round = (exact && !honly && r == GABP_OK) ? max_iter : -1;
-  if (r == GABP_OK && !exact && !honly && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) &&
+  if (r == GABP_OK && !exact && !honly && !ait && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) &&
       c->layout != kLayoutSerial) {
     const int last = held_round(c, st.conv_round, max_iter);
     gabp_status fr = freeze<double>(c, last, c->din64_d, b, GABP_FP64);
@@ -835,6 +881,13 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
 
 namespace {
 
+// Layout asked for at create: the caller's, else the compact layout for the
+// single loop and Aitken's extrapolation (both live in its sweep), else 0.
+int layout_request(const Ctx* c) {
+  if (c->opts.layout) return c->opts.layout;
+  return (c->opts.flags & (GABP_FLAG_SINGLE_LOOP | GABP_FLAG_AITKEN)) ? kLayoutCompact : 0;
+}
+
 std::string tune_key(const Ctx* c) {
   int nb = 0;
   while ((1LL << (nb + 1)) <= (long long)std::max(1, c->n)) ++nb;
@@ -842,7 +895,7 @@ std::string tune_key(const Ctx* c) {
   char buf[160];
   std::snprintf(buf, sizeof(buf), "fp%d-n2^%d-deg%d-max%d-L%d-epb%d-x%d",
                 c->opts.precision == GABP_FP32_REFINE ? 32 : 64, nb, (int)std::lround(avg),
-                c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256), c->opts.layout,
+                c->max_degree > 2048 ? 9999 : (c->max_degree > 256 ? 2048 : 256), layout_request(c),
                 c->opts.edges_per_block, c->nparts);
   return buf;
 }
@@ -911,12 +964,12 @@ gabp_status time_candidate(Ctx* c, int layout, int K, const void* rhs, const voi
 gabp_status autotune(Ctx* c) {
   const int epb = c->opts.edges_per_block;
   std::vector<int> layouts, Ks;
-  if (c->opts.layout) layouts.push_back(c->opts.layout);
-  else if (c->opts.flags & GABP_FLAG_SINGLE_LOOP) layouts = {kLayoutCompact};
+  const int req = layout_request(c);
+  if (req) layouts.push_back(req);
   else layouts = {kLayoutEdge, kLayoutNode, kLayoutCompact};
   if (epb) Ks.push_back(epb / kBlock);
   else Ks = {2, 4, 8};
-  int best_l = c->opts.layout ? c->opts.layout : layouts.back(), best_k = epb ? epb / kBlock : 4;
+  int best_l = req ? req : layouts.back(), best_k = epb ? epb / kBlock : 4;
   if (c->E >= 200000 && layouts.size() * Ks.size() > 1) {
     const std::string key = tune_key(c);
     const char* path = std::getenv("GABP_AUTOTUNE_CACHE");

@@ -84,7 +84,7 @@ constexpr int kFinishBlock = 1024;
 __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __restrict__ partials, int nblk,
                                                                DevStatus* st, const double* rhs_norm,
                                                                double tol, int round, double* norm_out,
-                                                               int gate_on_done) {
+                                                               int gate_on_done, double diverge_limit) {
   __shared__ double s_red[kFinishBlock / 64];
   if (gate_on_done && st->done) return;
   // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
     if (rel <= tol) {
       st->conv_round = round;
       st->done = 1;
-    } else if (!(rel <= kDivergeLimit)) {
+    } else if (!(rel <= diverge_limit)) {
       st->error |= kErrDiverged;
       st->done = 1;
     }
@@ -130,9 +130,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
 }
 
 hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
-                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s) {
+                               double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s,
+                               double diverge_limit) {
   hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nblk, st, rhs_norm, tol,
-                     round, norm_out, gate_on_done ? 1 : 0);
+                     round, norm_out, gate_on_done ? 1 : 0, diverge_limit);
   return hipGetLastError();
 }
 
@@ -598,6 +599,35 @@ hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, 
   const int blocks = std::min((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_copy_round, dim3(blocks), dim3(256), 0, s, x2[0], x2[1], pt2 ? pt2[0] : nullptr,
                      pt2 ? pt2[1] : nullptr, st, fallback_round, x, var, n);
+  return hipGetLastError();
+}
+
+// Aitken's delta-squared step on each node's last three means (Ch. 3
+// Sec. 3.2).  hist holds round t-2 and is advanced to round t-1 by the same
+// thread, so one vector of history suffices.  The second difference is formed
+// as (x2 - 2 x1) + x0; 2 x1 is exact, so a fused multiply-add leaves it
+// unchanged.
+__global__ void k_aitken(const double* __restrict__ x1, const double* __restrict__ x2, double* hist,
+                         double* __restrict__ y, const DevStatus* st, int make_y, int32_t n) {
+  if (st->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double a = hist[i], b = x1[i];
+    if (make_y) {
+      const double c = x2[i];
+      const double d1 = b - a;
+      const double den = (c - 2.0 * b) + a;
+      const double corr = d1 * d1 / den;
+      y[i] = (den != 0.0 && isfinite(corr)) ? a - corr : c;
+    }
+    hist[i] = b;
+  }
+}
+
+hipError_t launch_aitken(const double* x1, const double* x2, double* hist, double* y, const DevStatus* st,
+                         int make_y, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_aitken, dim3(blocks), dim3(256), 0, s, x1, x2, hist, y, st, make_y, n);
   return hipGetLastError();
 }
 
