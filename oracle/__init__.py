@@ -18,6 +18,9 @@ Application" (arXiv:0811.2518):
   Ch. 2 end of Sec. "The Gaussian BP Algorithm").
 * ``aitken_extrapolate`` / ``aitken_gabp`` -- Aitken's extrapolation of the
   means over three successive rounds (Ch. 3 Sec. "Convergence Acceleration").
+* ``augmented_csr`` / ``augmented_solution`` -- the symmetric block matrix of
+  Ch. 5 Sec. "Extension to General Linear Systems" for a rectangular B, and
+  the x-part of its solution by block elimination (the section's lemma).
 * ``fixpoint_violation`` -- the message equations of Alg. 2 evaluated on
   converged messages.
 * ``is_strictly_dd``, ``walk_rho``, ``rate_bound`` -- the sufficient conditions

@@ -34,7 +34,7 @@ __all__ = [
     "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
     "convfix_gabp", "convfix_single_loop", "adjoint_gradient", "fd_gradient", "loss",
     "greedy_colouring", "serial_gabp", "naive_serial_gabp",
-    "aitken_extrapolate", "aitken_gabp",
+    "aitken_extrapolate", "aitken_gabp", "augmented_csr", "augmented_solution",
 ]
 
 
@@ -651,6 +651,47 @@ def convfix_single_loop(n, row_ptr, col, val, b, Gamma, s=0.5, tol=1e-9, max_swe
     if history:
         out["history"] = hist
     return out
+
+
+# ---------------------------------------------------------------------------
+# general (rectangular) systems through the symmetric augmented matrix of
+# Ch. 5 Sec. 5.4
+# ---------------------------------------------------------------------------
+
+def augmented_csr(m, n, row_ptr, col, val, d, gamma):
+    """CSR of the symmetric block matrix [[D, B^T], [B, -gamma I]] for B of m x n.
+
+    B is given as CSR (rows of length n); D = diag(d), d_i != 0; gamma > 0.
+    Unknowns 0..n-1 are x, unknowns n..n+m-1 the auxiliary vector z of Ch. 5
+    Sec. 5.4; the section's own matrix is D = I with right-hand side {0, h}.
+    Returns (N, row_ptr, col, val) with sorted columns and the diagonal stored.
+    """
+    import scipy.sparse as sp
+    B = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col), np.asarray(row_ptr)),
+                      shape=(m, n))
+    K = sp.bmat([[sp.diags(np.asarray(d, dtype=np.float64)), B.T],
+                 [B, -float(gamma) * sp.identity(m)]], format="csr")
+    K.sort_indices()
+    return (n + m, K.indptr.astype(np.int32), K.indices.astype(np.int32),
+            K.data.astype(np.float64))
+
+
+def augmented_solution(m, n, row_ptr, col, val, d, gamma, b=None, h=None):
+    """x-part of the solution of [[D, B^T], [B, -gamma I]] {x, z} = {b, h}, by elimination of z.
+
+    The second block row gives z = (B x - h) / gamma; the first then reads
+    (B^T B / gamma + D) x = b + B^T h / gamma.  With D = I and b = 0 this is
+    the regularised pseudo-inverse solution (B^T B + gamma I)^-1 B^T h of Ch. 5
+    Sec. 5.4, and with h = 0, gamma = 1 it is (B^T B + D)^-1 b.  Dense; small
+    systems only.
+    """
+    B = np.zeros((m, n))
+    rows = _rows_of(row_ptr)
+    np.add.at(B, (rows, np.asarray(col)), np.asarray(val, dtype=np.float64))
+    b = np.zeros(n) if b is None else np.asarray(b, dtype=np.float64)
+    h = np.zeros(m) if h is None else np.asarray(h, dtype=np.float64)
+    S = B.T @ B / gamma + np.diag(np.asarray(d, dtype=np.float64))
+    return dense_solve(S, b + B.T @ h / gamma)
 
 
 # ---------------------------------------------------------------------------

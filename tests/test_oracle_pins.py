@@ -464,6 +464,86 @@ def test_aitken_gabp_on_poisson_converges_sooner_to_the_solution():
 
 
 # ---------------------------------------------------------------------------
+# general (rectangular) systems: the augmented matrix of Ch. 5 Sec. 5.4
+# ---------------------------------------------------------------------------
+
+def _dense_B(q):
+    B = np.zeros((q.m, q.n))
+    rows = np.repeat(np.arange(q.m), np.diff(q.row_ptr))
+    B[rows, q.col] = q.val
+    return B
+
+
+def test_augmented_csr_is_the_block_matrix():
+    q = workloads.ridge_problem(60, 25, 3, 0.5, 3)
+    N, rp, cl, vl = oracle.augmented_csr(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma)
+    assert N == q.m + q.n and len(vl) == q.n + q.m + 2 * len(q.val)
+    for r in range(N):
+        assert np.all(np.diff(cl[rp[r]:rp[r + 1]]) > 0)
+    K = np.zeros((N, N))
+    K[np.repeat(np.arange(N), np.diff(rp)), cl] = vl
+    B = _dense_B(q)
+    np.testing.assert_array_equal(K, K.T)
+    np.testing.assert_array_equal(K[:q.n, :q.n], np.diag(q.d))
+    np.testing.assert_array_equal(K[q.n:, :q.n], B)
+    np.testing.assert_array_equal(K[q.n:, q.n:], -q.gamma * np.eye(q.m))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_augmented_elimination_matches_the_full_block_solve(seed):
+    # the lemma of Ch. 5 Sec. 5.4: the first n unknowns of the block system
+    rng = np.random.default_rng(seed)
+    q = workloads.ridge_problem(50, 20, 3, 0.7, seed)
+    d = rng.uniform(0.2, 2.0, q.n)
+    b, h = rng.normal(size=q.n), rng.normal(size=q.m)
+    for gamma in (0.3, 1.0, 2.5):
+        N, rp, cl, vl = oracle.augmented_csr(q.m, q.n, q.row_ptr, q.col, q.val, d, gamma)
+        K = np.zeros((N, N))
+        K[np.repeat(np.arange(N), np.diff(rp)), cl] = vl
+        full = np.linalg.solve(K, np.concatenate([b, h]))
+        x = oracle.augmented_solution(q.m, q.n, q.row_ptr, q.col, q.val, d, gamma, b, h)
+        np.testing.assert_allclose(x, full[:q.n], rtol=1e-10, atol=1e-12 * np.abs(full).max())
+        # z is the scaled residual of the second block row
+        np.testing.assert_allclose(full[q.n:], (_dense_B(q) @ x - h) / gamma, rtol=1e-9,
+                                   atol=1e-11 * np.abs(full).max())
+
+
+def test_ridge_form_tends_to_the_pseudo_inverse_solution():
+    # D = I, b = 0: x = (B^T B + gamma I)^-1 B^T h -> the least-squares solution as gamma -> 0
+    q = workloads.ridge_problem(80, 30, 4, 1e-9, 4)
+    x = oracle.augmented_solution(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma, q.b, q.h)
+    ls = np.linalg.lstsq(_dense_B(q), q.h, rcond=None)[0]
+    np.testing.assert_allclose(x, ls, rtol=1e-6, atol=1e-8)
+
+
+def test_augmented_workload_is_the_btb_workload():
+    p = workloads.config5(2048)
+    q = workloads.augmented_config(2048)
+    np.testing.assert_array_equal(p.b, q.b)
+    x = oracle.augmented_solution(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma, q.b, q.h)
+    np.testing.assert_allclose(x, oracle.dense_solve(p.dense(), p.b), rtol=1e-11, atol=1e-12)
+
+
+def test_double_loop_solves_the_augmented_system():
+    # the section runs the double loop of Ch. 5 on the augmented matrix,
+    # loaded until its rescaled form is walk-summable
+    q = workloads.ridge_problem(600, 250, 3, 0.5, 5)
+    N, rp, cl, vl = oracle.augmented_csr(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma)
+    _, hi = oracle.walk_rho(N, rp, cl, vl)
+    assert hi > 1.0                                  # not walk-summable unloaded
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    diag = np.zeros(N)
+    diag[rows[rows == cl]] = vl[rows == cl]
+    Gamma = oracle.walk_loading(hi, 0.05) * diag
+    rhs = np.concatenate([q.b, q.h])
+    # exact inner solves: the outer step then contracts at rho((K + Gamma)^-1 Gamma) < 1
+    r = oracle.convfix_gabp(N, rp, cl, vl, rhs, Gamma, tol=1e-9, max_outer=2000, inner_tol=1e-13)
+    assert r["converged"]
+    x = oracle.augmented_solution(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma, q.b, q.h)
+    assert np.linalg.norm(r["x"][:q.n] - x) <= 1e-7 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: each plausible slip in the broadcast oracle fails a pin
 # ---------------------------------------------------------------------------
 

@@ -229,10 +229,8 @@ def config4(p=64):
     return grid3d_problem(p, SEED_BASE + 4, name=f"grid3d-{p}^3")
 
 
-def config5(n=1 << 20, rows=None, per_row=4, shift=0.1):
-    """A = B^T B + shift*I with B (rows x n) having per_row distinct N(0,1) entries per row."""
-    rows = 2 * n if rows is None else rows
-    rng = np.random.default_rng(SEED_BASE + 5)
+def rect_rows(rng, rows, n, per_row):
+    """B (rows x n, SciPy CSR) with per_row distinct uniform columns per row and N(0,1) values."""
     cols = rng.integers(0, n, (rows, per_row), dtype=np.int64)
     while True:  # redraw rows holding a repeated column
         s = np.sort(cols, axis=1)
@@ -241,8 +239,52 @@ def config5(n=1 << 20, rows=None, per_row=4, shift=0.1):
             break
         cols[bad] = rng.integers(0, n, (len(bad), per_row), dtype=np.int64)
     vals = rng.standard_normal((rows, per_row))
-    Bm = sp.csr_matrix((vals.ravel(), cols.ravel(),
-                        np.arange(0, rows * per_row + 1, per_row)), shape=(rows, n))
+    return sp.csr_matrix((vals.ravel(), cols.ravel(),
+                          np.arange(0, rows * per_row + 1, per_row)), shape=(rows, n))
+
+
+class RectProblem:
+    """[[D, B^T], [B, -gamma I]] {x, z} = {b, h}: B (m x n) as CSR with sorted columns."""
+
+    def __init__(self, m, n, row_ptr, col, val, d, gamma, b, h, name=""):
+        self.m, self.n = m, n
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        self.d, self.gamma, self.b, self.h = d, gamma, b, h
+        self.name = name
+
+
+def augmented_config(n=1 << 20, rows=None, per_row=4, shift=0.1):
+    """The B^T B + shift I system of config5, posed without forming B^T B.
+
+    Same seed and draws as config5 (B, then b): D = shift I, gamma = 1, h = 0,
+    so the x-part of the augmented solution is (B^T B + shift I)^-1 b.
+    """
+    rows = 2 * n if rows is None else rows
+    rng = np.random.default_rng(SEED_BASE + 5)
+    Bm = rect_rows(rng, rows, n, per_row)
+    b = rng.standard_normal(n)
+    Bm.sort_indices()
+    return RectProblem(rows, n, Bm.indptr.astype(np.int32), Bm.indices.astype(np.int32),
+                       Bm.data.astype(np.float64), np.full(n, shift), 1.0, b, np.zeros(rows),
+                       name=f"augmented-B{rows}x{n}+{shift}I")
+
+
+def ridge_problem(m, n, per_row, gamma, seed):
+    """The section's own form: D = I, b = 0, h ~ N(0,1): x = (B^T B + gamma I)^-1 B^T h."""
+    rng = np.random.default_rng(seed)
+    Bm = rect_rows(rng, m, n, per_row)
+    h = rng.standard_normal(m)
+    Bm.sort_indices()
+    return RectProblem(m, n, Bm.indptr.astype(np.int32), Bm.indices.astype(np.int32),
+                       Bm.data.astype(np.float64), np.ones(n), float(gamma), np.zeros(n), h,
+                       name=f"ridge-B{m}x{n}-g{gamma}")
+
+
+def config5(n=1 << 20, rows=None, per_row=4, shift=0.1):
+    """A = B^T B + shift*I with B (rows x n) having per_row distinct N(0,1) entries per row."""
+    rows = 2 * n if rows is None else rows
+    rng = np.random.default_rng(SEED_BASE + 5)
+    Bm = rect_rows(rng, rows, n, per_row)
     A = (Bm.T @ Bm).tocsr()
     A = ((A + A.T) * 0.5).tocsr()          # exact symmetry of the stored values
     A = (A + shift * sp.identity(n, format="csr")).tocsr()
