@@ -248,6 +248,49 @@ gabp_status gabp_backward(gabp_handle h, const double *x, const double *grad_x,
                           gabp_info *info);
 
 /*
+ * gabp_create_augmented -- a general, possibly over-determined, system through
+ * the symmetric augmented matrix of Ch. 5 Sec. 5.4 (extension to general
+ * linear systems):
+ *     K = [[D, B^T], [B, -gamma I]]   over the unknowns {x (n), z (m)},
+ * so that B^T B is never formed.  Eliminating z = (B x - h) / gamma from
+ * K {x, z} = {b, h} leaves (B^T B / gamma + D) x = b + B^T h / gamma; the
+ * section's own matrix is D = I with right-hand side {0, h}, whose x-part is
+ * the regularised least-squares solution (B^T B + gamma I)^-1 B^T h.
+ *   m, n       B is m x n (m >= 1, n >= 1, m + n < 2^31)
+ *   row_ptr, col_idx, vals   device CSR of B: int32 [m+1] (row_ptr[0] = 0),
+ *              int32 [nnz] strictly increasing within a row and in [0, n),
+ *              float64 [nnz], finite
+ *   d          device float64 [n]: the diagonal D, finite and nonzero
+ *   gamma      > 0, finite: the lower right block is -gamma I
+ *   opts, stream, out   as gabp_create.  K is indefinite, so the plain
+ *              iteration does not converge on it: the section runs the
+ *              double loop of Ch. 5, i.e. opts->gamma != 0 (< 0: the loading
+ *              picked from rho(|R|)).  With opts == NULL the defaults are
+ *              used with opts->gamma = -1.
+ * K (n + m unknowns, n + m + 2 nnz(B) stored entries, x first) is assembled
+ * on the host at create and ingested as by gabp_create; the handle works with
+ * every entry point that takes a single-system handle, on vectors of length
+ * n + m.  Errors: GABP_E_ARG for a malformed B, d or gamma, otherwise those of
+ * gabp_create.
+ */
+gabp_status gabp_create_augmented(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                  const double *vals, const double *d, double gamma,
+                                  const gabp_opts *opts, hipStream_t stream, gabp_handle *out);
+
+/*
+ * gabp_solve_augmented -- solve K {x, z} = {b, h} on a handle made by
+ * gabp_create_augmented and return the blocks (Ch. 5 Sec. 5.4).
+ *   b          device float64 [n], nullable (zero)
+ *   h          device float64 [m], nullable (zero)
+ *   x          device float64 [n] (output)
+ *   z          device float64 [m] (output, nullable)
+ *   tol, max_iter, info   as gabp_solve; the residual is that of K.
+ * GABP_E_ARG on a handle not made by gabp_create_augmented.
+ */
+gabp_status gabp_solve_augmented(gabp_handle hdl, const double *b, const double *h, double *x, double *z,
+                                 double tol, int32_t max_iter, gabp_info *info);
+
+/*
  * gabp_create_batched -- many independent systems in one handle.
  *   num_sys      number of systems (>= 1)
  *   sys_row_off  HOST int32 [num_sys+1]: system s owns global rows

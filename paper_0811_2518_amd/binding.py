@@ -31,7 +31,7 @@ LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
-           "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
+           "gabp_create_augmented", "gabp_solve_augmented", "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
            "gabp_plan_rows", "gabp_get_props",
            "gabp_destroy", "gabp_last_error")
 
@@ -93,6 +93,11 @@ def lib():
     L.gabp_messages.restype = c_i32
     L.gabp_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32, P(Info)]
     L.gabp_backward.restype = c_i32
+    L.gabp_create_augmented.argtypes = [c_i32, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, P(Opts),
+                                        c_void_p, P(c_void_p)]
+    L.gabp_create_augmented.restype = c_i32
+    L.gabp_solve_augmented.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32, P(Info)]
+    L.gabp_solve_augmented.restype = c_i32
     L.gabp_create_batched.argtypes = [c_i32, c_void_p, c_void_p, c_void_p, c_void_p, P(Opts), c_void_p,
                                       P(c_void_p)]
     L.gabp_create_batched.restype = c_i32
@@ -286,6 +291,65 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class AugmentedSolver(Solver):
+    """A rectangular B (m x n) through the symmetric matrix [[D, B^T], [B, -gamma I]] (Ch. 5 Sec. 5.4).
+
+    ``solve`` and ``backward`` of the base class act on the whole system of
+    n + m unknowns; ``solve_blocks`` takes the right-hand side {b, h} in its
+    two blocks and returns x (and z).  ``loading`` is the diagonal loading of
+    the double loop (< 0: picked from rho(|R|)); the system is indefinite, so
+    the plain iteration (loading 0) does not converge on it.
+    """
+
+    def __init__(self, m, n, row_ptr, col, val, d, gamma, *, loading=-1.0, precision="fp64", check_every=1,
+                 edges_per_block=0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
+                 layout="auto", single_loop=False, damping=0.5, natural_order=False, device="cuda",
+                 stream=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream, sh = _stream_handle(stream)
+        self.m_rows, self.n_cols = int(m), int(n)
+        B_rp = _dev(row_ptr, torch.int32, self.device)
+        B_col = _dev(col, torch.int32, self.device)
+        B_val = _dev(val, torch.float64, self.device)
+        dd = _dev(d, torch.float64, self.device)
+        self.opts = default_opts(
+            precision={"fp64": FP64, "fp32": FP32_REFINE, "fp32_refine": FP32_REFINE}[precision],
+            check_every=check_every, edges_per_block=edges_per_block, gamma=loading,
+            loading_delta=loading_delta, inner_tol=inner_tol, inner_max_iter=inner_max_iter,
+            max_outer=max_outer, layout=LAYOUTS[layout], damping=damping,
+            flags=(FLAG_SINGLE_LOOP if single_loop else 0) | (FLAG_NATURAL_ORDER if natural_order else 0))
+        h = ctypes.c_void_p()
+        st = lib().gabp_create_augmented(self.m_rows, self.n_cols, _ptr(B_rp), _ptr(B_col), _ptr(B_val), _ptr(dd),
+                                         float(gamma), ctypes.byref(self.opts), sh, ctypes.byref(h))
+        if st != OK:
+            raise _err(None, st, "gabp_create_augmented")
+        self._h = h
+        self.n = self.n_cols + self.m_rows
+
+    def backward(self, x, grad_x, tol=1e-12, max_iter=5000, grad_vals=False, check=True):
+        """Adjoint solve on the whole system; the gradient on K's entries is not offered (K is internal)."""
+        if grad_vals:
+            raise ValueError("grad_vals needs the caller's CSR; an augmented handle assembles its own")
+        return super().backward(x, grad_x, tol, max_iter, grad_vals=False, check=check)
+
+    def solve_blocks(self, b=None, h=None, tol=1e-9, max_iter=100000, *, x=None, z=False, check=True):
+        """x (and z) of [[D, B^T], [B, -gamma I]] {x, z} = {b, h}.  Returns (x, info[, z])."""
+        torch = _torch()
+        bb = None if b is None else _dev(b, torch.float64, self.device)
+        hh = None if h is None else _dev(h, torch.float64, self.device)
+        x = torch.empty(self.n_cols, dtype=torch.float64, device=self.device) if x is None else x
+        zz = torch.empty(self.m_rows, dtype=torch.float64, device=self.device) if z else None
+        info = Info()
+        st = lib().gabp_solve_augmented(self._h, _ptr(bb), _ptr(hh), _ptr(x), _ptr(zz), float(tol), int(max_iter),
+                                        ctypes.byref(info))
+        if check and st < 0:
+            raise _err(self._h, st, "gabp_solve_augmented")
+        d = info.as_dict()
+        d["status"] = st
+        return (x, d, zz) if z else (x, d)
 
 
 def last_create_error() -> str:

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gabp_internal.h"
 
@@ -152,6 +153,67 @@ void release_unused_layout(Ctx* c) {
 
 bool plain_mode(const Ctx* c) { return c->opts.precision == GABP_FP64 && c->gamma_used == 0.0 && c->opts.gamma == 0.0; }
 bool single_loop_mode(const Ctx* c) { return !plain_mode(c) && (c->opts.flags & GABP_FLAG_SINGLE_LOOP); }
+
+// The symmetric augmented matrix of Ch. 5 Sec. 5.4, [[D, B^T], [B, -gamma I]],
+// assembled on the host from a validated B (m x n CSR with sorted columns).
+// Rows 0..n-1 hold D_ii, then the entries of B^T in increasing row of B
+// (columns n + r); rows n..n+m-1 hold row r of B, then -gamma on the diagonal,
+// so every row's columns increase.
+struct HostCsr {
+  std::vector<int32_t> row_ptr, col;
+  std::vector<double> val;
+};
+
+std::string check_rect(int32_t m, int32_t n, const std::vector<int32_t>& bp, const std::vector<int32_t>& bc,
+                       const std::vector<double>& bv, const std::vector<double>& d, double gamma) {
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) return "gamma must be finite and > 0";
+  for (int32_t i = 0; i < n; ++i)
+    if (!(d[i] != 0.0) || !std::isfinite(d[i])) return "d must be finite and nonzero";
+  if (bp[0] != 0) return "row_ptr[0] must be 0";
+  for (int32_t r = 0; r < m; ++r)  // first, so that every row lies inside the nnz entries copied
+    if (bp[r + 1] < bp[r]) return "row_ptr decreases";
+  for (int32_t r = 0; r < m; ++r) {
+    for (int32_t e = bp[r]; e < bp[r + 1]; ++e) {
+      if (bc[e] < 0 || bc[e] >= n) return "column index out of [0, n)";
+      if (e > bp[r] && bc[e] <= bc[e - 1]) return "columns of a row must increase strictly";
+      if (!std::isfinite(bv[e])) return "non-finite value in B";
+    }
+  }
+  return "";
+}
+
+HostCsr assemble_augmented(int32_t m, int32_t n, const std::vector<int32_t>& bp, const std::vector<int32_t>& bc,
+                           const std::vector<double>& bv, const std::vector<double>& d, double gamma) {
+  const int32_t N = n + m;
+  const int64_t nnzB = bp[m];
+  std::vector<int64_t> cnt(n, 0);  // entries per column of B = per row of B^T
+  for (int64_t e = 0; e < nnzB; ++e) ++cnt[bc[e]];
+  HostCsr K;
+  K.row_ptr.assign(N + 1, 0);
+  for (int32_t i = 0; i < n; ++i) K.row_ptr[i + 1] = K.row_ptr[i] + 1 + (int32_t)cnt[i];
+  for (int32_t r = 0; r < m; ++r) K.row_ptr[n + r + 1] = K.row_ptr[n + r] + (bp[r + 1] - bp[r]) + 1;
+  K.col.resize(K.row_ptr[N]);
+  K.val.resize(K.row_ptr[N]);
+  std::vector<int32_t> next(n);
+  for (int32_t i = 0; i < n; ++i) {
+    K.col[K.row_ptr[i]] = i;
+    K.val[K.row_ptr[i]] = d[i];
+    next[i] = K.row_ptr[i] + 1;
+  }
+  for (int32_t r = 0; r < m; ++r) {
+    int32_t q = K.row_ptr[n + r];
+    for (int32_t e = bp[r]; e < bp[r + 1]; ++e, ++q) {
+      const int32_t c = bc[e];
+      K.col[next[c]] = n + r;  // B^T entry (c, n + r)
+      K.val[next[c]++] = bv[e];
+      K.col[q] = c;            // B entry (n + r, c)
+      K.val[q] = bv[e];
+    }
+    K.col[q] = n + r;
+    K.val[q] = -gamma;
+  }
+  return K;
+}
 
 }  // namespace
 
@@ -306,6 +368,95 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
     GABP_HIP(c, launch_grad_vals(c->row_ptr_d, c->col_d, grad_b, x, grad_vals, c->n, c->stream));
     GABP_HIP(c, hipStreamSynchronize(c->stream));
   }
+  return r;
+}
+
+gabp_status gabp_create_augmented(int32_t m, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                  const double* vals, const double* d, double gamma, const gabp_opts* opts,
+                                  hipStream_t stream, gabp_handle* out) {
+  if (!out) return fail(nullptr, GABP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (m < 1 || n < 1 || (int64_t)n + m >= INT32_MAX) return fail(nullptr, GABP_E_ARG, "m >= 1 and n >= 1");
+  if (!row_ptr || !col_idx || !vals || !d) return fail(nullptr, GABP_E_ARG, "NULL B or d");
+  // B and D to the host
+  std::vector<int32_t> bp(m + 1);
+  std::vector<double> dh(n);
+  hipError_t e = hipMemcpyAsync(bp.data(), row_ptr, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dh.data(), d, sizeof(double) * n, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "copy of B");
+  const int64_t nnzB = bp[m];
+  if (bp[0] != 0 || nnzB < 0 || (int64_t)n + m + 2 * nnzB >= INT32_MAX)
+    return fail(nullptr, GABP_E_ARG, "row_ptr[0] must be 0 and the augmented matrix must fit int32 indices");
+  std::vector<int32_t> bc(nnzB);
+  std::vector<double> bv(nnzB);
+  if (nnzB > 0) {
+    e = hipMemcpyAsync(bc.data(), col_idx, sizeof(int32_t) * nnzB, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(bv.data(), vals, sizeof(double) * nnzB, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "copy of B");
+  }
+  const std::string bad = check_rect(m, n, bp, bc, bv, dh, gamma);
+  if (!bad.empty()) return fail(nullptr, GABP_E_ARG, bad);
+  const HostCsr K = assemble_augmented(m, n, bp, bc, bv, dh, gamma);
+  gabp_opts o;
+  if (opts) o = *opts;
+  else {
+    gabp_default_opts(&o);
+    o.gamma = -1.0;
+  }
+  // ingest as any symmetric system (the library copies what it keeps)
+  const int32_t N = n + m;
+  const size_t nnzK = K.col.size();
+  void *rp_d = nullptr, *cl_d = nullptr, *vl_d = nullptr;
+  e = hipMalloc(&rp_d, sizeof(int32_t) * (N + 1));
+  if (e == hipSuccess) e = hipMalloc(&cl_d, sizeof(int32_t) * nnzK);
+  if (e == hipSuccess) e = hipMalloc(&vl_d, sizeof(double) * nnzK);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rp_d, K.row_ptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(cl_d, K.col.data(), sizeof(int32_t) * nnzK, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(vl_d, K.val.data(), sizeof(double) * nnzK, hipMemcpyHostToDevice, stream);
+  gabp_status r = GABP_OK;
+  if (e != hipSuccess) r = hip_fail(nullptr, e, "upload of the augmented matrix");
+  gabp_handle h = nullptr;
+  if (r == GABP_OK) r = gabp_create(N, (const int32_t*)rp_d, (const int32_t*)cl_d, (const double*)vl_d, &o, stream, &h);
+  (void)hipStreamSynchronize(stream);
+  (void)hipFree(rp_d);
+  (void)hipFree(cl_d);
+  (void)hipFree(vl_d);
+  if (r != GABP_OK) return r;
+  Ctx* c = h;
+  c->aug_n = n;
+  c->aug_m = m;
+  r = dev_alloc(c, (void**)&c->aug_rhs_d, sizeof(double) * N);
+  if (r == GABP_OK) r = dev_alloc(c, (void**)&c->aug_x_d, sizeof(double) * N);
+  if (r != GABP_OK) {
+    tl_error = c->err;
+    gabp_destroy(h);
+    return r;
+  }
+  *out = h;
+  return GABP_OK;
+}
+
+gabp_status gabp_solve_augmented(gabp_handle hdl, const double* b, const double* h, double* x, double* z,
+                                 double tol, int32_t max_iter, gabp_info* info) {
+  if (!hdl) return fail(nullptr, GABP_E_ARG, "NULL handle");
+  Ctx* c = hdl;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (c->aug_n < 0) return fail(c, GABP_E_ARG, "not a handle of gabp_create_augmented");
+  if (!x) return fail(c, GABP_E_ARG, "NULL x");
+  const int32_t n = c->aug_n, m = c->aug_m;
+  hipStream_t s = c->stream;
+  if (b) GABP_HIP(c, hipMemcpyAsync(c->aug_rhs_d, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  else GABP_HIP(c, launch_fill(c->aug_rhs_d, n, 0.0, s));
+  if (h) GABP_HIP(c, hipMemcpyAsync(c->aug_rhs_d + n, h, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+  else GABP_HIP(c, launch_fill(c->aug_rhs_d + n, m, 0.0, s));
+  const gabp_status r = gabp_solve(hdl, c->aug_rhs_d, c->aug_x_d, nullptr, tol, max_iter, info);
+  if (r < 0) return r;
+  GABP_HIP(c, hipMemcpyAsync(x, c->aug_x_d, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (z) GABP_HIP(c, hipMemcpyAsync(z, c->aug_x_d + n, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+  GABP_HIP(c, hipStreamSynchronize(s));
   return r;
 }
 

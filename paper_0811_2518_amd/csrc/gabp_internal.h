@@ -319,6 +319,9 @@ struct Ctx {
   std::vector<int32_t> colour_h;      // [n] colour of each caller row
   int32_t* slot_of_d = nullptr;       // [E] caller slot of each internal slot (XCD order only)
   double* msg_tmp_d = nullptr;        // [2E] exported messages in internal slot order (XCD order only)
+  int32_t aug_n = -1, aug_m = 0;      // augmented handle: x and z block sizes (-1: not one)
+  double* aug_rhs_d = nullptr;        // [n] right-hand side {b, h} of an augmented solve
+  double* aug_x_d = nullptr;          // [n] its solution {x, z}
   double* ait_y_d = nullptr;          // [n] Aitken estimate (GABP_FLAG_AITKEN)
   double* ait_hist_d = nullptr;       // [n] x_{t-2} for the next Aitken step
   int32_t nparts = 0;                 // XCD order: parts per group (8), else 0
