@@ -127,6 +127,34 @@ def test_full_btb_convergence_fix(btb_full, mode):
     assert relres(p.scipy(), x.cpu().numpy(), p.b) <= 1.05e-9
 
 
+def test_full_btb_through_the_augmented_matrix():
+    # the same B^T B + 0.1 I system, posed as [[0.1 I, B^T], [B, -I]] {x, z} = {b, 0}
+    # (Ch. 5 Sec. 5.4); both residuals are formed from B on the host, never from B^T B
+    import scipy.sparse as sp
+    q = workloads.augmented_config()
+    print(f"augmented: m {q.m}, n {q.n}, nnz(B) {len(q.val)}", flush=True)
+    s = g.AugmentedSolver(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma, precision="fp32", inner_tol=1e-2,
+                          inner_max_iter=2000, max_outer=5000, device=DEV)
+    pr = s.props()
+    assert pr["n"] == q.n + q.m and pr["num_offdiag"] == 2 * len(q.val)
+    assert pr["rho_hi"] > 1.0 and pr["gamma"] > 0.0
+    x, info, z = s.solve_blocks(b=torch.from_numpy(q.b).to(DEV), tol=1e-9, max_iter=1000000, z=True)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-9
+    B = sp.csr_matrix((q.val, q.col, q.row_ptr), shape=(q.m, q.n))
+    xh, zh = x.cpu().numpy(), z.cpu().numpy()
+    # the K residual, recomputed: {b - D x - B^T z, -B x + gamma z}
+    r1 = q.b - q.d * xh - B.T @ zh
+    r2 = -(B @ xh) + q.gamma * zh
+    rk = np.sqrt(r1 @ r1 + r2 @ r2) / np.linalg.norm(q.b)
+    assert rk <= 1.05e-9
+    # the eliminated system (B^T B + 0.1 I) x = b: its residual is r1 - B^T r2 (gamma = 1),
+    # so it is at most (1 + ||B||_2) times K's, with ||B||_2 <= sqrt(||B||_1 ||B||_inf)
+    r = q.b - B.T @ (B @ xh) - q.d * xh
+    aB = abs(B)
+    nB = float(np.sqrt(aB.sum(axis=0).max() * aB.sum(axis=1).max()))
+    assert np.linalg.norm(r) / np.linalg.norm(q.b) <= (1.0 + nB) * rk * (1 + 1e-9)
+
+
 @pytest.fixture(scope="module")
 def powerlaw_full():
     return workloads.powerlaw_config()
