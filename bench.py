@@ -648,6 +648,51 @@ def probe(torch, g, workloads, args):
     torch.cuda.synchronize()
 
 
+def extras(torch, g, workloads, args):
+    """The opt-in variants on their own, for a kernel trace: Aitken's extrapolation on G(n, 4n)
+    and on the Poisson example of Ch. 4 Sec. 4.3, and the B^T B + 0.1 I system through the
+    augmented matrix of Ch. 5 Sec. 5.4.  Prints one JSON line."""
+    out = {}
+    reps = max(1, min(args.steps, 3))
+    p = workloads.config2(args.n)
+    b = torch.from_numpy(p.b).to("cuda")
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    for ce in (1, 4):
+        for ait in (False, True):
+            log(f"G(n,4n): aitken={ait} check_every={ce}")
+            s = g.Solver(p.row_ptr, p.col, p.val, layout="compact", edges_per_block=512, reuse_precision=False,
+                         aitken=ait, check_every=ce)
+            s.solve(b, tol=TOL, max_iter=2000, x=x)  # warm-up
+            dt, (_, info) = timed(torch, lambda: s.solve(b, tol=TOL, max_iter=2000, x=x), reps=reps)
+            out[f"er_n2e20_{'aitken' if ait else 'plain'}_check{ce}"] = {
+                "time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "status": info["status"]}
+            s.close()
+    for side, tol in ((10, 1e-10), (32, 1e-6)):
+        q = workloads.poisson2d(side)
+        bq = torch.from_numpy(q.b).to("cuda")
+        for ait in (False, True):
+            log(f"Poisson p={side}: aitken={ait}")
+            s = g.Solver(q.row_ptr, q.col, q.val, layout="compact", reuse_precision=False, aitken=ait)
+            s.solve(bq, tol=tol, max_iter=200000)  # warm-up
+            dt, (_, info) = timed(torch, lambda: s.solve(bq, tol=tol, max_iter=200000), reps=reps)
+            out[f"poisson{side}_tol{tol:g}_{'aitken' if ait else 'plain'}"] = {
+                "time_to_tol_ms": 1e3 * dt, "sweeps": info["sweeps"], "status": info["status"]}
+            s.close()
+    log("augmented B^T B + 0.1 I")
+    q = workloads.augmented_config(args.n)
+    bq = torch.from_numpy(q.b).to("cuda")
+    sa = g.AugmentedSolver(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma, precision="fp32", inner_tol=1e-2,
+                           inner_max_iter=2000, max_outer=5000)
+    sa.solve_blocks(b=bq, tol=1e-9, max_iter=1000000, check=False)  # warm-up
+    dt, (_, info) = timed(torch, lambda: sa.solve_blocks(b=bq, tol=1e-9, max_iter=1000000, check=False), reps=reps)
+    pa = sa.props()
+    out["augmented_btb_fp32_inner"] = {"unknowns": pa["n"], "E": pa["num_offdiag"], "time_to_tol_ms": 1e3 * dt,
+                                       "outer_iters": info["outer_iters"], "inner_sweeps": info["sweeps"],
+                                       "status": info["status"], "rel_residual_K": info["rel_residual"]}
+    sa.close()
+    print(json.dumps({"extras": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -660,6 +705,8 @@ def main():
                     help="skip the other workloads (grid, adjoint, convergence fix, batched)")
     ap.add_argument("--probe", action="store_true",
                     help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
+    ap.add_argument("--extras", action="store_true",
+                    help="time the opt-in variants (Aitken's extrapolation, the augmented solve) on their own")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from the FETCH_SIZE and WRITE_SIZE counter runs "
                          "of the probe (no GPU needed)")
@@ -679,6 +726,9 @@ def main():
 
     if args.probe:
         probe(torch, g, workloads, args)
+        return
+    if args.extras:
+        extras(torch, g, workloads, args)
         return
 
     log("generating the G(n,4n) workload")
