@@ -132,7 +132,9 @@ typedef struct {
  * sweeps, y_{max_iter} returned), gabp_info.sweeps = t, and var (when asked
  * for) holds the variances of sweep t.  A large residual of y_t is not taken
  * for divergence (a node whose second difference nears zero can jump far for
- * one round); a NaN still is.  No precision messages are frozen for reuse. */
+ * one round); a NaN still is.  No precision messages are frozen for reuse.
+ * With GABP_FLAG_TIME_SWEEPS every sweep is timed (the sweeps carry no fused
+ * check; the Aitken step and the residual of y are not included). */
 #define GABP_FLAG_AITKEN 16
 
 typedef struct {

@@ -378,7 +378,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
       hipEvent_t e0, e1;
-      start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && ck, &e0, &e1);
+      start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && (ck || ait), &e0, &e1);
       if (e0) c->timed_mode = cfg.honly ? 1 : 0;
       GABP_HIP(c, launch_cnode<T>(mode, c->K, k, s, e0, e1));
       if (ck)

@@ -247,3 +247,11 @@ def test_fewer_than_three_rounds_is_an_argument_error():
     for M in (0, 1):
         _, info = s.solve(dev(p.b), tol=0, max_iter=M, check=False)
         assert info["status"] == binding.E_ARG
+
+
+def test_sweep_timing_covers_every_sweep():
+    p = workloads.grid2d_problem(30, 30, seed=2)
+    s = solver(p, time_sweeps=True)
+    _, info = s.solve(dev(p.b), tol=1e-10, max_iter=2000)
+    # every queued sweep is timed, including those that return at once past convergence
+    assert info["timed_sweeps"] >= info["sweeps"] and info["sweep_ms"] > 0
