@@ -255,3 +255,21 @@ def test_sweep_timing_covers_every_sweep():
     _, info = s.solve(dev(p.b), tol=1e-10, max_iter=2000)
     # every queued sweep is timed, including those that return at once past convergence
     assert info["timed_sweeps"] >= info["sweeps"] and info["sweep_ms"] > 0
+
+
+@pytest.mark.parametrize("variant", ["aitken", "single_loop"])
+def test_autotune_cache_keeps_the_compact_layout(tmp_path, monkeypatch, variant):
+    # a plain handle tunes over every layout and caches its choice; handles that
+    # need the compact layout are keyed by that request and never take another
+    monkeypatch.setenv("GABP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    p = workloads.er_problem(65536, 8, 31)
+    assert p.num_offdiag >= 200000                  # large enough to be timed at create
+    g.Solver(p.row_ptr, p.col, p.val, device=DEV).close()
+    kw = dict(aitken=True) if variant == "aitken" else dict(single_loop=True, gamma=-1.0)
+    for _ in range(2):                               # timed, then from the cache
+        s = g.Solver(p.row_ptr, p.col, p.val, device=DEV, **kw)
+        assert s.props()["layout"] == binding.LAYOUTS["compact"]
+        _, info = s.solve(dev(p.b), tol=1e-10, max_iter=2000)
+        assert info["status"] == binding.OK
+        s.close()
+    assert "L3" in (tmp_path / "tune.txt").read_text()
