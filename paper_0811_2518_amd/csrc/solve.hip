@@ -85,8 +85,8 @@ gabp_status finish_run(Ctx* c, const Poller& p) {
 }
 
 // Size of the next chunk of sweeps.  The first chunk reaches the sweep that
-// checks the second checked round; without a usable history the chunks then
-// double up to 16.  Once two checked rounds have been observed (the device
+// checks the second checked round; the second has the same size; without a
+// usable history the chunks then double up to 16.  Once two checked rounds have been observed (the device
 // status carries the last two), the relative residual's decay rate predicts
 // the round that reaches tol, and the chunk only covers the sweeps up to the
 // one that checks that round (a zero chunk just polls the sweeps already
@@ -101,7 +101,9 @@ struct ChunkPlan {
     return chunk;
   }
   int next(const Poller& p, int queued_through, int lag, int check_every, double tol) {
-    int c = std::min(chunk * 2, 16);
+    // no status seen yet: keep the first size (a short solve, such as an inner
+    // solve of a few sweeps, then queues few sweeps past its end)
+    int c = p.have ? std::min(chunk * 2, 16) : chunk;
     if (p.have && p.seen.last_round > round1) {
       if (p.seen.prev_round >= 0) {
         rel0 = p.seen.prev_rel;
