@@ -24,6 +24,8 @@
  *    [n+1] (row_ptr[0] = 0), int32 col_idx [nnz] strictly increasing within a
  *    row, float64 vals [nnz].  The pattern and the values must be symmetric
  *    (|A_ij - A_ji| <= 1e-12 * max|A|) and every A_ii must be nonzero.
+ *    gabp_create_augmented is the exception: it takes a rectangular B (no
+ *    diagonal, no symmetry) and builds the symmetric matrix itself.
  *  * Nothing throws across the ABI.  A negative status is an error (outputs
  *    unspecified); GABP_NOT_CONVERGED still writes the last iterate.
  *    gabp_last_error() returns a description of the last failure.
