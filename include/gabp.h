@@ -139,6 +139,16 @@ typedef struct {
  * check; the Aitken step and the residual of y are not included). */
 #define GABP_FLAG_AITKEN 16
 
+/* Run one launch per sweep even where the whole solve fits one workgroup.
+ * Without the flag, a plain FP64 solve (no reuse of frozen precisions, no
+ * Aitken step, no sweep timing) on a compact-layout handle with n <= 1024 rows
+ * and at most 4096 directed slots runs every sweep, check and stop decision
+ * inside one launch of 1024 lanes, with the messages in registers and the
+ * aggregates in LDS.  Both paths perform the same operations; x, the
+ * variances and the messages agree bit for bit, the reported residual up to
+ * its summation order. */
+#define GABP_FLAG_MULTI_LAUNCH 32
+
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
   int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */

@@ -222,6 +222,34 @@ struct SerialArgs {
   int32_t wl;              // store the earlier classes' residual part for the next sweep
 };
 
+// One-workgroup solve of a small system (small.hip): the whole synchronous
+// iteration in one launch of kSmallLanes lanes, for n <= kSmallLanes rows and
+// at most 4 kSmallLanes directed slots.
+constexpr int kSmallLanes = 1024;
+struct SmallArgs {
+  int32_t n;
+  int32_t E;
+  const int32_t* off_ptr;   // [n+1] off-diagonal CSR
+  const int32_t* col;       // [E]
+  const double* a;          // [E]
+  const double* diag;       // [n]
+  const double* rhs;        // [n]
+  const double* rhs_norm;   // device scalar ||rhs||_2 (nullable: formed in the kernel)
+  double tol;               // <= 0: exactly max_iter sweeps
+  int32_t max_iter;
+  int32_t check_every;
+  DevStatus* st;            // written once, at the end (as the finish kernels leave it)
+  double* xout[2];          // nullable: x of the returned round into [round & 1]
+  double* ptout[2];         // nullable: P~ of the returned round into [round & 1]
+  double* x_direct;         // nullable: x of the returned round
+  double* var_direct;       // nullable: 1 / P~ of the returned round
+  void* cin_out;            // nullable: [2][E] {P, h} incoming messages by round parity
+  void* agg_out[3];         // nullable: [n] {P~, h~} aggregates by round mod 3
+  const int32_t* gate;      // nullable: nonzero -> the kernel returns at once
+};
+bool small_fits(int64_t n, int64_t E);
+hipError_t launch_small(const SmallArgs& a, hipStream_t s);
+
 constexpr int kLayoutEdge = 1;     // outgoing message records + reverse-slot index
 constexpr int kLayoutNode = 2;     // node broadcast: aggregates published, edge pairs kept in place
 constexpr int kLayoutCompact = 3;  // node broadcast, one incoming message per slot, outgoing recomputed

@@ -1,0 +1,278 @@
+// One-workgroup solve of a small system: every sweep of the synchronous
+// iteration of Alg. 2 (Ch. 3 Sec. 3.3), the fused residual checks and the stop
+// rule run inside a single launch of 1024 lanes.
+//
+// A small system (n <= 1024 rows, E <= 4096 directed slots) spends more time
+// in kernel launches and host polling than in arithmetic when every sweep is a
+// launch of its own.  Here the whole state stays on chip:
+//   * lane l owns the slots l, l + 1024, ... of the off-diagonal CSR and keeps
+//     the incoming messages of its slots of the last two rounds in registers
+//     (the compact recurrence: in^(t) depends on in^(t-2) of the same slot
+//     only, so messages are never exchanged between lanes);
+//   * the node aggregates {P~, h~} of the last three rounds live in LDS, where
+//     the slot lanes gather them;
+//   * each round's new messages are staged in LDS and summed per row, in CSR
+//     order after the diagonal term, by one lane per row.
+// The arithmetic is that of the compact sweep kernel operation for operation
+// (products and sums separately rounded), so x, the variances and the messages
+// equal those of the multi-launch compact path bit for bit; only the residual
+// norm is summed in another order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "gabp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gabp {
+
+namespace {
+
+constexpr int kSB = kSmallLanes;  // lanes of the one workgroup
+
+__host__ __device__ constexpr size_t small_lds(int n, int K) {
+  // aggregates [3][n] {P, h}; staged P, h and a x terms [S]; residual partials
+  return sizeof(double) * (6 * (size_t)n + 3 * (size_t)kSB * K) + sizeof(double) * (kSB / 64);
+}
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic sum over the 1024 lanes: wave sums, then the 16 wave sums in
+// order by lane 0.  Every lane gets the total.
+__device__ __forceinline__ double small_sum(double v, double* s_red) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < kSB / 64; ++w) tot += s_red[w];
+  return tot;
+}
+
+template <int K>
+__global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
+  extern __shared__ __align__(16) double sm[];
+  const int tid = threadIdx.x;
+  const int n = A.n, E = A.E;
+  double* aggP = sm;              // [3][n]
+  double* aggH = sm + 3 * n;      // [3][n]
+  double* sP = sm + 6 * n;        // [S]
+  double* sH = sP + kSB * K;      // [S]
+  double* sX = sH + kSB * K;      // [S]
+  double* s_red = sX + kSB * K;   // [16]
+
+  if (A.gate && *A.gate) return;  // the inputs failed validation
+
+  // ---- set-up: the lane's slots and row, the prior as round 0 --------------
+  int sc[K], srow[K];
+  double sa[K];
+  // incoming messages of the even and of the odd rounds (named registers: an
+  // array indexed by the round's parity would live in scratch memory)
+  double mP0[K], mH0[K], mP1[K], mH1[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int s = tid + k * kSB;
+    sc[k] = 0;
+    srow[k] = 0;
+    sa[k] = 0.0;
+    mP0[k] = mH0[k] = mP1[k] = mH1[k] = 0.0;
+    if (s < E) {
+      sc[k] = A.col[s];
+      sa[k] = A.a[s];
+    }
+  }
+  const bool own_row = tid < n;
+  int rlo = 0, rhi = 0;
+  double dr = 0.0, br = 0.0;
+  if (own_row) {
+    rlo = A.off_ptr[tid];
+    rhi = A.off_ptr[tid + 1];
+    dr = A.diag[tid];
+    br = A.rhs[tid];
+    aggP[tid] = dr;  // round 0: the prior {A_ii, b_i}
+    aggH[tid] = br;
+    // the row of each slot, through the staging area
+    for (int s = rlo; s < rhi; ++s) ((int*)sX)[s] = tid;
+  }
+  // ||b||_2 (the norm kernel's value when given)
+  double bnorm;
+  if (A.rhs_norm) {
+    bnorm = *A.rhs_norm;
+  } else {
+    bnorm = sqrt(small_sum(own_row ? br * br : 0.0, s_red));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int s = tid + k * kSB;
+    if (s < E) srow[k] = ((const int*)sX)[s];
+  }
+
+  const bool exact = !(A.tol > 0.0);
+  const int M = A.max_iter;
+  const int ce = max(1, A.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+  double last_rel = -1.0, prev_rel = -1.0;
+  int last_round = -1, prev_round = -1, conv = -1, err = 0;
+  int t = 1;
+  // sweeps 1..M update the messages; sweep M+1 only checks round M
+  for (; t <= M + 1; ++t) {
+    const bool upd = t <= M;
+    const bool ck = exact ? (t == M + 1) : in_set(t - 1);
+    if (!upd && !ck) break;
+    const int q1 = (t - 1) % 3, q2 = (t + 1) % 3, qn = t % 3;  // rounds t-1, t-2, t
+    const bool first = t == 1;
+    const bool odd = (t & 1) != 0;
+    bool bad = false;
+    // 1. slot updates: in^(t) = F(A_i^(t-1), out^(t-1)), out^(t-1) = F(A_j^(t-2), in^(t-2))
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int s = tid + k * kSB;
+      if (s < E) {
+        const int c = sc[k], j = srow[k];
+        const double av = sa[k];
+        const double gP = aggP[q1 * n + c], gh = aggH[q1 * n + c];
+        double ax = 0.0;
+        if (ck) ax = av * (gh / gP);
+        if (upd) {
+          double Pout = 0.0, hout = 0.0;
+          if (!first) {  // in^(t-2): the same parity as round t
+            const double o2P = aggP[q2 * n + j], o2h = aggH[q2 * n + j];
+            const double inv_out = 1.0 / (o2P - (odd ? mP1[k] : mP0[k]));
+            Pout = -av * av * inv_out;
+            hout = -av * (o2h - (odd ? mH1[k] : mH0[k])) * inv_out;
+          }
+          const double inv_in = 1.0 / (gP - Pout);
+          const double Pn = -av * av * inv_in;
+          const double hn = -av * (gh - hout) * inv_in;
+          if (odd) {
+            mP1[k] = Pn;
+            mH1[k] = hn;
+          } else {
+            mP0[k] = Pn;
+            mH0[k] = hn;
+          }
+          sP[s] = Pn;
+          sH[s] = hn;
+          bad |= !(isfinite(Pn) && isfinite(hn));
+        }
+        sX[s] = ax;
+      }
+    }
+    if (__syncthreads_or(bad ? 1 : 0)) {  // as the multi-launch path: the error ends the solve
+      err |= kErrNonfinite;
+      ++t;
+      break;
+    }
+    // 2. row sums: round t's aggregates; the residual of round t-1
+    double res2 = 0.0;
+    if (own_row) {
+      if (upd) {
+        const double P = lds_row_sum(dr, sP, rlo, rhi);
+        const double h = lds_row_sum(br, sH, rlo, rhi);
+        aggP[qn * n + tid] = P;
+        aggH[qn * n + tid] = h;
+      }
+      if (ck) {
+        double acc = br - dr * (aggH[q1 * n + tid] / aggP[q1 * n + tid]);
+        acc = lds_row_sub(acc, sX, rlo, rhi);
+        res2 = acc * acc;
+      }
+    }
+    if (ck) {
+      const double rn = sqrt(small_sum(res2, s_red));
+      const double rel = bnorm > 0.0 ? rn / bnorm : rn;
+      prev_rel = last_rel;
+      prev_round = last_round;
+      last_rel = rel;
+      last_round = t - 1;
+      if (rel <= A.tol) conv = t - 1;
+      else if (!(rel <= kDivergeLimit)) err |= kErrDiverged;
+    }
+    if (conv >= 0 || err) {
+      ++t;
+      break;
+    }
+  }
+  __syncthreads();
+
+  // ---- results: the returned round and the state it leaves -----------------
+  const int ret = conv >= 0 ? conv : M;  // round whose means are returned
+  if (own_row) {
+    const int qr = ret % 3;
+    const double P = aggP[qr * n + tid], h = aggH[qr * n + tid];
+    if (A.xout[ret & 1]) A.xout[ret & 1][tid] = h / P;
+    if (A.ptout[ret & 1]) A.ptout[ret & 1][tid] = P;
+    if (A.x_direct) A.x_direct[tid] = h / P;
+    if (A.var_direct) A.var_direct[tid] = 1.0 / P;
+    for (int q = 0; q < 3; ++q)
+      if (A.agg_out[q]) {
+        double2 v;
+        v.x = aggP[q * n + tid];
+        v.y = aggH[q * n + tid];
+        ((double2*)A.agg_out[q])[tid] = v;
+      }
+  }
+  if (A.cin_out) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int s = tid + k * kSB;
+      if (s < E) {
+        double2 v0, v1;
+        v0.x = mP0[k];
+        v0.y = mH0[k];
+        v1.x = mP1[k];
+        v1.y = mH1[k];
+        ((double2*)A.cin_out)[s] = v0;
+        ((double2*)A.cin_out)[(size_t)E + s] = v1;
+      }
+    }
+  }
+  if (tid == 0) {
+    DevStatus st{};
+    st.done = 1;
+    st.conv_round = conv;
+    st.error = err;
+    st.last_rel = last_rel;
+    st.last_round = last_round;
+    st.prev_rel = prev_rel;
+    st.prev_round = prev_round;
+    *A.st = st;
+  }
+}
+
+}  // namespace
+
+size_t small_lds_bytes(int n, int K) { return small_lds(n, K); }
+
+bool small_fits(int64_t n, int64_t E) { return n >= 1 && n <= kSmallLanes && E <= (int64_t)kSmallLanes * 4; }
+
+hipError_t launch_small(const SmallArgs& a, hipStream_t s) {
+  if (!small_fits(a.n, a.E)) return hipErrorInvalidValue;
+  const int K = a.E <= kSB ? 1 : (a.E <= 2 * kSB ? 2 : 4);
+  const uint32_t lds = (uint32_t)small_lds(a.n, K);
+  switch (K) {
+    case 1:
+      (void)hipFuncSetAttribute((const void*)k_small<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_small<1>, dim3(1), dim3(kSB), lds, s, a);
+      break;
+    case 2:
+      (void)hipFuncSetAttribute((const void*)k_small<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_small<2>, dim3(1), dim3(kSB), lds, s, a);
+      break;
+    default:
+      (void)hipFuncSetAttribute((const void*)k_small<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k_small<4>, dim3(1), dim3(kSB), lds, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gabp

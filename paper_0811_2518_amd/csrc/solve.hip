@@ -513,6 +513,41 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
   return finish_run(c, poll);
 }
 
+// The whole plain FP64 iteration in one launch (small.hip), leaving the
+// state of the multi-launch compact path: the means (and P~) of the returned
+// round by parity, the incoming messages of the last two rounds and the
+// aggregates of the last three, and the status the finish kernels would leave.
+gabp_status run_small(Ctx* c, const RunCfg& cfg) {
+  SmallArgs a{};
+  a.n = c->n;
+  a.E = (int32_t)c->E;
+  a.off_ptr = c->off_ptr_d;
+  a.col = c->off_col_d;
+  a.a = c->a64_d;
+  a.diag = (const double*)cfg.diag;
+  a.rhs = (const double*)cfg.rhs;
+  a.rhs_norm = cfg.rhs_norm;
+  a.tol = cfg.tol;
+  a.max_iter = cfg.max_iter;
+  a.check_every = cfg.check_every;
+  a.st = cfg.st;
+  for (int p = 0; p < 2; ++p) {
+    a.xout[p] = (double*)cfg.x2[p];
+    a.ptout[p] = (double*)cfg.pt2[p];
+  }
+  a.cin_out = c->bstate_d;
+  for (int q = 0; q < 3; ++q) a.agg_out[q] = c->agg_d[q];
+  c->run_seen_final = false;
+  GABP_HIP(c, launch_small(a, c->stream));
+  return GABP_OK;
+}
+
+// Plain FP64 solves of small compact-layout handles take the one-launch path.
+bool use_small(const Ctx* c, const RunCfg& cfg) {
+  return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y &&
+         !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS)) && small_fits(c->n, c->E);
+}
+
 template <typename T>
 gabp_status run_sweeps(Ctx* c, const RunCfg& cfg) {
   c->run_seen_final = false;
@@ -677,7 +712,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     cfg.ait_y = c->ait_y_d;
     cfg.ait_hist = c->ait_hist_d;
   }
-  gabp_status rs = run_sweeps<double>(c, cfg);
+  gabp_status rs = use_small(c, cfg) ? run_small(c, cfg) : run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
   const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
   const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
