@@ -34,7 +34,7 @@ __all__ = [
     "rate_bound", "dd_loading", "walk_loading", "convfix_dense",
     "convfix_gabp", "convfix_single_loop", "adjoint_gradient", "fd_gradient", "loss",
     "greedy_colouring", "serial_gabp", "naive_serial_gabp",
-    "aitken_extrapolate", "aitken_gabp", "augmented_csr", "augmented_solution",
+    "aitken_extrapolate", "aitken_gabp", "steffensen_gabp", "augmented_csr", "augmented_solution",
 ]
 
 
@@ -305,6 +305,64 @@ def aitken_gabp(n, row_ptr, col, val, b, tol=1e-10, max_sweeps=2000, check_every
     if tol <= 0:
         _, rel = residual(n, row_ptr, col, val, y, b)
     out = {"y": y, "x": means[-1], "sweeps": t, "converged": converged, "rel_residual": rel}
+    if history:
+        out["history"] = hist
+    return out
+
+
+def steffensen_gabp(n, row_ptr, col, val, b, tol=1e-10, max_sweeps=2000, check_every=1, history=False):
+    """Steffensen's iterations on the GaBP means (Ch. 3 Sec. 3.2).
+
+    The iteration runs in cycles of two synchronous Alg. 2 rounds.  A cycle
+    starts from an estimate s (the round-0 means b_i / A_ii for the first
+    cycle), runs two rounds to get the means x1 and x2, and forms Aitken's
+    y = aitken_extrapolate(s, x1, x2).  Then y replaces the newest means: the
+    next messages are formed from node i's broadcast with its mean set to y_i
+    and its precision P~_i unchanged (reading: GaBP "executed again" from y
+    means the messages leave every node with y as its current mean), and y
+    starts the next cycle.
+
+    Stop rule as in the module docstring, applied to y at the ends of cycles,
+    rounds t (even) with t % check_every == 0 and at the last cycle, which ends
+    at round 2 * floor(max_sweeps / 2).  tol <= 0 runs every cycle and
+    returns the last y.  Needs max_sweeps >= 2.  Returns a dict with ``x``
+    (= y), ``prec``, ``sweeps``, ``converged``, ``rel_residual`` and, on
+    request, the (round, residual) history.
+    """
+    if max_sweeps < 2:
+        raise ValueError("a Steffensen cycle needs two rounds (max_sweeps >= 2)")
+    b = np.asarray(b, dtype=np.float64)
+    g = edge_graph(n, row_ptr, col, val)
+    Pii = g.diag
+    muii = b / g.diag
+    P = np.zeros(g.num_edges)
+    mu = np.zeros(g.num_edges)
+    Pt, mut = _broadcast(g, Pii, muii, P, mu)   # round 0
+    start = mut
+    hist = []
+    t = 0
+    rel = float("nan")
+    converged = False
+    while t + 2 <= max_sweeps:
+        P, mu = _internal_scalars(g, Pt, mut, P, mu)
+        Pt, x1 = _broadcast(g, Pii, muii, P, mu)
+        P, mu = _internal_scalars(g, Pt, x1, P, mu)
+        Pt, x2 = _broadcast(g, Pii, muii, P, mu)
+        t += 2
+        y = aitken_extrapolate(start, x1, x2)
+        mut = y          # the broadcast of round t carries y
+        start = y
+        if tol > 0 and (t % check_every == 0 or t + 2 > max_sweeps):
+            _, rel = residual(n, row_ptr, col, val, y, b)
+            hist.append((t, rel))
+            if rel <= tol:
+                converged = True
+                break
+            if not np.isfinite(rel):
+                break
+    if tol <= 0:
+        _, rel = residual(n, row_ptr, col, val, mut, b)
+    out = {"x": mut, "prec": Pt, "sweeps": t, "converged": converged, "rel_residual": rel}
     if history:
         out["history"] = hist
     return out

@@ -464,6 +464,112 @@ def test_aitken_gabp_on_poisson_converges_sooner_to_the_solution():
 
 
 # ---------------------------------------------------------------------------
+# Steffensen's iterations (Ch. 3 Sec. 3.2): cycles of two rounds, the
+# extrapolated means re-entering the broadcast
+# ---------------------------------------------------------------------------
+
+def _two_by_two(seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0)
+    A = np.array([[rng.uniform(1.5, 3.0), a], [a, rng.uniform(1.5, 3.0)]])
+    return A, rng.normal(size=2)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_steffensen_two_nodes_exact_after_one_cycle(seed):
+    # Closed form: two nodes form a tree of diameter 1, so the means of rounds
+    # 1 and 2 are already x*; Aitken's step on (x0, x*, x*) returns
+    # x0 - (x* - x0)^2 / (x0 - x*) = x*, so the first cycle ends exactly at x*.
+    A, b = _two_by_two(seed)
+    p = _csr(A, b)
+    xstar = np.linalg.solve(A, b)
+    r = oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=2)
+    assert r["sweeps"] == 2
+    np.testing.assert_allclose(r["x"], xstar, rtol=1e-13, atol=1e-15)
+    r = oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-12, max_sweeps=100)
+    assert r["converged"] and r["sweeps"] == 2
+
+
+def _ring(N=7, d=3.0, a=-1.0, beta=1.0):
+    A = np.diag(np.full(N, d))
+    for i in range(N):
+        A[i, (i + 1) % N] = A[(i + 1) % N, i] = a
+    return A, np.full(N, beta)
+
+
+def _ring_by_hand(cycles, d=3.0, a=-1.0, beta=1.0, restart=True):
+    """The cycle means on a uniform ring, where every node and every message is alike:
+    one scalar message (P, mu) and one scalar aggregate (P~, mean), written from Alg. 2
+    (P_ij = -a^2 / (P~_i - P_ji), mu_ij = (P~_i mu~_i - P_ji mu_ji) / a) and the cycle of
+    Ch. 3 Sec. 3.2.  With restart=False the extrapolated mean never re-enters."""
+    Pm, mm = 0.0, 0.0
+    Pt, xb = d, beta / d          # round 0; xb is the mean the nodes broadcast
+    start = xb
+    ys = []
+    for _ in range(cycles):
+        Pm, mm = -a * a / (Pt - Pm), (Pt * xb - Pm * mm) / a
+        Pt = d + 2 * Pm
+        x1 = (beta + 2 * Pm * mm) / Pt
+        Pm, mm = -a * a / (Pt - Pm), (Pt * x1 - Pm * mm) / a
+        Pt = d + 2 * Pm
+        x2 = (beta + 2 * Pm * mm) / Pt
+        y = start - (x1 - start) ** 2 / (x2 - 2 * x1 + start)
+        ys.append(y)
+        if restart:
+            xb, start = y, y
+        else:
+            xb, start = x2, x2
+    return ys
+
+
+def test_steffensen_ring_matches_scalar_recurrence():
+    A, b = _ring()
+    p = _csr(A, b)
+    ys = _ring_by_hand(6)
+    for k in range(1, 7):
+        r = oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=2 * k)
+        assert r["sweeps"] == 2 * k
+        np.testing.assert_allclose(r["x"], ys[k - 1], rtol=1e-13)
+    # odd caps run whole cycles only
+    r = oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=5)
+    assert r["sweeps"] == 4
+    np.testing.assert_allclose(r["x"], ys[1], rtol=1e-13)
+    # the pin tells the restarted cycle from its plausible slips: the un-restarted
+    # form (Aitken every other round) and plain GaBP differ from it by far more
+    # than the tolerance above
+    no_restart = _ring_by_hand(6, restart=False)
+    plain = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=8)["x"]
+    assert abs(no_restart[3] - ys[3]) > 1e-9 * abs(ys[3])
+    assert abs(plain[0] - ys[3]) > 1e-9 * abs(ys[3])
+    with pytest.raises(ValueError):
+        oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0.0, max_sweeps=1)
+
+
+@pytest.mark.parametrize("variant", ["newest_base", "plus_sign"])
+def test_steffensen_planted_mistakes_are_caught(monkeypatch, variant):
+    def bad(x0, x1, x2):
+        d1, den = x1 - x0, x2 - 2 * x1 + x0
+        return (x2 - d1 * d1 / den) if variant == "newest_base" else (x0 + d1 * d1 / den)
+    monkeypatch.setattr(oracle.gabp_oracle, "aitken_extrapolate", bad)
+    with pytest.raises(AssertionError):
+        test_steffensen_two_nodes_exact_after_one_cycle(0)
+    with pytest.raises(AssertionError):
+        test_steffensen_ring_matches_scalar_recurrence()
+
+
+def test_steffensen_limit_is_the_solution():
+    # where the cycles converge, the limit is A^-1 b (a fixed point of the
+    # message update with y = x), and the reported residual is that of y
+    for p in (workloads.config1(), workloads.er_problem(600, 6, 11, ratio=1.2)):
+        r = oracle.steffensen_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=1e-10, max_sweeps=4000)
+        assert r["converged"] and r["sweeps"] % 2 == 0
+        A = p.dense()
+        assert np.linalg.norm(p.b - A @ r["x"]) <= 1e-10 * np.linalg.norm(p.b)
+        xstar = oracle.dense_solve(A, p.b)
+        assert np.linalg.norm(r["x"] - xstar) <= 1e-8 * np.linalg.norm(xstar)
+
+
+# ---------------------------------------------------------------------------
 # general (rectangular) systems: the augmented matrix of Ch. 5 Sec. 5.4
 # ---------------------------------------------------------------------------
 
