@@ -139,6 +139,27 @@ typedef struct {
  * check; the Aitken step and the residual of y are not included). */
 #define GABP_FLAG_AITKEN 16
 
+/* Steffensen's iterations on the means (Ch. 3 Sec. 3.2, convergence
+ * acceleration).  Plain FP64 only, compact layout, not together with
+ * GABP_FLAG_AITKEN (else GABP_E_ARG).  The sweeps run in cycles of two.  A
+ * cycle starts from an estimate s (the round-0 means b_i / A_ii for the
+ * first), runs two sweeps of Alg. 2 to the means x_{t-1} and x_t, and forms
+ *   y = s - (x_{t-1} - s)^2 / (x_t - 2 x_{t-1} + s)
+ * (y = x_t where the second difference is zero or the correction is not
+ * finite).  y then replaces the means of round t: node i's aggregate keeps
+ * its precision P~_i and takes the mean y_i, so the messages of the next
+ * sweep leave every node with y as its current mean, and y starts the next
+ * cycle.  The stop rule is applied to y at the ends of cycles (rounds t with
+ * t % check_every == 0, and the last cycle), through the fused check of the
+ * following sweep; gabp_solve and gabp_backward return y and gabp_info.sweeps
+ * is even.  At most 2 floor(max_iter / 2) sweeps run (max_iter >= 2; tol <= 0
+ * runs all of them).  No precision messages are frozen for reuse.  Opt-in: on
+ * the benchmark workloads and on the paper's own examples it needs more
+ * sweeps than the plain iteration, and it can diverge where the plain
+ * iteration converges (the reading of the re-entry of y is recorded with the
+ * method's measurements in the design notes). */
+#define GABP_FLAG_STEFFENSEN 64
+
 /* Run one launch per sweep even where the whole solve fits one workgroup.
  * Without the flag, a plain FP64 solve (no reuse of frozen precisions, no
  * Aitken step, no sweep timing) on a compact-layout handle with n <= 1024 rows

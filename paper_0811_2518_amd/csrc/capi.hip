@@ -53,6 +53,12 @@ gabp_status check_opts(Ctx* c, const gabp_opts& o) {
     if (o.precision != GABP_FP64 || o.gamma != 0.0 || (o.flags & GABP_FLAG_SINGLE_LOOP))
       return fail(c, GABP_E_ARG, "Aitken's extrapolation applies to the plain FP64 iteration");
   }
+  if (o.flags & GABP_FLAG_STEFFENSEN) {
+    if (o.layout != 0 && o.layout != kLayoutCompact)
+      return fail(c, GABP_E_ARG, "Steffensen's iterations need the compact layout");
+    if (o.precision != GABP_FP64 || o.gamma != 0.0 || (o.flags & (GABP_FLAG_SINGLE_LOOP | GABP_FLAG_AITKEN)))
+      return fail(c, GABP_E_ARG, "Steffensen's iterations apply to the plain FP64 iteration, without Aitken's step");
+  }
   return GABP_OK;
 }
 

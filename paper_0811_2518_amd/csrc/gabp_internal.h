@@ -463,6 +463,12 @@ hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, 
 // round t-2.  Returns at once once the status is done.
 hipError_t launch_aitken(const double* x1, const double* x2, double* hist, double* y, const DevStatus* st,
                          int make_y, int32_t n, hipStream_t s);
+// Steffensen step at the end of a cycle (round t even, Ch. 3 Sec. 3.2): y =
+// aitken(start, x1, x2) with the same formula and fallback as launch_aitken;
+// then start = y, x2 = y and the round-t aggregate record {P~, h~} becomes
+// {P~, P~ y}.  Returns at once once the status is done.
+hipError_t launch_steffensen(const double* x1, double* x2, double* start, void* agg, const DevStatus* st,
+                             int32_t n, hipStream_t s);
 hipError_t launch_grad_vals(const int32_t* row_ptr, const int32_t* col, const double* lam,
                             const double* x, double* gv, int32_t n, hipStream_t s);
 hipError_t launch_scale_diag(const double* d, double f, double* out64, float* out32, int32_t n,

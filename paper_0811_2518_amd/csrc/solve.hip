@@ -36,6 +36,10 @@ struct RunCfg {
   // estimate y_t is formed and its residual checked in its place
   double* ait_y = nullptr;            // [n] nullable: plain checks
   double* ait_hist = nullptr;         // [n]
+  // Steffensen's iterations (compact layout, FP64): cycles of two sweeps;
+  // after each, the extrapolated means replace those of the cycle's last
+  // round and start the next cycle; only cycle ends are checked
+  double* stf_start = nullptr;        // [n] nullable: no restarts
 };
 
 template <typename T>
@@ -311,7 +315,11 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const int ce = std::max(1, cfg.check_every);
   auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
   const bool ait = cfg.ait_y != nullptr;
-  if (ait && sizeof(T) != 8) return fail(c, GABP_E_ARG, "Aitken's extrapolation runs in FP64");
+  const bool stf = cfg.stf_start != nullptr;
+  if ((ait || stf) && sizeof(T) != 8) return fail(c, GABP_E_ARG, "Aitken's and Steffensen's steps run in FP64");
+  if (stf && (M < 2 || (M & 1))) return fail(c, GABP_E_ARG, "internal: Steffensen cycles need an even max_iter >= 2");
+  // Steffensen: only the ends of cycles (even rounds >= 2) are checked
+  auto checked = [&](int j) { return !stf || (j >= 2 && (j & 1) == 0); };
   const int lag = ait ? 0 : 1;  // sweep t checks round t (Aitken) or t-1 (fused)
   OuterArgs ra{};               // residual of the Aitken estimate
   ra.blk_row = c->blk_row_d;
@@ -368,15 +376,15 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       k.agg2 = c->agg_d[(t + 1) % 3];  // round t-2
       k.anew = c->agg_d[t % 3];
       if (mode != kResid) {
-        const bool wx = ait || (exact ? t == M : in_set(t));
+        const bool wx = ait || stf || (exact ? t == M : in_set(t));
         k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
         k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
       }
-      if (t == 1 && (ait || (exact ? M == 0 : in_set(0)))) {
-        k.xout_prev = (T*)cfg.x2[0];
+      if (t == 1 && (ait || stf || (exact ? M == 0 : in_set(0)))) {
+        k.xout_prev = stf ? (T*)cfg.stf_start : (T*)cfg.x2[0];  // Steffensen: round 0 starts cycle 1
         k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
       }
-      const bool ck = !ait && (exact ? (t == M + 1) : in_set(t - 1));
+      const bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1)));
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
       hipEvent_t e0, e1;
@@ -386,6 +394,9 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       if (ck)
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
                                         true, s));
+      if (stf && mode != kResid && t >= 2 && (t & 1) == 0)  // end of a cycle: y replaces x_t
+        GABP_HIP(c, launch_steffensen((const double*)cfg.x2[(t - 1) & 1], (double*)cfg.x2[t & 1], cfg.stf_start,
+                                      c->agg_d[t % 3], cfg.st, c->n, s));
       if (ait) {
         // means of rounds t-2 (history), t-1 and t; y_t on the checked rounds
         const bool wy = t >= 2 && (exact ? t == M : in_set(t));
@@ -544,7 +555,7 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg) {
 
 // Plain FP64 solves of small compact-layout handles take the one-launch path.
 bool use_small(const Ctx* c, const RunCfg& cfg) {
-  return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y &&
+  return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y && !cfg.stf_start &&
          !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS)) && small_fits(c->n, c->E);
 }
 
@@ -680,8 +691,18 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   hipStream_t s = c->stream;
   const bool exact = tol <= 0.0;
   const bool ait = (c->opts.flags & GABP_FLAG_AITKEN) != 0;
+  const bool stf = (c->opts.flags & GABP_FLAG_STEFFENSEN) != 0;
   const bool honly = allow_reuse && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) && c->frozen_valid &&
-                     c->frozen_prec == GABP_FP64 && !exact && !ait;
+                     c->frozen_prec == GABP_FP64 && !exact && !ait && !stf;
+  if (stf) {
+    if (c->layout != kLayoutCompact) return fail(c, GABP_E_ARG, "Steffensen's iterations need the compact layout");
+    if (max_iter < 2) return fail(c, GABP_E_ARG, "Steffensen's iterations need max_iter >= 2");
+    max_iter &= ~1;  // whole cycles of two sweeps
+    if (!c->ait_hist_d) {
+      gabp_status e = dev_alloc(c, (void**)&c->ait_hist_d, sizeof(double) * c->n);
+      if (e != GABP_OK) return e;
+    }
+  }
   if (ait) {
     if (c->layout != kLayoutCompact) return fail(c, GABP_E_ARG, "Aitken's extrapolation needs the compact layout");
     if (max_iter < 2) return fail(c, GABP_E_ARG, "Aitken's extrapolation needs max_iter >= 2");
@@ -712,6 +733,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     cfg.ait_y = c->ait_y_d;
     cfg.ait_hist = c->ait_hist_d;
   }
+  if (stf) cfg.stf_start = c->ait_hist_d;
   gabp_status rs = use_small(c, cfg) ? run_small(c, cfg) : run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
   const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
@@ -734,7 +756,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     report_timing(c, info);
   }
   c->last_msg_round = (exact && !honly && r == GABP_OK) ? max_iter : -1;
-  if (r == GABP_OK && !exact && !honly && !ait && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) &&
+  if (r == GABP_OK && !exact && !honly && !ait && !stf && (c->opts.flags & GABP_FLAG_REUSE_PRECISION) &&
       c->layout != kLayoutSerial) {
     const int last = held_round(c, st.conv_round, max_iter);
     gabp_status fr = freeze<double>(c, last, c->din64_d, b, GABP_FP64);
@@ -922,7 +944,7 @@ namespace {
 // single loop and Aitken's extrapolation (both live in its sweep), else 0.
 int layout_request(const Ctx* c) {
   if (c->opts.layout) return c->opts.layout;
-  return (c->opts.flags & (GABP_FLAG_SINGLE_LOOP | GABP_FLAG_AITKEN)) ? kLayoutCompact : 0;
+  return (c->opts.flags & (GABP_FLAG_SINGLE_LOOP | GABP_FLAG_AITKEN | GABP_FLAG_STEFFENSEN)) ? kLayoutCompact : 0;
 }
 
 std::string tune_key(const Ctx* c) {

@@ -623,6 +623,33 @@ __global__ void k_aitken(const double* __restrict__ x1, const double* __restrict
   }
 }
 
+// Steffensen's restart (Ch. 3 Sec. 3.2): the extrapolated means replace the
+// newest ones, so the next sweep's messages are formed from {P~_i, P~_i y_i}.
+__global__ void k_steffensen(const double* __restrict__ x1, double* x2, double* start, double2* agg,
+                             const DevStatus* st, int32_t n) {
+  if (st->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double a = start[i], b = x1[i], c = x2[i];
+    const double d1 = b - a;
+    const double den = (c - 2.0 * b) + a;
+    const double corr = d1 * d1 / den;
+    const double y = (den != 0.0 && isfinite(corr)) ? a - corr : c;
+    start[i] = y;
+    x2[i] = y;
+    double2 g = agg[i];
+    g.y = g.x * y;
+    agg[i] = g;
+  }
+}
+
+hipError_t launch_steffensen(const double* x1, double* x2, double* start, void* agg, const DevStatus* st,
+                             int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_steffensen, dim3(blocks), dim3(256), 0, s, x1, x2, start, (double2*)agg, st, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_aitken(const double* x1, const double* x2, double* hist, double* y, const DevStatus* st,
                          int make_y, int32_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
