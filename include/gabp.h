@@ -364,18 +364,23 @@ gabp_status gabp_solve_batched(gabp_handle h, const int32_t *nrhs, const int64_t
 
 /* Load balance of the last gabp_solve_batched launch (host struct). */
 typedef struct {
-  int32_t num_items;        /* work items: (system, group of right-hand sides)   */
-  int32_t workgroups;       /* persistent workgroups launched                    */
-  double  makespan_ms;      /* first item start to last item end (device clock)  */
-  double  busy_ms;          /* sum of the item durations                         */
-  double  longest_item_ms;  /* duration of the longest item                      */
-  int64_t precision_sweeps; /* precision-phase sweeps summed over items          */
+  int32_t num_items;        /* right-hand-side items: (system, group of 1, 2, 4  */
+                            /* or 8 right-hand sides)                             */
+  int32_t workgroups;       /* persistent workgroups of the right-hand sides     */
+  double  makespan_ms;      /* first precision item start to last item end       */
+                            /* (device clock)                                     */
+  double  busy_ms;          /* sum of the item durations, both phases            */
+  double  longest_item_ms;  /* duration of the longest right-hand-side item      */
+  int64_t precision_sweeps; /* precision-phase sweeps summed over systems        */
   int64_t inner_sweeps;     /* right-hand-side sweeps summed over items          */
   int32_t longest_sys;      /* system of the longest item                        */
   int32_t longest_nrhs;     /* right-hand sides in that item                     */
   int32_t longest_sweeps;   /* its inner sweeps                                  */
-  int32_t longest_psweeps;  /* its precision-phase sweeps                        */
+  int32_t longest_psweeps;  /* precision-phase sweeps of its system              */
   double  longest_start_ms; /* its start after the first item's start            */
+  int32_t precision_items;  /* systems of the precision phase (one item each)     */
+  int32_t pad;
+  double  precision_ms;     /* duration of the precision phase (device clock)    */
 } gabp_batch_profile;
 
 /* gabp_get_batch_profile -- load-balance figures of the last batched solve. */

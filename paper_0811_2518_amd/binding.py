@@ -64,7 +64,8 @@ class BatchProfile(ctypes.Structure):
     _fields_ = [("num_items", c_i32), ("workgroups", c_i32), ("makespan_ms", c_f64), ("busy_ms", c_f64),
                 ("longest_item_ms", c_f64), ("precision_sweeps", c_i64), ("inner_sweeps", c_i64),
                 ("longest_sys", c_i32), ("longest_nrhs", c_i32), ("longest_sweeps", c_i32),
-                ("longest_psweeps", c_i32), ("longest_start_ms", c_f64)]
+                ("longest_psweeps", c_i32), ("longest_start_ms", c_f64), ("precision_items", c_i32),
+                ("pad", c_i32), ("precision_ms", c_f64)]
 
 
 class GabpError(RuntimeError):

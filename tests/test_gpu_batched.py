@@ -98,10 +98,10 @@ def test_batched_rejects_bad_rhs_layout(small_batch):
 
 
 def test_batched_groups_not_dividing_the_workgroup():
-    # many small systems, so that every system is one work item whose group
-    # is all of its k in {3, 5, 6, 7} right-hand sides: 512 lanes are then not
-    # a multiple of the group, tiles span several chunks and lanes carry
-    # several (slot, rhs) tasks of different right-hand sides
+    # many small systems with k in {3, 5, 6, 7} right-hand sides: each system's
+    # right-hand sides are split into groups of 4, 2 and 1 (a wave's 64 lanes
+    # take 64 / kg rows of kg right-hand sides), so every system has items of
+    # several group sizes that must cover its right-hand sides exactly once
     rng = np.random.default_rng(11)
     probs, ks = [], []
     for q in range(3000):
@@ -113,9 +113,11 @@ def test_batched_groups_not_dividing_the_workgroup():
     s, B, X, infos, st = _solve(bt)
     assert st == binding.OK
     prof = s.profile()
-    # most systems are one item whose group is all of its k right-hand sides
-    # (how many get split depends on the persistent grid's size)
-    assert prof["num_items"] <= 1.15 * bt.num_sys
+    # groups are powers of two: at least the binary decomposition of each k,
+    # at most one item per right-hand side; the precision phase once per system
+    popcount = sum(bin(int(k)).count("1") for k in ks)
+    assert popcount <= prof["num_items"] <= sum(ks)
+    assert prof["precision_items"] == bt.num_sys
     Xh = X.cpu().numpy()
     for q in range(0, bt.num_sys, 7):
         p = bt.system(q)
@@ -213,6 +215,23 @@ def test_batched_serial_groups_not_dividing_the_workgroup():
     s, B, X, infos, st = _solve(bt, layout="serial")
     assert st == binding.OK
     _check_against_dense(bt, X, infos, every=9)
+
+
+@pytest.mark.parametrize("layout", ["auto", "serial"])
+def test_batched_precision_phase_once_per_system(small_batch, layout):
+    # the precision update has no b term (Alg. 2): one precision phase per
+    # system, whatever the number of right-hand sides and items
+    bt = small_batch
+    s, B, X, infos, st = _solve(bt, layout=layout)
+    assert st == binding.OK
+    prof = s.profile()
+    assert prof["precision_items"] == bt.num_sys
+    assert prof["num_items"] >= bt.num_sys
+    assert 3 * bt.num_sys <= prof["precision_sweeps"] <= 10000 * bt.num_sys
+    assert prof["precision_ms"] <= prof["makespan_ms"]
+    # a second solve reruns the phase from zero messages: identical counts
+    X2, infos2, st2 = s.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=20000, X=X)
+    assert s.profile()["precision_sweeps"] == prof["precision_sweeps"]
 
 
 def test_batched_rejects_other_layouts(small_batch):
