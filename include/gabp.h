@@ -313,6 +313,23 @@ gabp_status gabp_create_augmented(int32_t m, int32_t n, const int32_t *row_ptr, 
                                   const gabp_opts *opts, hipStream_t stream, gabp_handle *out);
 
 /*
+ * gabp_plan_augmented -- the symmetric matrix K = [[D, B^T], [B, -gamma I]]
+ * of Ch. 5 Sec. 5.4 that gabp_create_augmented would build, assembled on the
+ * host, without a GPU.  All arrays are HOST arrays.
+ *   m, n, row_ptr, col_idx, vals, d, gamma   as gabp_create_augmented
+ *   K_row_ptr  int32 [n+m+1] (output, nullable)
+ *   K_col      int32 [cap] (output, nullable), K_val float64 [cap] (output,
+ *              nullable): K in full CSR, rows x first, columns increasing
+ *   cap        room in K_col / K_val
+ *   nnz_out    (output, nullable) stored entries of K, n + m + 2 nnz(B)
+ * GABP_E_ARG for a malformed B, d or gamma (the checks of
+ * gabp_create_augmented) or cap < *nnz_out when K_col or K_val is given.
+ */
+gabp_status gabp_plan_augmented(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                const double *vals, const double *d, double gamma, int32_t *K_row_ptr,
+                                int32_t *K_col, double *K_val, int64_t cap, int64_t *nnz_out);
+
+/*
  * gabp_solve_augmented -- solve K {x, z} = {b, h} on a handle made by
  * gabp_create_augmented and return the blocks (Ch. 5 Sec. 5.4).
  *   b          device float64 [n], nullable (zero)

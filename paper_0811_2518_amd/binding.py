@@ -34,7 +34,7 @@ LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
            "gabp_create_augmented", "gabp_solve_augmented", "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
-           "gabp_plan_rows", "gabp_get_props",
+           "gabp_plan_rows", "gabp_plan_augmented", "gabp_get_props",
            "gabp_destroy", "gabp_last_error")
 
 
@@ -114,6 +114,9 @@ def lib():
     L.gabp_plan_rows.argtypes = [c_i32, c_void_p, c_void_p, P(Opts), c_void_p, c_void_p, c_void_p, c_i32, c_void_p,
                                  P(Plan)]
     L.gabp_plan_rows.restype = c_i32
+    L.gabp_plan_augmented.argtypes = [c_i32, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_void_p,
+                                      c_void_p, c_void_p, c_i64, P(c_i64)]
+    L.gabp_plan_augmented.restype = c_i32
     L.gabp_get_props.argtypes = [c_void_p, P(Props)]
     L.gabp_get_props.restype = c_i32
     L.gabp_destroy.argtypes = [c_void_p]
@@ -151,6 +154,31 @@ def plan_rows(row_ptr, col, *, layout="auto", natural_order=False, edges_per_blo
             "class_blk": cls[:pl.num_colours + 1] if pl.num_colours else cls[:0],
             "num_colours": pl.num_colours, "xcd_parts": pl.xcd_parts, "num_blocks": pl.num_blocks,
             "num_chunks": pl.num_chunks}
+
+
+def plan_augmented(m, n, row_ptr, col, val, d, gamma):
+    """The augmented matrix gabp_create_augmented would build, assembled on the host (no GPU):
+    (row_ptr, col, val) NumPy arrays of K = [[D, B^T], [B, -gamma I]]."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+    cl = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    vl = np.ascontiguousarray(np.asarray(val, dtype=np.float64))
+    dd = np.ascontiguousarray(np.asarray(d, dtype=np.float64))
+    nnz = c_i64(0)
+    st = lib().gabp_plan_augmented(int(m), int(n), rp.ctypes.data_as(c_void_p), cl.ctypes.data_as(c_void_p),
+                                   vl.ctypes.data_as(c_void_p), dd.ctypes.data_as(c_void_p), float(gamma), None,
+                                   None, None, 0, ctypes.byref(nnz))
+    if st != OK:
+        raise _err(None, st, "gabp_plan_augmented")
+    Krp = np.zeros(int(m) + int(n) + 1, np.int32)
+    Kcl = np.zeros(max(nnz.value, 1), np.int32)
+    Kvl = np.zeros(max(nnz.value, 1), np.float64)
+    st = lib().gabp_plan_augmented(int(m), int(n), rp.ctypes.data_as(c_void_p), cl.ctypes.data_as(c_void_p),
+                                   vl.ctypes.data_as(c_void_p), dd.ctypes.data_as(c_void_p), float(gamma),
+                                   Krp.ctypes.data_as(c_void_p), Kcl.ctypes.data_as(c_void_p),
+                                   Kvl.ctypes.data_as(c_void_p), int(nnz.value), ctypes.byref(nnz))
+    if st != OK:
+        raise _err(None, st, "gabp_plan_augmented")
+    return Krp, Kcl[:nnz.value], Kvl[:nnz.value]
 
 
 def default_opts(**kw) -> Opts:

@@ -377,6 +377,35 @@ gabp_status gabp_backward(gabp_handle h, const double* x, const double* grad_x, 
   return r;
 }
 
+gabp_status gabp_plan_augmented(int32_t m, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                const double* vals, const double* d, double gamma, int32_t* K_row_ptr,
+                                int32_t* K_col, double* K_val, int64_t cap, int64_t* nnz_out) {
+  if (nnz_out) *nnz_out = 0;
+  if (m < 1 || n < 1 || (int64_t)n + m >= INT32_MAX) return fail(nullptr, GABP_E_ARG, "m >= 1 and n >= 1");
+  if (!row_ptr || !col_idx || !vals || !d) return fail(nullptr, GABP_E_ARG, "NULL B or d");
+  std::vector<int32_t> bp(row_ptr, row_ptr + m + 1);
+  const int64_t nnzB = bp[m];
+  if (bp[0] != 0 || nnzB < 0 || (int64_t)n + m + 2 * nnzB >= INT32_MAX)
+    return fail(nullptr, GABP_E_ARG, "row_ptr[0] must be 0 and the augmented matrix must fit int32 indices");
+  for (int32_t r = 0; r < m; ++r)
+    if (bp[r + 1] < bp[r]) return fail(nullptr, GABP_E_ARG, "row_ptr decreases");
+  std::vector<int32_t> bc(col_idx, col_idx + nnzB);
+  std::vector<double> bv(vals, vals + nnzB);
+  std::vector<double> dh(d, d + n);
+  const std::string bad = check_rect(m, n, bp, bc, bv, dh, gamma);
+  if (!bad.empty()) return fail(nullptr, GABP_E_ARG, bad);
+  const HostCsr K = assemble_augmented(m, n, bp, bc, bv, dh, gamma);
+  const int64_t nnzK = (int64_t)K.col.size();
+  if (nnz_out) *nnz_out = nnzK;
+  if (K_row_ptr) std::copy(K.row_ptr.begin(), K.row_ptr.end(), K_row_ptr);
+  if (K_col || K_val) {
+    if (cap < nnzK) return fail(nullptr, GABP_E_ARG, "cap below the number of stored entries of K");
+    if (K_col) std::copy(K.col.begin(), K.col.end(), K_col);
+    if (K_val) std::copy(K.val.begin(), K.val.end(), K_val);
+  }
+  return GABP_OK;
+}
+
 gabp_status gabp_create_augmented(int32_t m, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                                   const double* vals, const double* d, double gamma, const gabp_opts* opts,
                                   hipStream_t stream, gabp_handle* out) {

@@ -168,3 +168,27 @@ def test_long_rows_are_swept_in_chunks(epb, layout):
     # no long rows, no chunks
     q = workloads.er_problem(5000, 8, 95)
     assert binding.plan_rows(q.row_ptr, q.col, edges_per_block=epb)["num_chunks"] == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_augmented_assembly_is_the_block_matrix(seed):
+    # the host assembly of gabp_create_augmented (Ch. 5 Sec. 5.4) equals the
+    # oracle's block matrix entry for entry
+    q = workloads.ridge_problem(40 + 13 * seed, 25 + 7 * seed, 1 + seed, 0.3 + seed, seed)
+    rp, cl, vl = binding.plan_augmented(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma)
+    N, orp, ocl, ovl = oracle.augmented_csr(q.m, q.n, q.row_ptr, q.col, q.val, q.d, q.gamma)
+    assert len(rp) == N + 1
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(cl, ocl)
+    np.testing.assert_array_equal(vl, ovl)
+
+
+def test_augmented_assembly_rejects_malformed_input():
+    q = workloads.ridge_problem(30, 20, 2, 0.5, 4)
+    bad = q.col.copy()
+    bad[0] = q.n
+    with pytest.raises(binding.GabpError) as e:
+        binding.plan_augmented(q.m, q.n, q.row_ptr, bad, q.val, q.d, q.gamma)
+    assert e.value.status == binding.E_ARG
+    with pytest.raises(binding.GabpError):
+        binding.plan_augmented(q.m, q.n, q.row_ptr, q.col, q.val, q.d, 0.0)
