@@ -40,4 +40,4 @@ def test_struct_layouts():
     assert ctypes.sizeof(binding.Opts) == 8 * 4 + 4 * 8
     assert ctypes.sizeof(binding.Info) == 4 * 4 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(binding.Props) == 8 + 8 + 6 * 4 + 8 + 3 * 8
-    assert ctypes.sizeof(binding.BatchProfile) == 2 * 4 + 3 * 8 + 2 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(binding.BatchProfile) == 2 * 4 + 3 * 8 + 2 * 8 + 4 * 4 + 8 + 2 * 4 + 8
