@@ -449,6 +449,34 @@ gabp_status gabp_plan_rows(int32_t n, const int32_t *row_ptr, const int32_t *col
                            const gabp_opts *opts, int32_t *perm, int32_t *colour,
                            int32_t *blk_row, int32_t blk_cap, int32_t *class_blk, gabp_plan *plan);
 
+/*
+ * gabp_solve_noalloc -- for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the plain FP64 solve of gabp_create + gabp_solve (synchronous
+ * Alg. 2, check every sweep) in one call that allocates nothing.
+ *   n          unknowns, 0 <= n <= 1024 (larger: GABP_E_ARG)
+ *   row_ptr, col_idx, vals   device full symmetric CSR as for gabp_create,
+ *              at most 4096 off-diagonal entries (nnz - n; larger:
+ *              GABP_E_ARG, detected on the device)
+ *   b          device float64 [n]
+ *   x          device float64 [n] (output)
+ *   var        device float64 [n] (output, nullable): 1 / P~_i as gabp_solve
+ *   tol, max_iter   as gabp_solve (tol <= 0: exactly max_iter sweeps)
+ *   stream     the stream of the work; the current device must be its device
+ *   info       host, nullable
+ * Validation errors are those of gabp_create; solve statuses those of
+ * gabp_solve.  The results equal those of gabp_create + gabp_solve bit for
+ * bit.  Instead of allocating, the call uses a static device buffer of the
+ * library (61.7 KB per device, held until the process ends) for the
+ * validation flags, the split off-diagonal CSR and the status: calls that
+ * overlap on one device share that buffer and race, so serialise them.  Blocks
+ * until the stream has finished the solve.  gabp_last_error(NULL) describes a
+ * failure.
+ */
+gabp_status gabp_solve_noalloc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                               const double *b, double *x, double *var, double tol, int32_t max_iter,
+                               hipStream_t stream, gabp_info *info);
+
 /* gabp_props -- static properties of a handle (host output). */
 gabp_status gabp_get_props(gabp_handle h, gabp_props *props);
 

@@ -34,7 +34,7 @@ LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 # every entry point declared in include/gabp.h
 EXPORTS = ("gabp_default_opts", "gabp_create", "gabp_solve", "gabp_messages", "gabp_backward",
            "gabp_create_augmented", "gabp_solve_augmented", "gabp_create_batched", "gabp_solve_batched", "gabp_get_batch_profile", "gabp_get_colours",
-           "gabp_plan_rows", "gabp_plan_augmented", "gabp_get_props",
+           "gabp_plan_rows", "gabp_plan_augmented", "gabp_get_props", "gabp_solve_noalloc",
            "gabp_destroy", "gabp_last_error")
 
 
@@ -119,6 +119,9 @@ def lib():
     L.gabp_plan_augmented.restype = c_i32
     L.gabp_get_props.argtypes = [c_void_p, P(Props)]
     L.gabp_get_props.restype = c_i32
+    L.gabp_solve_noalloc.argtypes = [c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_f64, c_i32,
+                                     c_void_p, P(Info)]
+    L.gabp_solve_noalloc.restype = c_i32
     L.gabp_destroy.argtypes = [c_void_p]
     L.gabp_destroy.restype = None
     L.gabp_last_error.argtypes = [c_void_p]
@@ -383,6 +386,30 @@ class AugmentedSolver(Solver):
         d = info.as_dict()
         d["status"] = st
         return (x, d, zz) if z else (x, d)
+
+
+def solve_noalloc(row_ptr, col, val, b, tol=1e-10, max_iter=2000, *, x=None, var=False, device="cuda",
+                  stream=None, check=True):
+    """gabp_solve_noalloc: one plain FP64 solve of a small system (n <= 1024, at most 4096
+    off-diagonal entries) that allocates nothing on the device.  Returns (x, info[, var])."""
+    torch = _torch()
+    dv = torch.device(device)
+    _, sh = _stream_handle(stream)
+    rp = _dev(row_ptr, torch.int32, dv)
+    cl = _dev(col, torch.int32, dv)
+    vl = _dev(val, torch.float64, dv)
+    bb = _dev(b, torch.float64, dv)
+    n = int(rp.numel()) - 1
+    x = torch.empty(n, dtype=torch.float64, device=dv) if x is None else x
+    v = torch.empty(n, dtype=torch.float64, device=dv) if var else None
+    info = Info()
+    st = lib().gabp_solve_noalloc(n, _ptr(rp), _ptr(cl), _ptr(vl), _ptr(bb), _ptr(x), _ptr(v), float(tol),
+                                  int(max_iter), sh, ctypes.byref(info))
+    if check and st < 0:
+        raise _err(None, st, "gabp_solve_noalloc")
+    d = info.as_dict()
+    d["status"] = st
+    return (x, d, v) if var else (x, d)
 
 
 def last_create_error() -> str:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgabp.so")
-SOURCES = ["ingest.hip", "colour.hip", "partition.hip", "sweep.hip", "bcast.hip", "compact.hip", "serial.hip", "small.hip", "loading.hip", "solve.hip",
+SOURCES = ["ingest.hip", "colour.hip", "partition.hip", "sweep.hip", "bcast.hip", "compact.hip", "serial.hip", "small.hip", "noalloc.hip", "loading.hip", "solve.hip",
            "batched.hip", "capi.hip"]
 ARCH = os.environ.get("GABP_OFFLOAD_ARCH", "gfx950")
 

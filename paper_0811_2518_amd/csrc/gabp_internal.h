@@ -246,9 +246,12 @@ struct SmallArgs {
   void* cin_out;            // nullable: [2][E] {P, h} incoming messages by round parity
   void* agg_out[3];         // nullable: [n] {P~, h~} aggregates by round mod 3
   const int32_t* gate;      // nullable: nonzero -> the kernel returns at once
+  const int32_t* E_dev;     // nullable: E read on the device (then E is ignored)
 };
 bool small_fits(int64_t n, int64_t E);
 hipError_t launch_small(const SmallArgs& a, hipStream_t s);
+// the same with K = 4 slots per lane (E <= 4096, also when E lives on the device)
+hipError_t launch_small_k4(const SmallArgs& a, hipStream_t s);
 
 constexpr int kLayoutEdge = 1;     // outgoing message records + reverse-slot index
 constexpr int kLayoutNode = 2;     // node broadcast: aggregates published, edge pairs kept in place

@@ -59,15 +59,15 @@ template <int K>
 __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
   extern __shared__ __align__(16) double sm[];
   const int tid = threadIdx.x;
-  const int n = A.n, E = A.E;
+  if (A.gate && *A.gate) return;  // the inputs failed validation
+  const int n = A.n, E = A.E_dev ? *A.E_dev : A.E;
+  if (E < 0 || E > kSB * K || n < 1 || n > kSB) return;  // never run past the lanes' slots
   double* aggP = sm;              // [3][n]
   double* aggH = sm + 3 * n;      // [3][n]
   double* sP = sm + 6 * n;        // [S]
   double* sH = sP + kSB * K;      // [S]
   double* sX = sH + kSB * K;      // [S]
   double* s_red = sX + kSB * K;   // [16]
-
-  if (A.gate && *A.gate) return;  // the inputs failed validation
 
   // ---- set-up: the lane's slots and row, the prior as round 0 --------------
   int sc[K], srow[K];
@@ -272,6 +272,14 @@ hipError_t launch_small(const SmallArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_small<4>, dim3(1), dim3(kSB), lds, s, a);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_small_k4(const SmallArgs& a, hipStream_t s) {
+  if (a.n < 1 || a.n > kSB) return hipErrorInvalidValue;
+  const uint32_t lds = (uint32_t)small_lds(a.n, 4);
+  (void)hipFuncSetAttribute((const void*)k_small<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_small<4>, dim3(1), dim3(kSB), lds, s, a);
   return hipGetLastError();
 }
 
