@@ -267,6 +267,31 @@ def test_rate_bound_holds_on_grid():
     assert np.max(np.abs(r["x"] - x)) < target and t <= bound
 
 
+def test_rate_bound_gamma_by_hand():
+    # Ch. 3 Sec. 3.1 with eps_i = |a_ii| - sum_j |a_ij| (reading C10): on the
+    # path A = [[4, 1, 0], [1, 5, 2], [0, 2, 6]],
+    #   node 0: eps = 3, j = 1: 1 / (1 + 3 / (1 * 1)) = 1/4
+    #   node 1: eps = 2, j = 0: 1 / (1 + 2 / (1 * 2)) = 1/2;  j = 2: 1 / (1 + 2 / (2 * 2)) = 2/3
+    #   node 2: eps = 4, j = 1: 1 / (1 + 4 / (2 * 1)) = 1/3
+    # so gamma = 2/3 and the rounds to eps = 1e-6 are ceil(log 1e-6 / log(2/3)) = 35.
+    # The paper's other form, 1 / (1 + |a_ij| eps_i / |N(i)|), would give 1/2.
+    A = np.array([[4.0, 1.0, 0.0], [1.0, 5.0, 2.0], [0.0, 2.0, 6.0]])
+    t, gamma = oracle.rate_bound(A, 1e-6)
+    assert gamma == pytest.approx(2.0 / 3.0, rel=1e-15)
+    assert t == 35
+
+
+def test_dd_loading_by_hand():
+    # reading C11: Gamma_ii = max(0, (1 + delta) sum_{j != i} |A_ij| - A_ii); on
+    # [[1, 2, 0], [2, 5, 1], [0, 1, 3]] with delta = 0.05: row 0 needs
+    # 1.05 * 2 - 1 = 1.1, rows 1 and 2 are already dominant
+    A = np.array([[1.0, 2.0, 0.0], [2.0, 5.0, 1.0], [0.0, 1.0, 3.0]])
+    np.testing.assert_allclose(oracle.dd_loading(A, 0.05), [1.1, 0.0, 0.0], rtol=1e-15, atol=0)
+    # and no more loading than that: one percent less leaves row 0 not dominant
+    G = oracle.dd_loading(A, 0.05)
+    assert not oracle.is_strictly_dd(A + np.diag(G * np.array([0.9, 1.0, 1.0])))
+
+
 # ---------------------------------------------------------------------------
 # Ch. 5: diagonal loading and the double loop
 # ---------------------------------------------------------------------------
