@@ -51,7 +51,7 @@ constexpr int kWave = 64;
 constexpr int kWaves = kBT / kWave;
 constexpr int kSlice = 64;              // rows per slice
 constexpr int kSortWindow = 512;        // rows sorted by degree together
-constexpr int kQSlots = 8;              // slots of a row loaded together (FP32 passes)
+constexpr int kQSlots = 4;              // slots of a row loaded together (FP32 passes)
 constexpr int kMaxGroup = 8;            // right-hand sides per work item (1, 2, 4 or 8)
 constexpr float kPrecTol = 4e-7f;       // precision phase: relative change of P~ to stop at
 constexpr float kPrecStall = 2e-5f;     // ... or below this, once it stops halving (FP32 rounding floor)
@@ -642,8 +642,14 @@ __device__ __forceinline__ BItem uniform_item(const BItem& x) {
 }
 
 // Persistent kernels: every workgroup takes items until its queue is empty.
+// At most 64 VGPRs, so that four 512-lane workgroups reside per CU: measured
+// on the 4096-system batch, 97 VGPRs (two workgroups per CU) took 1.27 s
+// (colour-serial 0.82 s), 80 (three) 1.04 s (0.73 s) and 64 (four) 1.05 s
+// (0.69 s); 256-lane workgroups with five per CU took 1.34 s (0.83 s).  With
+// four per CU the chip runs near its memory bandwidth, so the few spilled
+// registers cost nothing measurable.
 template <bool SER>
-__global__ __launch_bounds__(kBT) void k_bprec(BatchArgs A) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(8))) void k_bprec(BatchArgs A) {
   __shared__ Shared sh;
   for (;;) {
     if (threadIdx.x == 0) sh.item = (int)atomicAdd(&A.queue[0], 1u);
@@ -656,7 +662,7 @@ __global__ __launch_bounds__(kBT) void k_bprec(BatchArgs A) {
 }
 
 template <bool SER>
-__global__ __launch_bounds__(kBT) void k_brhs(BatchArgs A) {
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(8))) void k_brhs(BatchArgs A) {
   __shared__ Shared sh;
   for (;;) {
     if (threadIdx.x == 0) sh.item = (int)atomicAdd(&A.queue[1], 1u);
@@ -715,37 +721,75 @@ __global__ void k_build_sell(int32_t nslices, const Slice* __restrict__ slices, 
   }
 }
 
-// Smallest diagonal-dominance ratio |A_ii| / sum_j |A_ij| over the rows of
-// each system (+inf for a system without off-diagonal entries).
-__global__ __launch_bounds__(256) void k_sys_ratio(int num_sys, const int32_t* __restrict__ sys_row_off,
-                                                   const int32_t* __restrict__ off_ptr,
-                                                   const double* __restrict__ a, const double* __restrict__ d,
-                                                   float* __restrict__ out) {
-  __shared__ float s_min[256];
+// Spectral radius of R = D^-1/2 (D - A) D^-1/2 (the signed off-diagonal part,
+// D = diag A) of every system, for the work estimate: kRhoIters steps of the
+// power iteration from a scrambled start, one workgroup per system, the
+// estimate being the growth of the 2-norm in the last step (a lower bound
+// that approaches rho).  Attractive systems (all A_ij < 0, the grids) have
+// rho(R) = rho(|R|) = 1 / (dominance ratio); mixed signs give much less, and
+// GaBP's sweep count follows rho(R), not the dominance ratio.
+constexpr int kRhoIters = 30;
+
+__global__ __launch_bounds__(256) void k_sys_rho(int num_sys, const int32_t* __restrict__ sys_row_off,
+                                                 const int32_t* __restrict__ off_ptr,
+                                                 const int32_t* __restrict__ off_col,
+                                                 const double* __restrict__ a, const double* __restrict__ d,
+                                                 double* xa, double* xb, float* __restrict__ out) {
+  __shared__ double s_red[4];
   for (int s = blockIdx.x; s < num_sys; s += gridDim.x) {
-    float m = INFINITY;
-    for (int r = sys_row_off[s] + (int)threadIdx.x; r < sys_row_off[s + 1]; r += 256) {
-      double sum = 0.0;
-      for (int q = off_ptr[r]; q < off_ptr[r + 1]; ++q) sum += fabs(a[q]);
-      if (sum > 0.0) m = fminf(m, (float)(fabs(d[r]) / sum));
+    const int r0 = sys_row_off[s], r1 = sys_row_off[s + 1];
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += 256) {
+      const uint32_t h = (uint32_t)r * 2654435761u;
+      xa[r] = (double)(h >> 8) * (1.0 / 16777216.0) - 0.5;
     }
-    s_min[threadIdx.x] = m;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) s_min[threadIdx.x] = fminf(s_min[threadIdx.x], s_min[threadIdx.x + off]);
+    double* x = xa;
+    double* y = xb;
+    double grow = 0.0;
+    for (int it = 0; it < kRhoIters; ++it) {
+      double nx = 0.0, ny = 0.0;
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += 256) {
+        const double sr = 1.0 / sqrt(fabs(d[r]));
+        double acc = 0.0;
+        for (int q = off_ptr[r]; q < off_ptr[r + 1]; ++q) {
+          const int c = off_col[q];
+          acc -= a[q] * x[c] / sqrt(fabs(d[c]));
+        }
+        acc *= sr;
+        y[r] = acc;
+        nx += x[r] * x[r];
+        ny += acc * acc;
+      }
+      // block sums of ||x||^2 and ||y||^2
+      double v[2] = {nx, ny};
+      for (int k = 0; k < 2; ++k) {
+        double w = v[k];
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = w;
+        __syncthreads();
+        v[k] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+      }
+      grow = v[0] > 0.0 ? sqrt(v[1] / v[0]) : 0.0;
+      const double sc = v[1] > 0.0 ? 1.0 / sqrt(v[1]) : 0.0;
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += 256) y[r] *= sc;
       __syncthreads();
+      double* t = x;
+      x = y;
+      y = t;
     }
-    if (threadIdx.x == 0) out[s] = s_min[0];
+    if (threadIdx.x == 0) out[s] = (float)grow;
     __syncthreads();
   }
 }
 
-// Relative sweep count of a system for the work estimate: Jacobi-like
-// contraction by about 1 / rho per sweep for dominance ratio rho, so the
-// sweeps to a fixed reduction scale as 1 / ln(rho) (bounded both ways).
-double sweep_weight(float ratio) {
-  if (!(ratio > 1.0f)) return 100.0;
-  return std::min(100.0, std::max(0.1, 1.0 / std::log((double)ratio)));
+// Relative sweep count of a system for the work estimate: GaBP's error
+// contracts by about rho(R) per sweep, so the sweeps to a fixed reduction
+// scale as -1 / ln(rho(R)) (bounded both ways).
+double sweep_weight(float rho) {
+  if (!(rho < 1.0f)) return 100.0;
+  if (!(rho > 0.0f)) return 0.1;
+  return std::min(100.0, std::max(0.1, -1.0 / std::log((double)rho)));
 }
 
 struct BatchState {
@@ -1000,27 +1044,33 @@ gabp_status batched_create(Ctx* c, int32_t num_sys, const int32_t* sys_row_off) 
   // the graph is captured and replayed on a stream of the handle's own, ordered
   // after the caller's stream by synchronisation (capture needs a non-null stream)
   GABP_HIP(c, hipStreamCreateWithFlags(&bs->gs, hipStreamNonBlocking));
-  // per-system dominance ratios for the work estimate
+  // per-system spectral radius of R for the work estimate
   bs->sys_weight.assign(num_sys, 1.0);
   if (c->E > 0) {
     int32_t* so_d = nullptr;
-    float* ratio_d = nullptr;
-    std::vector<float> ratio(num_sys);
+    float* rho_d = nullptr;
+    double *xa = nullptr, *xb = nullptr;
+    std::vector<float> rho(num_sys);
     hipError_t e = hipMalloc((void**)&so_d, sizeof(int32_t) * (num_sys + 1));
-    if (e == hipSuccess) e = hipMalloc((void**)&ratio_d, sizeof(float) * num_sys);
+    if (e == hipSuccess) e = hipMalloc((void**)&rho_d, sizeof(float) * num_sys);
+    if (e == hipSuccess) e = hipMalloc((void**)&xa, sizeof(double) * std::max(1, N));
+    if (e == hipSuccess) e = hipMalloc((void**)&xb, sizeof(double) * std::max(1, N));
     if (e == hipSuccess)
       e = hipMemcpyAsync(so_d, sys_row_off, sizeof(int32_t) * (num_sys + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_sys_ratio, dim3(std::min(num_sys, 4096)), dim3(256), 0, st, num_sys, so_d, c->off_ptr_d,
-                         c->a64_d, c->d64_d, ratio_d);
+      hipLaunchKernelGGL(k_sys_rho, dim3(std::min(num_sys, 8192)), dim3(256), 0, st, num_sys, so_d, c->off_ptr_d,
+                         c->off_col_d, c->a64_d, c->d64_d, xa, xb, rho_d);
       e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(ratio.data(), ratio_d, sizeof(float) * num_sys, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(rho.data(), rho_d, sizeof(float) * num_sys, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) (void)hipGetLastError();
     free_raw(so_d);
-    free_raw(ratio_d);
+    free_raw(rho_d);
+    free_raw(xa);
+    free_raw(xb);
     if (e != hipSuccess) return hip_fail(c, e, "batched work estimate");
-    for (int s = 0; s < num_sys; ++s) bs->sys_weight[s] = sweep_weight(ratio[s]);
+    for (int s = 0; s < num_sys; ++s) bs->sys_weight[s] = sweep_weight(rho[s]);
   }
   // the precision phase's order: largest systems first
   {
