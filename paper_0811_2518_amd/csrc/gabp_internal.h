@@ -454,6 +454,7 @@ struct OuterArgs {
   double tol;
   int32_t nblk;
   int32_t n;
+  const DevStatus* gate;  // nullable: the launch returns at once once gate->done is set
 };
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s);

@@ -332,6 +332,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   ra.partials = c->partials_d;
   ra.nblk = c->nblk;
   ra.n = c->n;
+  ra.gate = cfg.st;  // no residual of y once the solve has ended
 
   CnodeArgs<T> a{};
   a.blk_row = c->blk_row_d;

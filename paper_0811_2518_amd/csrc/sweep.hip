@@ -431,6 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
   __shared__ double s_ax[S];
   __shared__ int32_t s_ptr[kMaxRowsPerBlock + 4];
   __shared__ double s_red[kBlock / 64];
+  if (A.gate && A.gate->done) return;  // a residual queued past the end of a solve
   const int tid = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, A.nblk);
   const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
