@@ -467,6 +467,25 @@ def test_full_er_first_rounds_match_oracle(er_full, layout):
         assert rel(x, ref["x"]) <= 1e-12
 
 
+def test_full_er_bench_handle_matches_oracle(er_full):
+    # the benchmark's handle (autotuned layout and block size, no precision
+    # reuse) on the benchmark workload: sweeps 1-5 and the converged solve
+    # against the FP64 oracle at the 1e-10 bar, the stop sweep bit-exact
+    p = er_full
+    s = solver(p, reuse_precision=False)
+    print(f"bench handle: {s.props()}", flush=True)
+    for T in (1, 2, 3, 4, 5):
+        ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=0, max_sweeps=T)
+        x, info = s.solve(dev(p.b), tol=0, max_iter=T)
+        assert rel(x, ref["x"]) <= 1e-10, (T, rel(x, ref["x"]))
+    ref = oracle.broadcast_gabp(p.n, p.row_ptr, p.col, p.val, p.b, tol=TOL, max_sweeps=2000)
+    x, info = s.solve(dev(p.b), tol=TOL, max_iter=2000)
+    assert info["converged"] == 1 and info["sweeps"] == ref["sweeps"]
+    assert rel(x, ref["x"]) <= 1e-10, rel(x, ref["x"])
+    _, rr = oracle.residual(p.n, p.row_ptr, p.col, p.val, x.cpu().numpy(), p.b)
+    assert info["rel_residual"] == pytest.approx(rr, rel=1e-6)
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_full_er_converges_with_independent_residual(er_full, layout):
     p = er_full
