@@ -213,7 +213,11 @@ def traffic_from(fetch_dir, write_dir, n, out_path=None):
 
 
 def run_solves(torch, g, p, b, precision, steps, warmup, layout="auto"):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     s = g.Solver(p.row_ptr, p.col, p.val, precision=precision, reuse_precision=False, layout=layout)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         s.solve(b, tol=TOL, max_iter=2000, x=x)
@@ -232,7 +236,7 @@ def run_solves(torch, g, p, b, precision, steps, warmup, layout="auto"):
     props = s.props()
     xs = x.detach().cpu().numpy()
     s.close()
-    return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs}
+    return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs, "create_s": create_s}
 
 
 def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto", edges_per_block=0):
@@ -520,15 +524,16 @@ def suite_convfix(torch, g, workloads, inner_tol=1e-2):
         "status": info["status"], "rel_residual_K": info["rel_residual"], "rel_residual": res,
         "edge_updates_per_s": pa["num_offdiag"] * info["sweeps"] / dt}
     sa.close()
-    runs = {"double_loop_fp32_inner": out["time_to_tol_ms"]}
-    if out["augmented_double_loop_fp32_inner"]["status"] == 0:
-        runs["augmented_double_loop_fp32_inner"] = out["augmented_double_loop_fp32_inner"]["time_to_tol_ms"]
-    if out["double_loop_fp32_serial_inner"]["status"] == 0:
-        runs["double_loop_fp32_serial_inner"] = out["double_loop_fp32_serial_inner"]["time_to_tol_ms"]
-    runs.update({k: v["time_to_tol_ms"] for k, v in out.items() if k.startswith("single_loop") and v["status"] == 0})
-    best = min(runs, key=runs.get)
-    out["best"] = {"method": best, "time_to_tol_ms": runs[best],
-                   "speedup_vs_double_loop": out["time_to_tol_ms"] / runs[best]}
+    # every method on one criterion: the relative residual of A x = b itself, recomputed
+    # here in FP64, at or below 1e-9 (the augmented solve stops on the residual of K,
+    # whose scaling differs)
+    cand = {"double_loop_fp32_inner": out}
+    cand.update({k: v for k, v in out.items() if isinstance(v, dict) and "time_to_tol_ms" in v})
+    runs = {k: v["time_to_tol_ms"] for k, v in cand.items() if v["status"] == 0 and v["rel_residual"] <= 1e-9}
+    if runs:
+        best = min(runs, key=runs.get)
+        out["best"] = {"method": best, "time_to_tol_ms": runs[best], "criterion": "rel. residual of A <= 1e-9",
+                       "speedup_vs_double_loop": out["time_to_tol_ms"] / runs[best]}
     return out
 
 
@@ -571,6 +576,12 @@ def suite_batched(torch, g, workloads, sample=48):
             for j in range(r.shape[0]):
                 h.solve(r[j], tol=TOL, max_iter=100000)
     loop_s, _ = timed(torch, loop)
+    for h in handles:
+        h.close()
+    # the same loop with plain FP64 GaBP handles (frozen precisions reused after
+    # the first right-hand side of each system)
+    handles = [g.Solver(q.row_ptr, q.col, q.val, precision="fp64", reuse_precision=True) for q in systems]
+    loop64_s, _ = timed(torch, loop)
     for h in handles:
         h.close()
     # the same sample through one batched launch
@@ -618,8 +629,64 @@ def suite_batched(torch, g, workloads, sample=48):
             "load_balance": prof, "serial": serial,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,
-                                "speedup": loop_s / sub_s},
+                                "speedup": loop_s / sub_s,
+                                "loop_fp64_plain_ms": 1e3 * loop64_s,
+                                "speedup_vs_fp64_plain_loop": loop64_s / sub_s},
             "cpu_oracle_pool": cpu_pool}
+
+
+# The paper's own figures (context only: iteration counts at its message-change
+# threshold 1e-6 with no hardware or precision stated, and the kernel-ridge
+# training times of Ch. 8 on CPU clusters).
+PAPER_ROUNDS = {
+    "nonpsd_3x3 (Ch. 4 Sec. 4.2, b = 1)": {"parallel": 38, "serial": 25, "parallel_steffensen": 21,
+                                           "serial_steffensen": 14},
+    "poisson_p10 (Ch. 4 Sec. 4.3, f = -1)": {"parallel": 134, "serial": 73, "parallel_aitken": 25,
+                                              "parallel_steffensen": 56, "serial_steffensen": 32, "jacobi": 354,
+                                              "gauss_seidel": 136, "optimal_sor": 37},
+    "cdma_r3 (Ch. 7, b = 1)": {"parallel": 23, "serial": 16, "parallel_steffensen": 13, "serial_steffensen": 9,
+                               "jacobi": 111, "optimal_sor": 17},
+    "cdma_r4 (Ch. 7, b = 1)": {"parallel": 24, "serial": 13, "parallel_steffensen": 13, "serial_steffensen": 7,
+                               "jacobi": 24, "optimal_sor": 14},
+}
+PAPER_KRR = {
+    "hardware": "5 x 3.5 GHz Intel Pentium, C + MPICH2 (UCI sets); IBM Blue Gene, 1024 CPUs (large sets)",
+    "gabp_vs_ibm_parallel_solver_s": {"Isolet": [228, 1328], "Letter": [468, 601], "Mushroom": [226, 176],
+                                      "Nursery": [221, 297], "Pageblocks": [26, 37], "Pen digits": [45, 155],
+                                      "Spambase": [49, 79]},
+    "blue_gene_1024_cpus_s": {"Covertype (150k)": 468, "MNIST (60k)": 756},
+}
+
+
+def paper_context(torch, g, workloads):
+    """The paper's printed round counts beside this build's sweep counts on the same small
+    systems, at relative residual 1e-6 (the stop rule here; the paper's is an unstated
+    message-change rule, so the counts are context, not parity targets)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import _golden
+    mats = {}
+    d = _golden.load("nonpsd3.txt")
+    mats["nonpsd_3x3 (Ch. 4 Sec. 4.2, b = 1)"] = workloads.from_dense(_golden.as_float(_golden.matrix(d)),
+                                                                      _golden.as_float(_golden.vector(d, "b")))
+    mats["poisson_p10 (Ch. 4 Sec. 4.3, f = -1)"] = workloads.poisson2d(10)
+    for key, f in (("cdma_r3 (Ch. 7, b = 1)", "cdma_r3.txt"), ("cdma_r4 (Ch. 7, b = 1)", "cdma_r4.txt")):
+        d = _golden.load(f)
+        A = _golden.as_float(_golden.matrix(d))
+        mats[key] = workloads.from_dense(A, np.ones(len(A)))
+    ours = {}
+    for key, q in mats.items():
+        bq = torch.from_numpy(q.b).to("cuda")
+        row = {}
+        for name, kw in (("parallel", {}), ("serial", {"layout": "serial"}), ("parallel_aitken", {"aitken": True}),
+                         ("parallel_steffensen", {"steffensen": True})):
+            s = g.Solver(q.row_ptr, q.col, q.val, reuse_precision=False, **kw)
+            _, info = s.solve(bq, tol=1e-6, max_iter=5000, check=False)
+            row[name] = info["sweeps"] if info["converged"] else f"not converged ({info['status']})"
+            s.close()
+        ours[key] = row
+    return {"note": "context only: the paper's iteration counts use a message-change threshold of 1e-6 "
+                    "(precision and hardware unstated); this build stops on the relative residual",
+            "paper_rounds": PAPER_ROUNDS, "this_build_sweeps_rel_residual_1e-6": ours, "paper_krr_times": PAPER_KRR}
 
 
 def probe(torch, g, workloads, args):
@@ -646,6 +713,35 @@ def probe(torch, g, workloads, args):
         log(f"{prec}/{layout}/{epb}: {info}")
         s.close()
     torch.cuda.synchronize()
+
+
+def batched_probe(torch, g, workloads, args):
+    """Launches for rocprofv3 runs of the batched solve: the 1 GiB copy (counter
+    calibration), then one solve of the first NSYS systems of the 4096-system
+    batch.  Prints one JSON line with the algorithmic bytes of that launch."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
+    del src, dst
+    bt = workloads.config3(num_sys=args.batched_probe)
+    B = torch.from_numpy(bt.B).to("cuda")
+    bs = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val)
+    X = torch.empty_like(B)
+    for rep in range(max(1, args.steps)):
+        log(f"batched probe: {bt.num_sys} systems, solve {rep}")
+        dt, (X, infos, st) = timed(torch, lambda: bs.solve(bt.nrhs, bt.rhs_off, B, tol=TOL, max_iter=100000, X=X,
+                                                           check=False), reps=1)
+    E_s = np.diff(bt.row_ptr[bt.sys_row_off]) - np.diff(bt.sys_row_off)
+    slot_rhs = float(np.sum(E_s.astype(np.float64) * bt.nrhs * np.array([i["sweeps"] for i in infos])))
+    prof = bs.profile()
+    bs.close()
+    print(json.dumps({"batched_probe": {"num_sys": bt.num_sys, "status": st, "time_to_tol_ms": 1e3 * dt,
+                                        "converged_systems": sum(i["converged"] for i in infos),
+                                        "slot_rhs_updates": slot_rhs, "alg_bytes": 12 * slot_rhs,
+                                        "load_balance": prof}}), flush=True)
 
 
 def extras(torch, g, workloads, args):
@@ -705,6 +801,8 @@ def main():
                     help="skip the other workloads (grid, adjoint, convergence fix, batched)")
     ap.add_argument("--probe", action="store_true",
                     help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
+    ap.add_argument("--batched-probe", type=int, metavar="NSYS", default=0,
+                    help="profiling probe: the 1 GiB copy and solves of the first NSYS systems of the batch")
     ap.add_argument("--extras", action="store_true",
                     help="time the opt-in variants (Aitken's extrapolation, the augmented solve) on their own")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -726,6 +824,9 @@ def main():
 
     if args.probe:
         probe(torch, g, workloads, args)
+        return
+    if args.batched_probe:
+        batched_probe(torch, g, workloads, args)
         return
     if args.extras:
         extras(torch, g, workloads, args)
@@ -827,7 +928,8 @@ def main():
                          ("powerlaw_n2e20", lambda: suite_powerlaw(torch, g, workloads)),
                          ("adjoint_grid3d_64", lambda: suite_adjoint(torch, g, workloads)),
                          ("convfix_btb", lambda: suite_convfix(torch, g, workloads)),
-                         ("batched_4096", lambda: suite_batched(torch, g, workloads))):
+                         ("batched_4096", lambda: suite_batched(torch, g, workloads)),
+                         ("paper_context", lambda: paper_context(torch, g, workloads))):
             log(f"suite: {name}")
             try:
                 suite[name] = fn()
@@ -869,6 +971,7 @@ def main():
                                "and dispatch gaps of each sweep"},
         "cpu_baseline": cpu,
         "fp64": {"time_to_tol_ms": ms_step, "sweeps": sweeps64, "rel_residual": res64,
+                 "create_ms": 1e3 * r64["create_s"],
                  "wall_ms_per_step": 1e3 * r64["wall_s"] / args.steps,
                  "tol_roofline": tol_roofline(ms_step, sweeps64, n, E, 8),
                  "vs_oracle": vs_oracle.get("fp64")},
