@@ -170,6 +170,18 @@ typedef struct {
  * its summation order. */
 #define GABP_FLAG_MULTI_LAUNCH 32
 
+/* Test aid for the compact layout (ignored by the other layouts; implies one
+ * launch per sweep).  Before every sweep t the aggregate buffer that sweep t
+ * writes (it holds round t-3, which no sweep reads again) and the half of the
+ * slot-state buffer holding the other round parity (in^(t-1), which sweep t
+ * must not touch) are filled with all-ones bit patterns (NaN in FP32 and
+ * FP64); that half is saved before and restored after the sweep.  Once the
+ * device status reports the end of the solve the fills are skipped, as are
+ * the sweeps.  A solve that reads none of these stale words returns the same
+ * bits as without the flag.  Costs two device copies and two fills per sweep,
+ * and a save buffer of one slot-state half kept by the handle. */
+#define GABP_FLAG_POISON_STALE 128
+
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
   int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */

@@ -315,6 +315,7 @@ struct Ctx {
   int last_msg_round = -1;              // round held by msg_d[last_msg_round & 1] (tol <= 0 solves)
   int layout = kLayoutEdge;
   void* bstate_d = nullptr;             // node layout: per-slot message pairs [E]
+  void* poison_save_d = nullptr;        // GABP_FLAG_POISON_STALE: one saved slot-state half
                                         // (compact layout: the two incoming-message buffers)
   void* agg_d[3] = {nullptr, nullptr, nullptr};  // published aggregates [n]: by round parity (node
                                                  // layout), by round mod 3 (compact layout)
@@ -423,6 +424,8 @@ size_t sweep_lds_bytes(int K, int elt, bool joint);
 size_t msg_bytes(int elt, bool joint);  // bytes of one message record
 hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+// All-ones words over [p, p + bytes) unless st->done is set (bytes a multiple of 4).
+hipError_t launch_poison(void* p, size_t bytes, const DevStatus* st, hipStream_t s);
 hipError_t launch_norm(const double* v, int64_t n, double* partials, int nparts, double* out,
                        DevStatus* st, hipStream_t s);
 hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, const DevStatus* st,

@@ -359,6 +359,13 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   GABP_HIP(c, launch_cnode_prior<T>(c->n, cfg.honly ? (const T*)c->inv_pt_d : (const T*)cfg.diag,
                                     (const T*)cfg.rhs, c->agg_d[0], s));
   const int main_mode = cfg.honly ? kHOnly : kJoint;
+  // test aid: stale buffers filled with NaN around every sweep
+  const bool poison = (c->opts.flags & GABP_FLAG_POISON_STALE) && c->E > 0;
+  const size_t half = 2 * sizeof(T) * (size_t)c->E;
+  if (poison && !c->poison_save_d) {
+    const gabp_status r = dev_alloc(c, &c->poison_save_d, 2 * sizeof(double) * (size_t)c->E);
+    if (r != GABP_OK) return r;
+  }
   const int last = M + 1;
   Poller poll;
   ChunkPlan plan;
@@ -388,10 +395,17 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       const bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1)));
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
+      void* other = poison ? cin_buf<T>(c, t + 1) : nullptr;  // in^(t-1): not sweep t's to touch
+      if (poison) {
+        GABP_HIP(c, hipMemcpyAsync(c->poison_save_d, other, half, hipMemcpyDeviceToDevice, s));
+        GABP_HIP(c, launch_poison(other, half, cfg.st, s));
+        GABP_HIP(c, launch_poison(k.anew, 2 * sizeof(T) * (size_t)c->n, cfg.st, s));  // round t-3
+      }
       hipEvent_t e0, e1;
       start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && (ck || ait), &e0, &e1);
       if (e0) c->timed_mode = cfg.honly ? 1 : 0;
       GABP_HIP(c, launch_cnode<T>(mode, c->K, k, s, e0, e1));
+      if (poison) GABP_HIP(c, hipMemcpyAsync(other, c->poison_save_d, half, hipMemcpyDeviceToDevice, s));
       if (ck)
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
                                         true, s));
@@ -557,7 +571,8 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg) {
 // Plain FP64 solves of small compact-layout handles take the one-launch path.
 bool use_small(const Ctx* c, const RunCfg& cfg) {
   return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y && !cfg.stf_start &&
-         !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS)) && small_fits(c->n, c->E);
+         !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS | GABP_FLAG_POISON_STALE)) &&
+         small_fits(c->n, c->E);
 }
 
 template <typename T>

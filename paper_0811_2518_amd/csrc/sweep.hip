@@ -554,6 +554,20 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_poison(uint32_t* p, int64_t n, const DevStatus* st) {
+  if (st && st->done) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0xffffffffu;
+}
+
+hipError_t launch_poison(void* p, size_t bytes, const DevStatus* st, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_poison, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, n, st);
+  return hipGetLastError();
+}
+
 // ||v||_2 in two deterministic stages: per-workgroup partial sums, then one
 // workgroup adding them in index order.
 __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* v, int64_t n, double* partials) {
