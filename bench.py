@@ -139,6 +139,20 @@ for _K in (2, 4, 8):
     TRAFFIC_KERNELS[f"k_serial_fp64_k{_K}"] = (f"k_serial<double, {_K}, false>", "serial.hip")
 
 
+def streamed_reads_and_gathers(tag, n, E, elt=8):
+    """(streamed read bytes, gathered payload bytes) of one FP64 joint sweep
+    launch of the kernel behind a TRAFFIC_KERNELS tag, from the kernel byte
+    models above: the streamed reads are the coalesced row and slot loads, the
+    gathers the neighbour records read through an index."""
+    if tag.startswith("k_cnode"):    # compact: column, A_ij, incoming pair; row ptr, A_ii, b, own aggregates of two rounds
+        return (4 + 3 * elt) * E + (4 + 6 * elt) * n, 2 * elt * E
+    if tag.startswith("k_bcast"):    # node broadcast: column, A_ij, both pairs; row ptr, A_ii, b, own aggregate
+        return (4 + 5 * elt) * E + (4 + 4 * elt) * n, 2 * elt * E
+    if tag.startswith("k_serial"):   # colour-serial: column, A_ij, outgoing pair; row ptr, A_ii, b, aggregate, L
+        return (4 + 3 * elt) * E + (4 + 4 * elt + 8) * n, 2 * elt * E
+    return (4 + elt) * E + (4 + 3 * elt) * n, 3 * elt * E  # edge layout: rev, A_ij; the reverse record
+
+
 def kernel_bytes_of(layout, n, E, elt):
     if layout == 4:
         return serial_layout_bytes(n, E, elt)
@@ -147,6 +161,20 @@ def kernel_bytes_of(layout, n, E, elt):
     if layout == 2:
         return node_layout_bytes(n, E, elt)
     return sweep_bytes(n, E, elt, check=True)
+
+
+def measured_traffic_split(kernel_tag):
+    """HBM bytes per launch by the split model (streamed reads at the copy's
+    counter scale, gathers at the random-line scale), if the counters are current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(kernel_tag)
+    if not ent or "split" not in ent or ent.get("source_sha") != source_hash(TRAFFIC_KERNELS[kernel_tag][1]):
+        return None
+    return ent["split"]["bytes_per_launch"]
 
 
 def measured_traffic(kernel_tag):
@@ -176,8 +204,9 @@ def traffic_from(fetch_dir, write_dir, n, out_path=None):
 
     f, w = rows(fetch_dir), rows(write_dir)
     assert len(f) == len(w) and all(a["Kernel_Name"] == b["Kernel_Name"] for a, b in zip(f, w))
-    copy_f = [float(r["Counter_Value"]) for r in f if "copyBuffer" in r["Kernel_Name"]][:3]
-    copy_w = [float(r["Counter_Value"]) for r in w if "copyBuffer" in r["Kernel_Name"]][:3]
+    # the three 1 GiB copies are the largest copy dispatches of the probe
+    copy_f = sorted(float(r["Counter_Value"]) for r in f if "copyBuffer" in r["Kernel_Name"])[-3:]
+    copy_w = sorted(float(r["Counter_Value"]) for r in w if "copyBuffer" in r["Kernel_Name"])[-3:]
     fs = (1 << 20) / statistics.median(copy_f)  # KiB of the 1 GiB copy
     ws = (1 << 20) / statistics.median(copy_w)
     dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3  # us
@@ -208,6 +237,39 @@ def traffic_from(fetch_dir, write_dir, n, out_path=None):
                     "fetch_kib": fk, "write_kib": wk, "fetch_scale": fs, "write_scale": ws,
                     "bytes_per_launch": b, "source_file": src, "source_sha": source_hash(src)}
         print(f"| `{kname}` | {len(units)} | {fk:.1f} | {wk:.1f} | {b / 1e6:.1f} | {unit} |")
+    # counter scales of random line gathers (the calibration launches of the
+    # probe): FETCH_SIZE counts coalesced streams at half their bytes (the copy)
+    # but random line fills at about their full size, so the copy's x2 scale
+    # overstates the gathers of a sweep.  Split model: the kernel's streamed
+    # reads at the copy's scale, the rest of the count at the gathers' scale.
+    cal = calibration_report(fetch_dir, write_dir)
+    lines = cal.get("lines_128B")
+    if lines:
+        idx_bytes = 8 * lines["gathers"]  # int64 index stream of the gather
+        raw = lines["fetch_bytes_scaled"] / fs
+        beta = (raw - idx_bytes / fs) / float(1 << 30)
+        cal["gather_count_per_byte"] = beta
+        print(f"calibration: a random 128-byte line gather of 1 GiB counts {beta:.3f} of its bytes "
+              f"(the copy {1 / fs:.3f})")
+        for name in ("halves_64B", "records_16B"):
+            ent = cal.get(name)
+            if ent:
+                raw_g = ent["fetch_bytes_scaled"] / fs - 8 * ent["gathers"] / fs
+                ent["line_bytes_per_gather"] = raw_g / beta / ent["gathers"]
+                print(f"calibration: {name}: {ent['line_bytes_per_gather']:.1f} bytes fetched per gather")
+        E_ = 8 * n  # G(n, 4n): 4n distinct pairs, 8n directed slots
+        for tag, ent in out.items():
+            seq, gpay = streamed_reads_and_gathers(tag, n, E_)
+            gathered = (ent["fetch_kib"] * 1024.0 - seq / fs) / beta
+            ent["split"] = {"streamed_read_bytes": seq, "gather_payload_bytes": gpay,
+                            "gather_traffic_bytes": gathered, "gathers": E_,
+                            "bytes_per_gather": gathered / E_,
+                            "write_bytes": ent["write_kib"] * 1024.0 * ws,
+                            "bytes_per_launch": seq + gathered + ent["write_kib"] * 1024.0 * ws}
+            print(f"split {tag}: streamed {seq / 1e6:.1f} MB, gathers {gathered / 1e6:.1f} MB "
+                  f"({gathered / E_:.1f} B per gather of {gpay / E_:.0f} B), total "
+                  f"{ent['split']['bytes_per_launch'] / 1e6:.1f} MB")
+    out["_calibration"] = cal
     with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
 
@@ -239,15 +301,17 @@ def run_solves(torch, g, p, b, precision, steps, warmup, layout="auto"):
     return {"wall_s": wall, "event_ms": ev_ms, "infos": infos, "props": props, "x": xs, "create_s": create_s}
 
 
-def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto", edges_per_block=0):
+def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto", edges_per_block=0, check_every=1):
     """Per-sweep time of the checked FP64 joint sweep: slope between two
     fixed-length runs (tolerance below reach, so every sweep carries the fused
     check and nothing stops early), each timed with events around the whole
     call.  Includes the one-workgroup finish kernel and the dispatch gaps
     (for the colour-serial layout: all class launches of a sweep).  Pass the
-    layout and block size a timed solve used to time that same kernel."""
+    layout and block size a timed solve used to time that same kernel.  With
+    check_every >= n2 both runs check the same rounds (the prior and the
+    last), so the slope is the sweep without its check."""
     s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False, layout=layout,
-                 edges_per_block=edges_per_block)
+                 edges_per_block=edges_per_block, check_every=check_every)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda")
     s.solve(b, tol=1e-300, max_iter=n1, x=x)
     best = {}
@@ -456,6 +520,12 @@ def suite_adjoint(torch, g, workloads):
                           "alg_frac": ab / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "kernel_frac": kb / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "kernel_bytes_per_launch": kb, "alg_bytes_per_launch": ab}
+    # the same sweep without the fused check and its one-workgroup finish kernel
+    # (the solve checks every sweep; check_every trades that cost for a later stop)
+    per_u = sweep_period(torch, g, p, b, check_every=64)
+    out["joint_sweep_unchecked"] = {"avg_launch_ms": per_u,
+                                    "alg_frac": ab / (per_u * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "kernel_frac": kb / (per_u * 1e-3) / 1e9 / HBM_PEAK_GBS}
     return out
 
 
@@ -689,15 +759,76 @@ def paper_context(torch, g, workloads):
             "paper_rounds": PAPER_ROUNDS, "this_build_sweeps_rel_residual_1e-6": ours, "paper_krr_times": PAPER_KRR}
 
 
-def probe(torch, g, workloads, args):
-    """Launches for rocprofv3 counter runs: a plain copy of known size, then solves."""
+def calibration_launches(torch):
+    """Launches of known traffic for the rocprofv3 counter runs, in this order: a
+    1 GiB device copy three times; the same 1 GiB read as 128-byte lines in a
+    random order (every line once); one 64-byte half of every line, in a random
+    order; 2^24 random 16-byte records.  The index_select launches also read
+    their int64 index arrays.  Returns the expected bytes of the three gathers
+    for a fetch granularity of 64 and of 128 bytes."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    lines = src.view(-1, 16)
+    perm = torch.randperm(lines.shape[0], device="cuda", generator=gen)
+    halves = src.view(-1, 8)
+    ph = torch.randperm(halves.shape[0] // 2, device="cuda", generator=gen) * 2
+    recs = src.view(-1, 2)
+    pr = torch.randint(0, recs.shape[0], (1 << 24,), device="cuda", generator=gen)
+    out_h = torch.empty((ph.numel(), 8), dtype=torch.float64, device="cuda")
+    out_r = torch.empty((pr.numel(), 2), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
-    del src, dst
+    torch.index_select(lines, 0, perm, out=dst.view(-1, 16))
+    torch.index_select(halves, 0, ph, out=out_h)
+    torch.index_select(recs, 0, pr, out=out_r)
+    torch.cuda.synchronize()
+    log(f"calibration: copy 3 x {src.numel() * 8} bytes; line, half-line and 16-byte record gathers")
+    expect = {"lines_128B": {"read_64": (1 << 30) + 8 * perm.numel(), "read_128": (1 << 30) + 8 * perm.numel(),
+                             "write": 1 << 30},
+              "halves_64B": {"read_64": 64 * ph.numel() + 8 * ph.numel(), "read_128": 128 * ph.numel() + 8 * ph.numel(),
+                             "write": 64 * ph.numel()},
+              "records_16B": {"read_64": 64 * pr.numel() + 8 * pr.numel(), "read_128": 128 * pr.numel() + 8 * pr.numel(),
+                              "write": 16 * pr.numel()}}
+    del src, dst, perm, ph, pr, out_h, out_r
+    torch.cuda.empty_cache()
+    return expect
+
+
+def calibration_report(fetch_dir, write_dir):
+    """Scaled FETCH_SIZE / WRITE_SIZE of the calibration gathers against their known bytes
+    (the copy sets the scale, as in traffic_from)."""
+    import csv
+    import statistics
+
+    def rows(d):
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            return list(csv.DictReader(fh))
+
+    f, w = rows(fetch_dir), rows(write_dir)
+    cf = [float(r["Counter_Value"]) for r in f if "copyBuffer" in r["Kernel_Name"]]
+    cw = [float(r["Counter_Value"]) for r in w if "copyBuffer" in r["Kernel_Name"]]
+    cf = sorted(cf)[-3:]
+    cw = sorted(cw)[-3:]
+    fs = (1 << 20) / statistics.median(cf)
+    ws = (1 << 20) / statistics.median(cw)
+    gi = [i for i, r in enumerate(f) if "gather_kernel" in r["Kernel_Name"]][:3]
+    wi = [i for i, r in enumerate(w) if "gather_kernel" in r["Kernel_Name"]][:3]
+    n_idx = [1 << 23, 1 << 23, 1 << 24]
+    names = ["lines_128B", "halves_64B", "records_16B"]
+    out = {"fetch_scale": fs, "write_scale": ws}
+    for name, i, j, m in zip(names, gi, wi, n_idx):
+        out[name] = {"kernel": f[i]["Kernel_Name"][:80], "fetch_bytes_scaled": float(f[i]["Counter_Value"]) * 1024 * fs,
+                     "write_bytes_scaled": float(w[j]["Counter_Value"]) * 1024 * ws, "gathers": m}
+    return out
+
+
+def probe(torch, g, workloads, args):
+    """Launches for rocprofv3 counter runs: the calibration launches of known
+    traffic, then solves."""
+    calibration_launches(torch)
     p = workloads.config2(args.n)
     b = torch.from_numpy(p.b).to("cuda")
     # every block size of the layouts the autotuner picks for the timed solves,
@@ -716,16 +847,10 @@ def probe(torch, g, workloads, args):
 
 
 def batched_probe(torch, g, workloads, args):
-    """Launches for rocprofv3 runs of the batched solve: the 1 GiB copy (counter
+    """Launches for rocprofv3 runs of the batched solve: the calibration launches (counter
     calibration), then one solve of the first NSYS systems of the 4096-system
     batch.  Prints one JSON line with the algorithmic bytes of that launch."""
-    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    log(f"copy probe: 3 x {src.numel() * 8} bytes read and written")
-    del src, dst
+    calibration_launches(torch)
     bt = workloads.config3(num_sys=args.batched_probe)
     B = torch.from_numpy(bt.B).to("cuda")
     bs = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val)
@@ -871,6 +996,7 @@ def main():
     achieved = alg / (per_launch_ms * 1e-3) / 1e9
     kname, ktag = LAYOUT_KERNELS[layout]
     traffic = measured_traffic(f"{ktag}_k{r64['props']['edges_per_block'] // 256}")
+    traffic_split = measured_traffic_split(f"{ktag}_k{r64['props']['edges_per_block'] // 256}")
 
     # the two precisions against each other (both are compared with the FP64
     # oracle's solution below when the CPU baseline runs)
@@ -966,6 +1092,12 @@ def main():
                      "copy_GBs": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs,
                      "traffic_GBs": traffic / (per_launch_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_split": traffic_split,
+                     "traffic_split_note": "FETCH_SIZE counts a coalesced stream at half its bytes but a random "
+                                           "128-byte line fill at 0.97 of them (calibration launches of the "
+                                           "probe), so traffic (both counts at the copy's scale) overstates "
+                                           "the gathers; traffic_split scales the kernel's streamed reads as "
+                                           "the copy and the rest of the count as random line fills",
                      "avg_launch_ms": per_launch_ms,
                      "timing": "slope of fixed-length checked runs; includes the finish kernel "
                                "and dispatch gaps of each sweep"},
