@@ -723,11 +723,12 @@ __global__ void k_build_sell(int32_t nslices, const Slice* __restrict__ slices, 
 
 // Spectral radius of R = D^-1/2 (D - A) D^-1/2 (the signed off-diagonal part,
 // D = diag A) of every system, for the work estimate: kRhoIters steps of the
-// power iteration from a scrambled start, one workgroup per system, the
-// estimate being the growth of the 2-norm in the last step (a lower bound
-// that approaches rho).  Attractive systems (all A_ij < 0, the grids) have
-// rho(R) = rho(|R|) = 1 / (dominance ratio); mixed signs give much less, and
-// GaBP's sweep count follows rho(R), not the dominance ratio.
+// power iteration from a scrambled start, one workgroup per system, on the
+// similar matrix D^-1 (D - A) (same spectrum, no square roots), the estimate
+// being the growth of the 2-norm in the last step (it approaches rho).
+// Attractive systems (all A_ij < 0, the grids) have rho(R) = rho(|R|) =
+// 1 / (dominance ratio); mixed signs give much less, and GaBP's sweep count
+// follows rho(R), not the dominance ratio.
 constexpr int kRhoIters = 30;
 
 __global__ __launch_bounds__(256) void k_sys_rho(int num_sys, const int32_t* __restrict__ sys_row_off,
@@ -749,13 +750,9 @@ __global__ __launch_bounds__(256) void k_sys_rho(int num_sys, const int32_t* __r
     for (int it = 0; it < kRhoIters; ++it) {
       double nx = 0.0, ny = 0.0;
       for (int r = r0 + (int)threadIdx.x; r < r1; r += 256) {
-        const double sr = 1.0 / sqrt(fabs(d[r]));
         double acc = 0.0;
-        for (int q = off_ptr[r]; q < off_ptr[r + 1]; ++q) {
-          const int c = off_col[q];
-          acc -= a[q] * x[c] / sqrt(fabs(d[c]));
-        }
-        acc *= sr;
+        for (int q = off_ptr[r]; q < off_ptr[r + 1]; ++q) acc -= a[q] * x[off_col[q]];
+        acc /= d[r];
         y[r] = acc;
         nx += x[r] * x[r];
         ny += acc * acc;
