@@ -10,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgabp.so")
+# measurement aid for the benchmark (random-gather cost), not part of the library
+PROBE_SOURCE = os.path.join("probe", "gather_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libgabp_probe.so")
 SOURCES = ["ingest.hip", "colour.hip", "partition.hip", "sweep.hip", "bcast.hip", "compact.hip", "serial.hip", "small.hip", "noalloc.hip", "loading.hip", "solve.hip",
            "batched.hip", "capi.hip"]
 ARCH = os.environ.get("GABP_OFFLOAD_ARCH", "gfx950")
@@ -24,7 +27,7 @@ CFLAGS = [
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(OUT_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
     cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
@@ -42,8 +45,15 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    pobj = _compile(PROBE_SOURCE)
+    tmp = PROBE_LIB + ".tmp"
+    res = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, pobj],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, PROBE_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE_LIB}")
     return LIB
 
 

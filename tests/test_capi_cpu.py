@@ -41,3 +41,11 @@ def test_struct_layouts():
     assert ctypes.sizeof(binding.Info) == 4 * 4 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(binding.Props) == 8 + 8 + 6 * 4 + 8 + 3 * 8
     assert ctypes.sizeof(binding.BatchProfile) == 2 * 4 + 3 * 8 + 2 * 8 + 4 * 4 + 8 + 2 * 4 + 8
+
+
+def test_probe_library_loads_and_exports_its_entry_point():
+    # the benchmark's gather-cost probe is a library of its own, outside the ABI above
+    import ctypes
+    from paper_0811_2518_amd import build
+    lib = ctypes.CDLL(build.PROBE_LIB)
+    assert hasattr(lib, "gabp_probe_gather16")
