@@ -33,8 +33,9 @@ namespace {
 constexpr int kSB = kSmallLanes;  // lanes of the one workgroup
 
 __host__ __device__ constexpr size_t small_lds(int n, int K) {
-  // aggregates [3][n] {P, h}; staged P, h and a x terms [S]; residual partials
-  return sizeof(double) * (6 * (size_t)n + 3 * (size_t)kSB * K) + sizeof(double) * (kSB / 64);
+  // aggregates [3][n] {P, h}; means of the last round [n]; staged P, h and
+  // a x terms [S]; residual partials of two sweeps
+  return sizeof(double) * (7 * (size_t)n + 3 * (size_t)kSB * K) + sizeof(double) * (2 * kSB / 64);
 }
 
 __device__ __forceinline__ double wsum(double v) {
@@ -44,10 +45,12 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // Deterministic sum over the 1024 lanes: wave sums, then the 16 wave sums in
-// order by lane 0.  Every lane gets the total.
+// order, by every lane.  Every lane gets the total.  The caller passes one of
+// two buffers by sweep parity, so no barrier is needed before the wave sums are
+// stored (a lane cannot be a whole sweep ahead of another); the barrier after
+// them also orders everything the lanes did before the call.
 __device__ __forceinline__ double small_sum(double v, double* s_red) {
   v = wsum(v);
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
   __syncthreads();
   double tot = 0.0;
@@ -64,10 +67,11 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
   if (E < 0 || E > kSB * K || n < 1 || n > kSB) return;  // never run past the lanes' slots
   double* aggP = sm;              // [3][n]
   double* aggH = sm + 3 * n;      // [3][n]
-  double* sP = sm + 6 * n;        // [S]
+  double* xm = sm + 6 * n;        // [n] means h~ / P~ of the last round, for the next check
+  double* sP = sm + 7 * n;        // [S]
   double* sH = sP + kSB * K;      // [S]
   double* sX = sH + kSB * K;      // [S]
-  double* s_red = sX + kSB * K;   // [16]
+  double* s_red = sX + kSB * K;   // [2][16]
 
   // ---- set-up: the lane's slots and row, the prior as round 0 --------------
   int sc[K], srow[K];
@@ -97,6 +101,7 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
     br = A.rhs[tid];
     aggP[tid] = dr;  // round 0: the prior {A_ii, b_i}
     aggH[tid] = br;
+    xm[tid] = br / dr;
     // the row of each slot, through the staging area
     for (int s = rlo; s < rhi; ++s) ((int*)sX)[s] = tid;
   }
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
   if (A.rhs_norm) {
     bnorm = *A.rhs_norm;
   } else {
-    bnorm = sqrt(small_sum(own_row ? br * br : 0.0, s_red));
+    bnorm = sqrt(small_sum(own_row ? br * br : 0.0, s_red + kSB / 64));
   }
   __syncthreads();
 #pragma unroll
@@ -121,17 +126,19 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
   double last_rel = -1.0, prev_rel = -1.0;
   int last_round = -1, prev_round = -1, conv = -1, err = 0;
   int t = 1;
+  bool synced = true;  // the set-up ended with a barrier
   // sweeps 1..M update the messages; sweep M+1 only checks round M
   for (; t <= M + 1; ++t) {
     const bool upd = t <= M;
     const bool ck = exact ? (t == M + 1) : in_set(t - 1);
     if (!upd && !ck) break;
+    const bool ck_next = upd && (exact ? (t == M) : in_set(t));  // sweep t+1 checks round t
     const int q1 = (t - 1) % 3, q2 = (t + 1) % 3, qn = t % 3;  // rounds t-1, t-2, t
     const bool first = t == 1;
     const bool odd = (t & 1) != 0;
     bool bad = false;
     // 1. slot updates: in^(t) = F(A_i^(t-1), out^(t-1)), out^(t-1) = F(A_j^(t-2), in^(t-2))
-    __syncthreads();
+    if (!synced) __syncthreads();  // the last row phase's aggregates and means are in place
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int s = tid + k * kSB;
@@ -140,7 +147,7 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
         const double av = sa[k];
         const double gP = aggP[q1 * n + c], gh = aggH[q1 * n + c];
         double ax = 0.0;
-        if (ck) ax = av * (gh / gP);
+        if (ck) ax = av * xm[c];  // x_c of round t-1 = gh / gP, formed once by c's row lane
         if (upd) {
           double Pout = 0.0, hout = 0.0;
           if (!first) {  // in^(t-2): the same parity as round t
@@ -174,20 +181,25 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
     // 2. row sums: round t's aggregates; the residual of round t-1
     double res2 = 0.0;
     if (own_row) {
+      double xi = 0.0;
+      if (ck) xi = xm[tid];  // read before it is replaced by round t's mean below
       if (upd) {
         const double P = lds_row_sum(dr, sP, rlo, rhi);
         const double h = lds_row_sum(br, sH, rlo, rhi);
         aggP[qn * n + tid] = P;
         aggH[qn * n + tid] = h;
+        if (ck_next) xm[tid] = h / P;
       }
       if (ck) {
-        double acc = br - dr * (aggH[q1 * n + tid] / aggP[q1 * n + tid]);
+        double acc = br - dr * xi;
         acc = lds_row_sub(acc, sX, rlo, rhi);
         res2 = acc * acc;
       }
     }
+    synced = false;
     if (ck) {
-      const double rn = sqrt(small_sum(res2, s_red));
+      const double rn = sqrt(small_sum(res2, s_red + (t & 1) * (kSB / 64)));
+      synced = true;
       const double rel = bnorm > 0.0 ? rn / bnorm : rn;
       prev_rel = last_rel;
       prev_round = last_round;

@@ -543,7 +543,7 @@ gabp_status run_serial(Ctx* c, const RunCfg& cfg) {
 // state of the multi-launch compact path: the means (and P~) of the returned
 // round by parity, the incoming messages of the last two rounds and the
 // aggregates of the last three, and the status the finish kernels would leave.
-gabp_status run_small(Ctx* c, const RunCfg& cfg) {
+gabp_status run_small(Ctx* c, const RunCfg& cfg, double* x, double* var) {
   SmallArgs a{};
   a.n = c->n;
   a.E = (int32_t)c->E;
@@ -552,7 +552,9 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg) {
   a.a = c->a64_d;
   a.diag = (const double*)cfg.diag;
   a.rhs = (const double*)cfg.rhs;
-  a.rhs_norm = cfg.rhs_norm;
+  a.rhs_norm = nullptr;  // ||b|| formed in the kernel
+  a.x_direct = x;
+  a.var_direct = var;
   a.tol = cfg.tol;
   a.max_iter = cfg.max_iter;
   a.check_every = cfg.check_every;
@@ -729,7 +731,6 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
       }
   }
   reset_timing(c);
-  GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
   RunCfg cfg;
   cfg.honly = honly;
   cfg.rhs = b;
@@ -750,11 +751,15 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     cfg.ait_hist = c->ait_hist_d;
   }
   if (stf) cfg.stf_start = c->ait_hist_d;
-  gabp_status rs = use_small(c, cfg) ? run_small(c, cfg) : run_sweeps<double>(c, cfg);
+  // the one-launch path forms ||b|| itself and writes x and the variances of
+  // the returned round directly
+  const bool small = use_small(c, cfg);
+  if (!small) GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
+  gabp_status rs = small ? run_small(c, cfg, x, var) : run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
   const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
   const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
-  GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
+  if (!small) GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
   if (ait) GABP_HIP(c, hipMemcpyAsync(x, c->ait_y_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   if (var && honly) GABP_HIP(c, hipMemcpyAsync(var, c->inv_pt_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   DevStatus st;
