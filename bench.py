@@ -329,6 +329,24 @@ def sweep_period(torch, g, p, b, n1=8, n2=40, reps=3, layout="auto", edges_per_b
     return (best[n2] - best[n1]) / (n2 - n1)
 
 
+def kernel_event_period(torch, g, p, b, layout="auto", edges_per_block=0, sweeps=40, reps=3):
+    """Average duration of the checked FP64 joint sweep kernel itself: HIP
+    events attached to every sweep dispatch (GABP_FLAG_TIME_SWEEPS) on the
+    handle's stream, over `sweeps` checked sweeps, best of reps.  Agrees with
+    the rocprofv3 kernel average; the finish kernel is not included."""
+    s = g.Solver(p.row_ptr, p.col, p.val, precision="fp64", reuse_precision=False, layout=layout,
+                 edges_per_block=edges_per_block, time_sweeps=True)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    s.solve(b, tol=1e-300, max_iter=8, x=x)
+    best = float("inf")
+    for _ in range(reps):
+        _, info = s.solve(b, tol=1e-300, max_iter=sweeps, x=x)
+        if info["timed_sweeps"] > 0:
+            best = min(best, info["sweep_ms"] / info["timed_sweeps"])
+    s.close()
+    return best
+
+
 def copy_rate(torch, nbytes=1 << 30, reps=5):
     """Measured device copy bandwidth (bytes read + written per second) of a
     1 GiB device-to-device tensor copy, best of reps."""
@@ -825,6 +843,58 @@ def calibration_report(fetch_dir, write_dir):
     return out
 
 
+def gather_probe(torch, args):
+    """Cost of random 16-byte gathers (libgabp_probe.so): 2^23 gathers with a
+    streamed int32 index, best of five launches, (1) by the size of the
+    gathered array and (2) on a 16.8 MB array (the aggregates of the bench
+    workload) with a share of each workgroup's indices drawn inside the 2.1 MB
+    window of its XCD (workgroup b runs on XCD b mod 8), the rest uniform.
+    Prints one JSON line."""
+    import ctypes
+    from paper_0811_2518_amd import build as pbuild
+    if not os.path.exists(pbuild.PROBE_LIB):
+        raise RuntimeError(f"{pbuild.PROBE_LIB} is not built: run python -m paper_0811_2518_amd.build")
+    lib = ctypes.CDLL(pbuild.PROBE_LIB)
+    lib.gabp_probe_gather16.restype = ctypes.c_int
+    lib.gabp_probe_gather16.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_float)]
+    n, grid = 1 << 23, 4096
+    stride = grid * 256
+    out = torch.empty((stride, 2), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(5)
+
+    def run(idx_np, nsrc):
+        idx = torch.from_numpy(idx_np.astype(np.int32)).to("cuda")
+        src = torch.ones((nsrc, 2), dtype=torch.float64, device="cuda")
+        ms = ctypes.c_float()
+        torch.cuda.synchronize()
+        st = lib.gabp_probe_gather16(idx.data_ptr(), n, src.data_ptr(), nsrc, out.data_ptr(), grid, 5,
+                                     ctypes.byref(ms))
+        if st != 0:
+            raise RuntimeError(f"gather probe: HIP error {st}")
+        return {"us": 1e3 * ms.value, "G_gathers_per_s": n / (ms.value * 1e-3) / 1e9}
+
+    by_size = {}
+    for mb in (1.05, 2.1, 4.2, 8.4, 16.8, 33.6):
+        nsrc = int(mb * 1e6 / 16)
+        by_size[f"{mb:g} MB"] = run(rng.integers(0, nsrc, n), nsrc)
+        log(f"gather probe: {mb:g} MB array: {by_size[f'{mb:g} MB']}")
+    nsrc = int(16.8e6 / 16) // 8 * 8
+    W = nsrc // 8
+    xcd = ((np.arange(n) % stride) // 256) % 8
+    by_share = {}
+    for share in (0.0, 0.41, 0.70, 1.0):
+        inside = rng.random(n) < share
+        idx = np.where(inside, xcd * W + rng.integers(0, W, n), rng.integers(0, nsrc, n))
+        by_share[f"{share:g}"] = run(idx, nsrc)
+        log(f"gather probe: share {share:g} inside the XCD window: {by_share[f'{share:g}']}")
+    print(json.dumps({"gather_probe": {"gathers": n, "record_bytes": 16, "index": "int32, streamed",
+                                        "by_array_size": by_size,
+                                        "xcd_window": {"array_MB": 16.8, "window_MB": 2.1, "by_share": by_share}}}),
+          flush=True)
+
+
 def probe(torch, g, workloads, args):
     """Launches for rocprofv3 counter runs: the calibration launches of known
     traffic, then solves."""
@@ -928,6 +998,8 @@ def main():
                     help="profiling probe: a 1 GiB device copy (counter calibration) and a few solves")
     ap.add_argument("--batched-probe", type=int, metavar="NSYS", default=0,
                     help="profiling probe: the 1 GiB copy and solves of the first NSYS systems of the batch")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="measurement probe: cost of random 16-byte gathers by array size and XCD window")
     ap.add_argument("--extras", action="store_true",
                     help="time the opt-in variants (Aitken's extrapolation, the augmented solve) on their own")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -953,6 +1025,9 @@ def main():
     if args.batched_probe:
         batched_probe(torch, g, workloads, args)
         return
+    if args.gather_probe:
+        gather_probe(torch, args)
+        return
     if args.extras:
         extras(torch, g, workloads, args)
         return
@@ -971,6 +1046,8 @@ def main():
     layout_name = {v: k for k, v in g.binding.LAYOUTS.items()}[r64["props"]["layout"]]
     per_launch_ms = sweep_period(torch, g, p, b, layout=layout_name,
                                  edges_per_block=r64["props"]["edges_per_block"])
+    per_kernel_ms = kernel_event_period(torch, g, p, b, layout=layout_name,
+                                        edges_per_block=r64["props"]["edges_per_block"])
     copy_gbs = copy_rate(torch) / 1e9
     log("colour-serial schedule: FP64 and FP32 + FP64 refinement solves")
     r64s = run_solves(torch, g, p, b, "fp64", args.steps, args.warmup, layout="serial")
@@ -993,7 +1070,7 @@ def main():
     layout = r64["props"]["layout"]
     alg = alg_sweep_bytes(n, E, 8)
     kernel_bytes = kernel_bytes_of(layout, n, E, 8)
-    achieved = alg / (per_launch_ms * 1e-3) / 1e9
+    achieved = alg / (per_kernel_ms * 1e-3) / 1e9
     kname, ktag = LAYOUT_KERNELS[layout]
     traffic = measured_traffic(f"{ktag}_k{r64['props']['edges_per_block'] // 256}")
     traffic_split = measured_traffic_split(f"{ktag}_k{r64['props']['edges_per_block'] // 256}")
@@ -1088,19 +1165,23 @@ def main():
                      "alg_bytes_per_launch": alg,
                      "alg_model": "48 B/slot + 52 B/node (FP64 sweep, per-unit algorithmic model)",
                      "kernel_bytes_per_launch": kernel_bytes,
-                     "kernel_frac": kernel_bytes / (per_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "kernel_frac": kernel_bytes / (per_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "copy_GBs": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs,
-                     "traffic_GBs": traffic / (per_launch_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_GBs": traffic / (per_kernel_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_split_GBs": traffic_split / (per_kernel_ms * 1e-3) / 1e9 if traffic_split else None,
                      "traffic_split": traffic_split,
                      "traffic_split_note": "FETCH_SIZE counts a coalesced stream at half its bytes but a random "
                                            "128-byte line fill at 0.97 of them (calibration launches of the "
                                            "probe), so traffic (both counts at the copy's scale) overstates "
                                            "the gathers; traffic_split scales the kernel's streamed reads as "
                                            "the copy and the rest of the count as random line fills",
-                     "avg_launch_ms": per_launch_ms,
-                     "timing": "slope of fixed-length checked runs; includes the finish kernel "
-                               "and dispatch gaps of each sweep"},
+                     "avg_launch_ms": per_kernel_ms,
+                     "avg_launch_ms_slope": per_launch_ms,
+                     "frac_by_slope": alg / (per_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "timing": "HIP events attached to each of 40 checked sweep dispatches on the handle's "
+                               "stream (the kernel alone); avg_launch_ms_slope is the slope of fixed-length "
+                               "checked runs, which adds the finish kernel and the dispatch gaps"},
         "cpu_baseline": cpu,
         "fp64": {"time_to_tol_ms": ms_step, "sweeps": sweeps64, "rel_residual": res64,
                  "create_ms": 1e3 * r64["create_s"],
