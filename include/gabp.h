@@ -381,11 +381,18 @@ gabp_status gabp_create_batched(int32_t num_sys, const int32_t *sys_row_off,
  *   B        device float64 [rhs_off[num_sys]]
  *   X        device float64 [rhs_off[num_sys]] (output)
  *   tol      per-RHS relative residual target (FP64 refinement)
- *   max_iter cap on inner sweeps per system (all outer steps)
+ *   max_iter cap on the inner sweeps of each work item (all its outer steps)
  *   infos    HOST gabp_info [num_sys] (output, nullable)
- * One persistent-kernel launch (captured in a HIP graph and replayed)
- * processes all systems; precision messages are computed once per system and
- * shared by its right-hand sides.  Returns the worst status over systems.
+ * One HIP graph runs two persistent kernels; it is captured when the call's
+ * B, X, tol, max_iter, nrhs and rhs_off differ from the last call's and
+ * replayed when they repeat.  The
+ * first computes each system's precision messages once (FP32 P-only sweeps of
+ * Alg. 2 until P~ settles, at most opts.inner_max_iter sweeps) and freezes the
+ * h-update coefficients.  The second takes work items of 1, 2, 4 or 8
+ * right-hand sides of one system, all reading that system's frozen
+ * coefficients, and runs the FP64 refinement loop on each (FP64 residual,
+ * FP32 h-only inner sweeps to opts.inner_tol, at most opts.max_outer outer
+ * steps).  Returns the worst status over systems.
  */
 gabp_status gabp_solve_batched(gabp_handle h, const int32_t *nrhs, const int64_t *rhs_off,
                                const double *B, double *X, double tol, int32_t max_iter,
