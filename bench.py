@@ -712,8 +712,9 @@ def suite_batched(torch, g, workloads, sample=48):
             "roofline": {"bound": "hbm", "alg_bytes_per_update": 12,
                          "achieved_GBs": 12 * slot_rhs / dt / 1e9,
                          "frac": 12 * slot_rhs / dt / 1e9 / HBM_PEAK_GBS,
-                         "note": "HBM-equivalent: the working set of a work item (up to about 1e5 slots "
-                                 "x 8 right-hand sides) largely stays in its CU's share of L2"},
+                         "note": "algorithmic bytes over the whole solve (precision phase included); the "
+                                 "counters put the true traffic at 18-35 B per update, at about the device "
+                                 "copy rate (profiles/k_brhs_batch512_traffic.md)"},
             "load_balance": prof, "serial": serial,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
                                 "loop_ms": 1e3 * loop_s, "batched_ms": 1e3 * sub_s,

@@ -238,3 +238,47 @@ def test_batched_rejects_other_layouts(small_batch):
     bt = small_batch
     with pytest.raises(binding.GabpError):
         g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV, layout="compact")
+
+
+@pytest.mark.parametrize("layout", ["auto", "serial"])
+def test_batched_degenerate_systems(layout):
+    # empty systems, one- and two-node systems and an all-zero right-hand side,
+    # between ordinary ones: the empty ones converge at once, a zero right-hand
+    # side returns x = 0 exactly, everything else meets the parity bar
+    empty = workloads.Problem(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0))
+    probs = [workloads.grid2d_problem(9, 7, 41), empty, workloads.from_dense(np.array([[2.0]]), np.ones(1)),
+             workloads.from_dense(np.array([[2.0, -1.0], [-1.0, 3.0]]), np.ones(2)),
+             workloads.er_problem(300, 6, 42, ratio=1.2), empty,
+             workloads.from_dense(np.array([[0.5]]), np.ones(1))]
+    ks = [3, 2, 1, 4, 8, 1, 2]
+    bt = workloads.batch_of(probs, ks, seed=43)
+    n0 = probs[0].n
+    B0 = bt.B[bt.rhs_off[0]:bt.rhs_off[1]].reshape(n0, ks[0])
+    B0[:, 1] = 0.0  # one right-hand side of zeros (a view into the batch's B)
+    s, B, X, infos, st = _solve(bt, layout=layout)
+    assert st == binding.OK
+    assert all(i["converged"] == 1 and i["status"] == binding.OK for i in infos)
+    Xh = X.cpu().numpy()
+    x0 = Xh[bt.rhs_off[0]:bt.rhs_off[1]].reshape(n0, ks[0])
+    assert np.all(x0[:, 1] == 0.0)
+    for q in range(bt.num_sys):
+        p = bt.system(q)
+        if p.n == 0:
+            continue
+        k = p.b.shape[1]
+        xs = Xh[bt.rhs_off[q]:bt.rhs_off[q + 1]].reshape(p.n, k)
+        ref = oracle.dense_solve(p.dense(), p.b)
+        assert np.linalg.norm(xs - ref) <= 1e-8 * max(np.linalg.norm(ref), 1e-300), q
+
+
+def test_batched_unreachable_tolerance_ends_at_max_iter():
+    # every work item stops at the sweep cap and reports it; the launch ends
+    bt = workloads.config3(num_sys=16, nmin=64, nmax=1500, kmax=12, seed=4343)
+    s = g.BatchedSolver(bt.sys_row_off, bt.row_ptr, bt.col, bt.val, device=DEV)
+    B = torch.from_numpy(bt.B).to(DEV)
+    X, infos, st = s.solve(bt.nrhs, bt.rhs_off, B, tol=1e-300, max_iter=40, check=False)
+    assert st == binding.NOT_CONVERGED
+    for i in infos:
+        assert i["converged"] == 0 and i["status"] == binding.NOT_CONVERGED
+        assert 1 <= i["sweeps"] <= 40, i
+    assert torch.isfinite(X).all()
