@@ -93,7 +93,12 @@ typedef struct {
 /* Reuse precision messages frozen by an earlier solve on the same handle: the
  * P messages depend on A only (the precision update of Alg. 2 has no b term), so later solves
  * and the adjoint solve run mean-only sweeps.  Without the flag every
- * gabp_solve runs the full synchronous iteration from zero messages. */
+ * gabp_solve runs the full synchronous iteration from zero messages.  Inside
+ * one call, the outer loops freeze the precisions after the first inner solve
+ * and run the later inner solves mean-only when diagonal loading is on (many
+ * outer steps) or the flag is set; plain refinement without the flag runs
+ * every inner solve from zero messages (two outer steps at the default
+ * tolerances, where freezing would not pay). */
 #define GABP_FLAG_REUSE_PRECISION 1
 
 /* Profiling aid: time every main-mode sweep that carries the fused residual
