@@ -538,6 +538,11 @@ def suite_adjoint(torch, g, workloads):
                           "alg_frac": ab / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "kernel_frac": kb / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "kernel_bytes_per_launch": kb, "alg_bytes_per_launch": ab}
+    # the checked sweep kernel alone, by events attached to its dispatches
+    per_k = kernel_event_period(torch, g, p, b)
+    out["joint_sweep"].update({"kernel_event_ms": per_k,
+                               "alg_frac_kernel": ab / (per_k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "kernel_frac_kernel": kb / (per_k * 1e-3) / 1e9 / HBM_PEAK_GBS})
     # the same sweep without the fused check and its one-workgroup finish kernel
     # (the solve checks every sweep; check_every trades that cost for a later stop)
     per_u = sweep_period(torch, g, p, b, check_every=64)

@@ -167,12 +167,12 @@ typedef struct {
 
 /* Run one launch per sweep even where the whole solve fits one workgroup.
  * Without the flag, a plain FP64 solve (no reuse of frozen precisions, no
- * Aitken step, no sweep timing) on a compact-layout handle with n <= 1024 rows
- * and at most 4096 directed slots runs every sweep, check and stop decision
- * inside one launch of 1024 lanes, with the messages in registers and the
- * aggregates in LDS.  Both paths perform the same operations; x, the
- * variances and the messages agree bit for bit, the reported residual up to
- * its summation order. */
+ * Aitken or Steffensen step, no sweep timing) on a compact-layout handle with
+ * n <= 1024 rows, and either at most 4096 directed slots or at most 6 slots in
+ * every row, runs every sweep, check and stop decision inside one launch of
+ * 1024 lanes, with the messages in registers and the aggregates in LDS.  Both
+ * paths perform the same operations; x, the variances and the messages agree
+ * bit for bit, the reported residual up to its summation order. */
 #define GABP_FLAG_MULTI_LAUNCH 32
 
 /* Test aid for the compact layout (ignored by the other layouts; implies one

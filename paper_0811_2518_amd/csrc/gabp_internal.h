@@ -247,8 +247,11 @@ struct SmallArgs {
   void* agg_out[3];         // nullable: [n] {P~, h~} aggregates by round mod 3
   const int32_t* gate;      // nullable: nonzero -> the kernel returns at once
   const int32_t* E_dev;     // nullable: E read on the device (then E is ignored)
+  int32_t max_deg;          // largest row of the off-diagonal CSR (0: not known on the host)
 };
 bool small_fits(int64_t n, int64_t E);
+// rows of at most 6 slots: a lane per row, any E
+bool small_rows_fit(int64_t n, int32_t max_deg);
 hipError_t launch_small(const SmallArgs& a, hipStream_t s);
 // the same with K = 4 slots per lane (E <= 4096, also when E lives on the device)
 hipError_t launch_small_k4(const SmallArgs& a, hipStream_t s);
@@ -331,6 +334,8 @@ struct Ctx {
   double* norms_d = nullptr;              // [4]: ||b||, ||r_outer||, spare
   DevStatus* st_d = nullptr;              // [2]: inner / outer
   DevStatus* st_h = nullptr;              // pinned host mirror [4]
+  DevStatus* st_small_h = nullptr;        // pinned, coherent: written by the one-launch solve itself
+  DevStatus* st_small_d = nullptr;        // ... its device address
   DevStatus run_seen{};                   // status the last sweep loop's poller observed
   bool run_seen_final = false;            // ... and it was final (done set, nothing runs after)
   hipEvent_t ev[2] = {nullptr, nullptr};

@@ -262,11 +262,219 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
 
 }  // namespace
 
+// Rows of at most KR slots: lane i owns row i.  The messages of the row's
+// slots and the row's own aggregates of the last three rounds stay in
+// registers; only the aggregates the neighbours gather live in LDS, two rounds
+// by parity.  The lane sums its row as it updates the slots, in CSR order
+// after the diagonal (the order of the slot-per-lane kernel above and of the
+// multi-launch path), so the results are the same bit for bit.  A sweep needs
+// one barrier: the lanes publish round t and their residual partials, then
+// wait for each other, and only then read round t or overwrite round t-1.
+template <int KR>
+__global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
+  extern __shared__ __align__(16) double sm[];
+  const int tid = threadIdx.x;
+  if (A.gate && *A.gate) return;
+  const int n = A.n;
+  if (n < 1 || n > kSB) return;
+  double* gP = sm;               // [2][n] P~ by round parity
+  double* gH = sm + 2 * n;       // [2][n] h~ by round parity
+  double* gX = sm + 4 * n;       // [2][n] means h~ / P~ by round parity, for the next check
+  double* s_red = sm + 6 * n;    // [2][16] residual partials by sweep parity
+  const bool own = tid < n;
+  int rlo = 0, deg = 0;
+  double dr = 1.0, br = 0.0;
+  if (own) {
+    rlo = A.off_ptr[tid];
+    deg = A.off_ptr[tid + 1] - rlo;
+    dr = A.diag[tid];
+    br = A.rhs[tid];
+  }
+  if (deg > KR) deg = KR;  // the host sends only rows of at most KR slots
+  int cc[KR];
+  double aa[KR], mP0[KR], mH0[KR], mP1[KR], mH1[KR];
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    cc[k] = 0;
+    aa[k] = 0.0;
+    mP0[k] = mH0[k] = mP1[k] = mH1[k] = 0.0;
+    if (k < deg) {
+      cc[k] = A.col[rlo + k];
+      aa[k] = A.a[rlo + k];
+    }
+  }
+  // own aggregates of rounds t-1, t-2, t-3 (round 0: the prior {A_ii, b_i})
+  double o1P = dr, o1h = br, o2P = 0.0, o2h = 0.0, o3P = 0.0, o3h = 0.0;
+  if (own) {
+    gP[tid] = dr;
+    gH[tid] = br;
+    gX[tid] = br / dr;
+  }
+  double bnorm;
+  if (A.rhs_norm) {
+    bnorm = *A.rhs_norm;
+  } else {
+    bnorm = sqrt(small_sum(own ? br * br : 0.0, s_red + kSB / 64));
+  }
+  __syncthreads();
+
+  const bool exact = !(A.tol > 0.0);
+  const int M = A.max_iter;
+  const int ce = max(1, A.check_every);
+  auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
+  double last_rel = -1.0, prev_rel = -1.0;
+  int last_round = -1, prev_round = -1, conv = -1, err = 0;
+  int T = 0;  // the last round whose aggregates were formed
+  for (int t = 1; t <= M + 1; ++t) {
+    const bool upd = t <= M;
+    const bool ck = exact ? (t == M + 1) : in_set(t - 1);
+    if (!upd && !ck) break;
+    const bool ck_next = upd && (exact ? (t == M) : in_set(t));  // sweep t+1 checks round t
+    const int p1 = (t - 1) & 1, pn = t & 1;  // parities of rounds t-1 (read) and t (written)
+    const bool first = t == 1;
+    const bool odd = (t & 1) != 0;
+    bool bad = false;
+    double P = dr, h = br, acc = 0.0;
+    if (ck) acc = br - dr * gX[p1 * n + tid];  // the row's residual in round t-1
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      if (k < deg) {
+        const int c = cc[k];
+        const double av = aa[k];
+        const double gPc = gP[p1 * n + c], gHc = gH[p1 * n + c];
+        if (ck) acc -= av * gX[p1 * n + c];  // x_c = h~_c / P~_c, formed once by c's lane
+        if (upd) {
+          // in^(t) = F(A_c^(t-1), out^(t-1)), out^(t-1) = F(A_own^(t-2), in^(t-2))
+          double Pout = 0.0, hout = 0.0;
+          if (!first) {
+            const double mp = odd ? mP1[k] : mP0[k], mh = odd ? mH1[k] : mH0[k];
+            const double inv_out = 1.0 / (o2P - mp);
+            Pout = -av * av * inv_out;
+            hout = -av * (o2h - mh) * inv_out;
+          }
+          const double inv_in = 1.0 / (gPc - Pout);
+          const double Pn = -av * av * inv_in;
+          const double hn = -av * (gHc - hout) * inv_in;
+          if (odd) {
+            mP1[k] = Pn;
+            mH1[k] = hn;
+          } else {
+            mP0[k] = Pn;
+            mH0[k] = hn;
+          }
+          P += Pn;
+          h += hn;
+          bad |= !(isfinite(Pn) && isfinite(hn));
+        }
+      }
+    }
+    if (upd && own) {
+      gP[pn * n + tid] = P;
+      gH[pn * n + tid] = h;
+      if (ck_next) gX[pn * n + tid] = h / P;
+    }
+    double* red = s_red + (t & 1) * (kSB / 64);
+    if (ck) {
+      const double v = wsum(own ? acc * acc : 0.0);
+      if ((tid & 63) == 0) red[tid >> 6] = v;
+    }
+    const bool any_bad = __syncthreads_or(bad ? 1 : 0) != 0;
+    if (upd) {
+      o3P = o2P;
+      o3h = o2h;
+      o2P = o1P;
+      o2h = o1h;
+      o1P = P;
+      o1h = h;
+      T = t;
+    }
+    if (any_bad) {  // as the multi-launch path: the error ends the solve
+      err |= kErrNonfinite;
+      break;
+    }
+    if (ck) {
+      double tot = 0.0;
+      for (int w = 0; w < kSB / 64; ++w) tot += red[w];
+      const double rn = sqrt(tot);
+      const double rel = bnorm > 0.0 ? rn / bnorm : rn;
+      prev_rel = last_rel;
+      prev_round = last_round;
+      last_rel = rel;
+      last_round = t - 1;
+      if (rel <= A.tol) conv = t - 1;
+      else if (!(rel <= kDivergeLimit)) err |= kErrDiverged;
+    }
+    if (conv >= 0 || err) break;
+  }
+
+  // ---- results: the returned round and the state it leaves -----------------
+  const int ret = conv >= 0 ? conv : M;
+  double rP = o1P, rh = o1h;
+  if (ret == T - 1) {
+    rP = o2P;
+    rh = o2h;
+  } else if (ret == T - 2) {
+    rP = o3P;
+    rh = o3h;
+  }
+  if (own) {
+    if (A.xout[ret & 1]) A.xout[ret & 1][tid] = rh / rP;
+    if (A.ptout[ret & 1]) A.ptout[ret & 1][tid] = rP;
+    if (A.x_direct) A.x_direct[tid] = rh / rP;
+    if (A.var_direct) A.var_direct[tid] = 1.0 / rP;
+    // the aggregates of rounds T, T-1 and T-2 by round mod 3
+    const double P3[3] = {o1P, o2P, o3P}, H3[3] = {o1h, o2h, o3h};
+    for (int j = 0; j < 3 && j <= T; ++j) {
+      void* dst = A.agg_out[(T - j) % 3];
+      if (dst) {
+        double2 v;
+        v.x = P3[j];
+        v.y = H3[j];
+        ((double2*)dst)[tid] = v;
+      }
+    }
+  }
+  if (A.cin_out && own) {
+    const int E = A.E;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      if (k < deg) {
+        double2 v0, v1;
+        v0.x = mP0[k];
+        v0.y = mH0[k];
+        v1.x = mP1[k];
+        v1.y = mH1[k];
+        ((double2*)A.cin_out)[rlo + k] = v0;
+        ((double2*)A.cin_out)[(size_t)E + rlo + k] = v1;
+      }
+    }
+  }
+  if (tid == 0) {
+    DevStatus st{};
+    st.done = 1;
+    st.conv_round = conv;
+    st.error = err;
+    st.last_rel = last_rel;
+    st.last_round = last_round;
+    st.prev_rel = prev_rel;
+    st.prev_round = prev_round;
+    *A.st = st;
+  }
+}
+
 size_t small_lds_bytes(int n, int K) { return small_lds(n, K); }
 
 bool small_fits(int64_t n, int64_t E) { return n >= 1 && n <= kSmallLanes && E <= (int64_t)kSmallLanes * 4; }
 
+bool small_rows_fit(int64_t n, int32_t max_deg) { return n >= 1 && n <= kSmallLanes && max_deg >= 1 && max_deg <= 6; }
+
 hipError_t launch_small(const SmallArgs& a, hipStream_t s) {
+  if (a.E_dev == nullptr && small_rows_fit(a.n, a.max_deg)) {  // a lane per row
+    const uint32_t lds = (uint32_t)(sizeof(double) * (6 * (size_t)a.n + 2 * kSB / 64));
+    if (a.max_deg <= 4) hipLaunchKernelGGL(k_small_rows<4>, dim3(1), dim3(kSB), lds, s, a);
+    else hipLaunchKernelGGL(k_small_rows<6>, dim3(1), dim3(kSB), lds, s, a);
+    return hipGetLastError();
+  }
   if (!small_fits(a.n, a.E)) return hipErrorInvalidValue;
   const int K = a.E <= kSB ? 1 : (a.E <= 2 * kSB ? 2 : 4);
   const uint32_t lds = (uint32_t)small_lds(a.n, K);

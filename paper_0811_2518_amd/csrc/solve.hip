@@ -553,12 +553,17 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg, double* x, double* var) {
   a.diag = (const double*)cfg.diag;
   a.rhs = (const double*)cfg.rhs;
   a.rhs_norm = nullptr;  // ||b|| formed in the kernel
+  a.max_deg = c->max_degree;
   a.x_direct = x;
   a.var_direct = var;
   a.tol = cfg.tol;
   a.max_iter = cfg.max_iter;
   a.check_every = cfg.check_every;
-  a.st = cfg.st;
+  a.st = c->st_small_d;  // the status goes straight to pinned host memory (no copy launch)
+  DevStatus blank{};     // as the status reset leaves it, should the kernel not write
+  blank.conv_round = blank.last_round = blank.prev_round = -1;
+  blank.last_rel = blank.prev_rel = -1.0;
+  *c->st_small_h = blank;
   for (int p = 0; p < 2; ++p) {
     a.xout[p] = (double*)cfg.x2[p];
     a.ptout[p] = (double*)cfg.pt2[p];
@@ -574,7 +579,7 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg, double* x, double* var) {
 bool use_small(const Ctx* c, const RunCfg& cfg) {
   return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y && !cfg.stf_start &&
          !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS | GABP_FLAG_POISON_STALE)) &&
-         small_fits(c->n, c->E);
+         (small_fits(c->n, c->E) || small_rows_fit(c->n, c->max_degree));
 }
 
 template <typename T>
@@ -763,7 +768,13 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   if (ait) GABP_HIP(c, hipMemcpyAsync(x, c->ait_y_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   if (var && honly) GABP_HIP(c, hipMemcpyAsync(var, c->inv_pt_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   DevStatus st;
-  gabp_status r = read_status(c, c->st_d, &st);
+  gabp_status r = GABP_OK;
+  if (small) {
+    GABP_HIP(c, hipStreamSynchronize(s));
+    st = *c->st_small_h;
+  } else {
+    r = read_status(c, c->st_d, &st);
+  }
   if (r != GABP_OK) return r;
   r = map_status(c, st, exact);
   const int sweeps = st.conv_round >= 0 ? st.conv_round : max_iter;
