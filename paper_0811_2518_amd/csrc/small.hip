@@ -270,9 +270,19 @@ __global__ __launch_bounds__(kSB) void k_small(SmallArgs A) {
 // multi-launch path), so the results are the same bit for bit.  A sweep needs
 // one barrier: the lanes publish round t and their residual partials, then
 // wait for each other, and only then read round t or overwrite round t-1.
+// Workgroup barrier ordering LDS only (the sweeps touch no global memory).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int KR>
 __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
   extern __shared__ __align__(16) double sm[];
+  // non-finite message flags by sweep mod 3: sweep t sets [t % 3] and clears
+  // [(t + 1) % 3], which no lane reads or sets until sweep t + 1
+  __shared__ int s_bad[3];
   const int tid = threadIdx.x;
   if (A.gate && *A.gate) return;
   const int n = A.n;
@@ -310,6 +320,7 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
     gH[tid] = br;
     gX[tid] = br / dr;
   }
+  if (tid < 3) s_bad[tid] = 0;
   double bnorm;
   if (A.rhs_norm) {
     bnorm = *A.rhs_norm;
@@ -378,7 +389,10 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
       const double v = wsum(own ? acc * acc : 0.0);
       if ((tid & 63) == 0) red[tid >> 6] = v;
     }
-    const bool any_bad = __syncthreads_or(bad ? 1 : 0) != 0;
+    if (tid == 0) s_bad[(t + 1) % 3] = 0;
+    if (bad) s_bad[t % 3] = 1;
+    lds_barrier();
+    const bool any_bad = s_bad[t % 3] != 0;
     if (upd) {
       o3P = o2P;
       o3h = o2h;

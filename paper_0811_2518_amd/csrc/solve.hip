@@ -564,12 +564,14 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg, double* x, double* var) {
   blank.conv_round = blank.last_round = blank.prev_round = -1;
   blank.last_rel = blank.prev_rel = -1.0;
   *c->st_small_h = blank;
-  for (int p = 0; p < 2; ++p) {
-    a.xout[p] = (double*)cfg.x2[p];
-    a.ptout[p] = (double*)cfg.pt2[p];
+  // the messages and aggregates are left in the handle only where something
+  // reads them later: the frozen-precision pass of the reuse flag, and
+  // gabp_messages after a fixed-sweep solve (x and the variances go straight
+  // to the caller)
+  if (cfg.tol <= 0.0 || (c->opts.flags & GABP_FLAG_REUSE_PRECISION)) {
+    a.cin_out = c->bstate_d;
+    for (int q = 0; q < 3; ++q) a.agg_out[q] = c->agg_d[q];
   }
-  a.cin_out = c->bstate_d;
-  for (int q = 0; q < 3; ++q) a.agg_out[q] = c->agg_d[q];
   c->run_seen_final = false;
   GABP_HIP(c, launch_small(a, c->stream));
   return GABP_OK;
