@@ -862,22 +862,21 @@ def gather_probe(torch, args):
     if not os.path.exists(pbuild.PROBE_LIB):
         raise RuntimeError(f"{pbuild.PROBE_LIB} is not built: run python -m paper_0811_2518_amd.build")
     lib = ctypes.CDLL(pbuild.PROBE_LIB)
-    lib.gabp_probe_gather16.restype = ctypes.c_int
-    lib.gabp_probe_gather16.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
-                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                                        ctypes.POINTER(ctypes.c_float)]
+    fn = lib.gabp_probe_gather16_policy
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                   ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
     n, grid = 1 << 23, 4096
     stride = grid * 256
     out = torch.empty((stride, 2), dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(5)
 
-    def run(idx_np, nsrc):
+    def run(idx_np, nsrc, policy=0):
         idx = torch.from_numpy(idx_np.astype(np.int32)).to("cuda")
         src = torch.ones((nsrc, 2), dtype=torch.float64, device="cuda")
         ms = ctypes.c_float()
         torch.cuda.synchronize()
-        st = lib.gabp_probe_gather16(idx.data_ptr(), n, src.data_ptr(), nsrc, out.data_ptr(), grid, 5,
-                                     ctypes.byref(ms))
+        st = fn(idx.data_ptr(), n, src.data_ptr(), nsrc, out.data_ptr(), grid, 5, policy, ctypes.byref(ms))
         if st != 0:
             raise RuntimeError(f"gather probe: HIP error {st}")
         return {"us": 1e3 * ms.value, "G_gathers_per_s": n / (ms.value * 1e-3) / 1e9}
@@ -896,9 +895,19 @@ def gather_probe(torch, args):
         idx = np.where(inside, xcd * W + rng.integers(0, W, n), rng.integers(0, nsrc, n))
         by_share[f"{share:g}"] = run(idx, nsrc)
         log(f"gather probe: share {share:g} inside the XCD window: {by_share[f'{share:g}']}")
+    # the gathered load's cache policy: plain, non-temporal, relaxed atomic loads at agent / system scope
+    by_policy = {}
+    idx41 = np.where(rng.random(n) < 0.41, xcd * W + rng.integers(0, W, n), rng.integers(0, nsrc, n))
+    for pol, name in enumerate(("plain", "nontemporal", "atomic_agent", "atomic_system")):
+        small = int(2.1e6 / 16)
+        by_policy[name] = {"2.1 MB": run(rng.integers(0, small, n), small, pol),
+                           "16.8 MB": run(rng.integers(0, nsrc, n), nsrc, pol),
+                           "16.8 MB, share 0.41": run(idx41, nsrc, pol)}
+        log(f"gather probe: policy {name}: {by_policy[name]}")
     print(json.dumps({"gather_probe": {"gathers": n, "record_bytes": 16, "index": "int32, streamed",
                                         "by_array_size": by_size,
-                                        "xcd_window": {"array_MB": 16.8, "window_MB": 2.1, "by_share": by_share}}}),
+                                        "xcd_window": {"array_MB": 16.8, "window_MB": 2.1, "by_share": by_share},
+                                        "by_policy": by_policy}}),
           flush=True)
 
 

@@ -49,3 +49,4 @@ def test_probe_library_loads_and_exports_its_entry_point():
     from paper_0811_2518_amd import build
     lib = ctypes.CDLL(build.PROBE_LIB)
     assert hasattr(lib, "gabp_probe_gather16")
+    assert hasattr(lib, "gabp_probe_gather16_policy")
