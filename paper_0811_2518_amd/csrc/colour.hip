@@ -6,7 +6,8 @@
 // that none of its neighbours j < i holds.  That is a sequential O(E) pass on
 // the host over the already validated off-diagonal pattern.  The
 // off-diagonal CSR is then renumbered on the device so that each class is a
-// contiguous row range, rows kept in increasing caller order inside a class.
+// contiguous row range, rows kept in increasing caller order inside a class
+// (for a single system with XCD parts: inside a class's part and time slab).
 // For a batch of independent systems, first fit in global row order colours
 // every system on its own (no edge crosses a system), and the renumbering
 // stays inside each system's row block.
@@ -154,13 +155,15 @@ void plan_colour_order(Ctx* c, const std::vector<int32_t>& col, const int32_t* s
     ncol = std::max(ncol, k + 1);
   }
 
-  // a single system may also split every class by XCD part (the order inside
-  // a class does not change the iteration)
+  // a single system may also split every class by XCD part, and each part's
+  // rows by time slab (the order inside a class does not change the
+  // iteration)
   std::vector<int32_t> part;
   const bool parts = !sys_row_off && !(c->opts.flags & GABP_FLAG_NATURAL_ORDER) && xcd_parts(c, col, part);
+  const std::vector<int32_t> slab = parts ? time_slabs(c, col, part) : std::vector<int32_t>();
 
   // classes as contiguous ranges inside each system, caller order inside a
-  // class (inside a class's part with XCD parts); cls_row lists every
+  // class (inside a class's part and slab with XCD parts); cls_row lists every
   // system's class starts (global rows) followed by its end, cls_base[s]
   // where system s's list begins
   c->ncol = ncol;
@@ -185,9 +188,14 @@ void plan_colour_order(Ctx* c, const std::vector<int32_t>& col, const int32_t* s
       c->nparts = np;
       c->part_start.assign(sub.size(), 0);
       for (size_t k = 0; k < sub.size(); ++k) c->part_start[k] = r0 + sub[k];
-      std::vector<int32_t> next(sub.begin(), sub.end() - 1);
+      // inside a (class, part) range, the rows slab by slab (time slabs, as
+      // in the synchronous XCD order), caller order inside a slab
+      const int ns = kTimeSlabs;
+      std::vector<int32_t> cell((size_t)nc * np * ns + 1, 0);
+      for (int32_t i = r0; i < r1; ++i) ++cell[((size_t)colour[i] * np + part[i]) * ns + slab[i] + 1];
+      std::partial_sum(cell.begin(), cell.end(), cell.begin());
       for (int32_t i = r0; i < r1; ++i) {
-        const int32_t p = r0 + next[(size_t)colour[i] * np + part[i]]++;
+        const int32_t p = r0 + cell[((size_t)colour[i] * np + part[i]) * ns + slab[i]]++;
         perm_inv[i] = p;
         perm_inv[n + p] = i;
       }

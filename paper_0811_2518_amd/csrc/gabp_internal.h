@@ -418,6 +418,9 @@ gabp_status permute_rows(Ctx* c, const std::vector<int32_t>& perm_inv, bool keep
 // partition.hip: XCD-aware row order (8 slot-balanced parts, part x on XCD x).
 // xcd_parts fills part[caller row] and says whether the parts pay off.
 bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& part);
+// time_slabs cuts every part into kTimeSlabs slabs of equal work (slab[caller row]).
+constexpr int kTimeSlabs = 8;
+std::vector<int32_t> time_slabs(const Ctx* c, const std::vector<int32_t>& col, const std::vector<int32_t>& part);
 bool plan_xcd_order(Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& perm_inv);
 gabp_status apply_xcd_order(Ctx* c);
 

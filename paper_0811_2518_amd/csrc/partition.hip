@@ -10,8 +10,18 @@
 //      propagation: a node moves to the part holding most of its neighbours,
 //      within a 2% balance margin, until a pass moves fewer than 0.1% of
 //      the nodes.
-//   2. The rows are renumbered part by part.
-//   3. The workgroup partition pads every part to the same number of
+//   2. Each part is cut into 8 time slabs of equal work.  Workgroups are
+//      dispatched in order, so at any moment every XCD sweeps rows of about
+//      the same slab; a gather whose neighbour lies in that slab (of any
+//      part) finds a line that the other XCDs' concurrent gathers, or its own
+//      XCD's, have just brought into L2.  The slabs are grown breadth-first
+//      over the whole graph from 8 seeds, a node joining a slab only while
+//      its part's share of that slab has room, then refined by label
+//      propagation on the slab label alone (the part is kept).  On G(n, 4n)
+//      the slabs hold 43% of the edges, as the parts do, and two thirds of
+//      the edges lie inside a part or a slab.
+//   3. The rows are renumbered part by part, slab by slab inside a part.
+//   4. The workgroup partition pads every part to the same number of
 //      workgroups, so the XCD-aware workgroup map sends part x to XCD x.
 // The iteration is unchanged: every row keeps its slots, in order.  Only the
 // numbering differs, and the C ABI restores the caller's order.  The order is
@@ -33,6 +43,8 @@ namespace {
 constexpr int kParts = 8;          // XCDs
 constexpr double kBalance = 0.02;  // allowed deviation of a part's work from the mean
 constexpr int kRefine = 8;         // label-propagation passes
+constexpr int kSlabs = kTimeSlabs;  // time slabs per part
+constexpr int kSlabRefine = 2;     // label-propagation passes on the slabs
 constexpr int64_t kMinSlots = 4096;
 // required rise of the fraction of edges inside the parts: measured, parts
 // holding 43% of G(n, 4n)'s edges (31 points above 8 ranges of the caller's
@@ -161,19 +173,125 @@ bool xcd_parts(const Ctx* c, const std::vector<int32_t>& col, std::vector<int32_
   return inside_fraction(op, col, part) >= inside_fraction(op, col, natural) + kMinGain;
 }
 
+// 2. time slabs inside the parts (part[] is kept); returns the slab of every node
+std::vector<int32_t> time_slabs(const Ctx* c, const std::vector<int32_t>& col, const std::vector<int32_t>& part) {
+  const int32_t n = c->n;
+  const std::vector<int32_t>& op = c->off_ptr_h;
+  // what the growth reads of a neighbour, in one record: one cache miss per
+  // visited slot instead of three
+  struct Node {
+    int32_t part, w, slab, pad;
+  };
+  std::vector<Node> nd(n);
+  std::vector<int64_t> ptot(kParts, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t d = op[i + 1] - op[i];
+    nd[i] = Node{part[i], (int32_t)((d > kLongRow ? 0 : d) + 1), -1, 0};
+    ptot[part[i]] += nd[i].w;
+  }
+  // a slab's share of part p: its work may reach cap[p] while growing, and
+  // stays within the balance margin around it under refinement
+  std::vector<int64_t> cap(kParts);
+  for (int p = 0; p < kParts; ++p) cap[p] = ptot[p] / kSlabs + 1;
+  std::vector<int64_t> load((size_t)kParts * kSlabs, 0);
+  auto fits = [&](const Node& v, int s) { return load[(size_t)v.part * kSlabs + s] + v.w <= cap[v.part]; };
+  // one queue per slab (a vector and its read position); a node enters one queue once
+  std::vector<std::vector<int32_t>> fifo(kSlabs);
+  int32_t assigned = 0;
+  auto take = [&](int32_t v, int s) {
+    nd[v].slab = s;
+    load[(size_t)nd[v].part * kSlabs + s] += nd[v].w;
+    ++assigned;
+    fifo[s].push_back(v);
+  };
+  std::vector<size_t> head(kSlabs, 0);
+  // seeds between the parts' seeds of the caller's order
+  for (int s = 0; s < kSlabs; ++s) {
+    const int32_t v = (int32_t)(((int64_t)2 * s + 1) * n / (2 * kSlabs));
+    if (nd[v].slab < 0) take(v, s);
+  }
+  // restart points: a node that a slab skips here never fits it later, since
+  // the loads only grow while the slabs grow
+  std::vector<int32_t> scan(kSlabs, 0);
+  while (assigned < n) {
+    bool grew = false;
+    for (int s = 0; s < kSlabs; ++s) {
+      if (head[s] == fifo[s].size()) continue;
+      const int32_t v = fifo[s][head[s]++];
+      grew = true;
+      for (int32_t e = op[v]; e < op[v + 1]; ++e) {
+        const int32_t u = col[e];
+        if (nd[u].slab < 0 && fits(nd[u], s)) take(u, s);
+      }
+    }
+    if (grew) continue;
+    // every queue ran dry: restart each slab at the lowest node it can take
+    bool seeded = false;
+    for (int s = 0; s < kSlabs; ++s) {
+      int32_t& v = scan[s];
+      while (v < n && (nd[v].slab >= 0 || !fits(nd[v], s))) ++v;
+      if (v < n) {
+        take(v, s);
+        seeded = true;
+      }
+    }
+    if (!seeded) break;
+  }
+  std::vector<int32_t> slab(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (nd[i].slab < 0) {  // whatever is left goes to its part's lightest slab
+      const int64_t* L = &load[(size_t)nd[i].part * kSlabs];
+      int best = 0;
+      for (int s = 1; s < kSlabs; ++s)
+        if (L[s] < L[best]) best = s;
+      nd[i].slab = best;
+      load[(size_t)nd[i].part * kSlabs + best] += nd[i].w;
+    }
+    slab[i] = nd[i].slab;
+  }
+  // label propagation on the slab label; two passes take nearly all the gain
+  for (int it = 0; it < kSlabRefine; ++it) {
+    int64_t moved = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      int cnt[kSlabs] = {0};
+      for (int32_t e = op[v]; e < op[v + 1]; ++e) ++cnt[slab[col[e]]];
+      const int cur = slab[v];
+      int best = cur;
+      for (int s = 0; s < kSlabs; ++s)
+        if (cnt[s] > cnt[best]) best = s;
+      int64_t* L = &load[(size_t)nd[v].part * kSlabs];
+      const double cp = (double)cap[nd[v].part];
+      if (best != cur && (double)(L[best] + nd[v].w) <= (1.0 + kBalance) * cp &&
+          (double)(L[cur] - nd[v].w) >= (1.0 - kBalance) * cp) {
+        slab[v] = best;
+        L[best] += nd[v].w;
+        L[cur] -= nd[v].w;
+        ++moved;
+      }
+    }
+    if (moved * 1000 < n) break;
+  }
+  return slab;
+}
+
 bool plan_xcd_order(Ctx* c, const std::vector<int32_t>& col, std::vector<int32_t>& perm_inv) {
   const int32_t n = c->n;
   std::vector<int32_t> part;
   if (!xcd_parts(c, col, part)) return false;
-  // 3. rows part by part, caller order inside a part
+  const std::vector<int32_t> slab = time_slabs(c, col, part);
+  // 3. rows part by part, slab by slab inside a part, caller order inside a slab
   c->nparts = kParts;
   c->part_start.assign(kParts + 1, 0);
-  for (int32_t i = 0; i < n; ++i) ++c->part_start[part[i] + 1];
-  for (int p = 0; p < kParts; ++p) c->part_start[p + 1] += c->part_start[p];
-  perm_inv.assign(2 * (size_t)n, 0);
-  std::vector<int32_t> next(c->part_start.begin(), c->part_start.end() - 1);
+  std::vector<int32_t> cell((size_t)kParts * kSlabs + 1, 0);
   for (int32_t i = 0; i < n; ++i) {
-    const int32_t p = next[part[i]]++;
+    ++c->part_start[part[i] + 1];
+    ++cell[(size_t)part[i] * kSlabs + slab[i] + 1];
+  }
+  for (int p = 0; p < kParts; ++p) c->part_start[p + 1] += c->part_start[p];
+  for (size_t k = 0; k + 1 < cell.size(); ++k) cell[k + 1] += cell[k];
+  perm_inv.assign(2 * (size_t)n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t p = cell[(size_t)part[i] * kSlabs + slab[i]]++;
     perm_inv[i] = p;
     perm_inv[n + p] = i;
   }

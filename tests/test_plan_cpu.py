@@ -78,6 +78,20 @@ def test_xcd_order_on_a_random_graph(epb, graph):
     weight = np.where(deg > 512, 0, deg) + 1.0
     work = np.bincount(owner[plan["perm"]], weights=weight, minlength=8)
     assert work.max() <= 1.05 * work.mean()
+    # time slabs: a row's slab is the eighth of its part's workgroups it sits
+    # in (workgroups run in order, so all XCDs sweep about the same slab at
+    # once); far more edges than the 1/8 of a random order join rows of one
+    # slab, and together with the parts they cover most of the edges
+    nb = plan["num_blocks"]
+    q = nb // XCDS
+    br = plan["blk_row"]
+    tslab = np.empty(p.n, np.int64)
+    for w in range(nb):
+        tslab[br[w]:br[w + 1]] = (w % q) * 8 // q
+    same_slab = np.mean(tslab[r] == tslab[c])
+    either = np.mean((owner[r] == owner[c]) | (tslab[r] == tslab[c]))
+    assert same_slab >= 0.25, same_slab
+    assert either >= inside + 0.12, (either, inside)
     # without the XCD order: the caller's rows, no padding
     nat = binding.plan_rows(p.row_ptr, p.col, edges_per_block=epb, natural_order=True)
     assert nat["xcd_parts"] == 0 and np.array_equal(nat["perm"], np.arange(p.n))
@@ -102,8 +116,8 @@ def test_serial_plan_colouring_is_the_oracles(name):
     np.testing.assert_array_equal(plan["colour"], ref)
     assert plan["num_colours"] == int(ref.max()) + 1
     blocks_ok(p, plan, 512)
-    # classes are contiguous internal ranges in colour order, caller order
-    # inside a class (inside a class's XCD part when there are parts)
+    # classes are contiguous internal ranges in colour order (with XCD parts,
+    # split by part, each part's rows slab by slab)
     col_int = np.empty(p.n, np.int64)
     col_int[plan["perm"]] = ref
     assert np.all(np.diff(col_int) >= 0)
