@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "gabp_internal.h"
 
@@ -277,6 +278,15 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A value every lane of the workgroup holds alike, kept in scalar registers
+// (the lane-per-row kernel runs at the VGPR limit of a 1024-lane workgroup).
+__device__ __forceinline__ double uni_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <int KR>
 __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
   extern __shared__ __align__(16) double sm[];
@@ -327,23 +337,45 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
   } else {
     bnorm = sqrt(small_sum(own ? br * br : 0.0, s_red + kSB / 64));
   }
+  bnorm = uni_d(bnorm);
   __syncthreads();
 
   const bool exact = !(A.tol > 0.0);
   const int M = A.max_iter;
   const int ce = max(1, A.check_every);
   auto in_set = [&](int j) { return j == M || (j % ce) == 0; };
-  double last_rel = -1.0, prev_rel = -1.0;
+  // relative residual of a checked round from its sum of squares, formed as
+  // the multi-launch finish forms it
+  auto rel_of = [&](double tot) {
+    const double rn = sqrt(tot);
+    return bnorm > 0.0 ? rn / bnorm : rn;
+  };
+  // the stop test needs that relative residual only near a threshold: a sum
+  // of squares clearly above (tol |b|)^2 cannot pass, one clearly below
+  // (1e8 |b|)^2 cannot diverge (margins far above the rounding of sqrt and
+  // the division); the decisions are the exact ones
+  const double scale = bnorm > 0.0 ? bnorm : 1.0;
+  double conv_pre = A.tol >= 0.0 ? (A.tol * scale) * (A.tol * scale) * (1.0 + 1e-6) : -1.0;
+  if (A.tol > 0.0 && !(conv_pre > 1e-280 && conv_pre < 1e280)) conv_pre = INFINITY;  // out of range: always exact
+  conv_pre = uni_d(conv_pre);
+  const double div_pre = uni_d((kDivergeLimit * scale) * (kDivergeLimit * scale) * (1.0 - 1e-6));
+  double last_tot = 0.0, prev_tot = 0.0;
   int last_round = -1, prev_round = -1, conv = -1, err = 0;
   int T = 0;  // the last round whose aggregates were formed
-  for (int t = 1; t <= M + 1; ++t) {
+  // One sweep.  Rows of at most 4 slots take the parity of t as a
+  // compile-time constant (std::true_type / std::false_type), so the message
+  // registers of the two parities need no selects or moves; rows of up to 6
+  // slots take it at run time, which keeps the code within the register
+  // budget.  Returns true when the solve ends.
+  auto sweep = [&](auto odd_c, const int t) -> bool {
+    const bool ODD = odd_c;
+    if (t > M + 1) return true;  // sweeps 1..M, then the check of round M
     const bool upd = t <= M;
     const bool ck = exact ? (t == M + 1) : in_set(t - 1);
-    if (!upd && !ck) break;
+    if (!upd && !ck) return true;
     const bool ck_next = upd && (exact ? (t == M) : in_set(t));  // sweep t+1 checks round t
-    const int p1 = (t - 1) & 1, pn = t & 1;  // parities of rounds t-1 (read) and t (written)
-    const bool first = t == 1;
-    const bool odd = (t & 1) != 0;
+    const int p1 = ODD ? 0 : 1, pn = ODD ? 1 : 0;  // parities of rounds t-1 (read) and t (written)
+    const bool first = ODD && t == 1;
     bool bad = false;
     double P = dr, h = br, acc = 0.0;
     if (ck) acc = br - dr * gX[p1 * n + tid];  // the row's residual in round t-1
@@ -357,16 +389,15 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
         if (upd) {
           // in^(t) = F(A_c^(t-1), out^(t-1)), out^(t-1) = F(A_own^(t-2), in^(t-2))
           double Pout = 0.0, hout = 0.0;
-          if (!first) {
-            const double mp = odd ? mP1[k] : mP0[k], mh = odd ? mH1[k] : mH0[k];
-            const double inv_out = 1.0 / (o2P - mp);
+          if (!first) {  // in^(t-2) has the parity of t
+            const double inv_out = 1.0 / (o2P - (ODD ? mP1[k] : mP0[k]));
             Pout = -av * av * inv_out;
-            hout = -av * (o2h - mh) * inv_out;
+            hout = -av * (o2h - (ODD ? mH1[k] : mH0[k])) * inv_out;
           }
           const double inv_in = 1.0 / (gPc - Pout);
           const double Pn = -av * av * inv_in;
           const double hn = -av * (gHc - hout) * inv_in;
-          if (odd) {
+          if (ODD) {
             mP1[k] = Pn;
             mH1[k] = hn;
           } else {
@@ -384,7 +415,7 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
       gH[pn * n + tid] = h;
       if (ck_next) gX[pn * n + tid] = h / P;
     }
-    double* red = s_red + (t & 1) * (kSB / 64);
+    double* red = s_red + pn * (kSB / 64);
     if (ck) {
       const double v = wsum(own ? acc * acc : 0.0);
       if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -404,22 +435,32 @@ __global__ __launch_bounds__(kSB) void k_small_rows(SmallArgs A) {
     }
     if (any_bad) {  // as the multi-launch path: the error ends the solve
       err |= kErrNonfinite;
-      break;
+      return true;
     }
     if (ck) {
       double tot = 0.0;
       for (int w = 0; w < kSB / 64; ++w) tot += red[w];
-      const double rn = sqrt(tot);
-      const double rel = bnorm > 0.0 ? rn / bnorm : rn;
-      prev_rel = last_rel;
+      tot = uni_d(tot);
+      prev_tot = last_tot;
       prev_round = last_round;
-      last_rel = rel;
+      last_tot = tot;
       last_round = t - 1;
-      if (rel <= A.tol) conv = t - 1;
-      else if (!(rel <= kDivergeLimit)) err |= kErrDiverged;
+      if (tot <= conv_pre && rel_of(tot) <= A.tol) conv = t - 1;
+      else if (!(tot < div_pre) && !(rel_of(tot) <= kDivergeLimit)) err |= kErrDiverged;
     }
-    if (conv >= 0 || err) break;
+    return conv >= 0 || err != 0;
+  };
+  if constexpr (KR <= 4) {
+    for (int t = 1;; t += 2) {
+      if (sweep(std::true_type{}, t)) break;
+      if (sweep(std::false_type{}, t + 1)) break;
+    }
+  } else {
+    for (int t = 1;; ++t)
+      if (sweep((t & 1) != 0, t)) break;
   }
+  const double last_rel = last_round >= 0 ? rel_of(last_tot) : -1.0;
+  const double prev_rel = prev_round >= 0 ? rel_of(prev_tot) : -1.0;
 
   // ---- results: the returned round and the state it leaves -----------------
   const int ret = conv >= 0 ? conv : M;
