@@ -111,8 +111,9 @@ def compact_layout_bytes(n, E, elt):
     slot column 4 + A_ij elt + the incoming message read and written 4 elt +
     the gathered neighbour aggregate 2 elt; per node row pointer 4 + A_ii, b_i
     + own aggregates of the two previous rounds read and the new one written
-    6 elt + x written elt."""
-    return (4 + 7 * elt) * E + (4 + 9 * elt) * n
+    6 elt.  (A solve to a tolerance writes no means in its sweeps: x of the
+    returned round is formed once at the end from its aggregate record.)"""
+    return (4 + 7 * elt) * E + (4 + 8 * elt) * n
 
 
 def serial_layout_bytes(n, E, elt):

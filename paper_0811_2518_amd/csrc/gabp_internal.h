@@ -439,6 +439,12 @@ hipError_t launch_norm(const double* v, int64_t n, double* partials, int nparts,
 hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, const DevStatus* st,
                              int32_t fallback_round, double* x, double* var, int32_t n,
                              hipStream_t s);
+// x of the returned round (the converged one, else fallback_round) of a
+// compact run from its aggregate record, as the sweep forms it: h~ / P~, or
+// h~ * (1 / P~) with frozen precisions.  agg: the three rotating FP64
+// aggregate buffers, [n] {P~ or 1 / P~, h~} each.
+hipError_t launch_x_from_agg(void* const* agg, bool honly, const DevStatus* st, int32_t fallback_round, double* x,
+                             int32_t n, hipStream_t s);
 // outer correction step: x_new = x_old + d (d from the inner solve, FP32 or FP64
 // selected on the device by the inner status), r = b - A x_new in FP64, r_in =
 // r in the inner precision, ||r|| and the check against tol.

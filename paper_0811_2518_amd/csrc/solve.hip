@@ -40,6 +40,10 @@ struct RunCfg {
   // after each, the extrapolated means replace those of the cycle's last
   // round and start the next cycle; only cycle ends are checked
   double* stf_start = nullptr;        // [n] nullable: no restarts
+  // compact layout with a tolerance: the sweeps write no means; the caller
+  // forms x of the returned round from that round's aggregate record, which
+  // the three rotating buffers still hold when the run ends
+  bool x_at_end = false;
 };
 
 template <typename T>
@@ -384,11 +388,11 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       k.agg2 = c->agg_d[(t + 1) % 3];  // round t-2
       k.anew = c->agg_d[t % 3];
       if (mode != kResid) {
-        const bool wx = ait || stf || (exact ? t == M : in_set(t));
+        const bool wx = ait || stf || (exact ? t == M : (in_set(t) && !cfg.x_at_end));
         k.xout = wx ? (T*)cfg.x2[t & 1] : nullptr;
         k.ptout = (wx && cfg.pt2[0]) ? (T*)cfg.pt2[t & 1] : nullptr;
       }
-      if (t == 1 && (ait || stf || (exact ? M == 0 : in_set(0)))) {
+      if (t == 1 && (ait || stf || (exact ? M == 0 : (in_set(0) && !cfg.x_at_end)))) {
         k.xout_prev = stf ? (T*)cfg.stf_start : (T*)cfg.x2[0];  // Steffensen: round 0 starts cycle 1
         k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
       }
@@ -761,12 +765,18 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   // the one-launch path forms ||b|| itself and writes x and the variances of
   // the returned round directly
   const bool small = use_small(c, cfg);
+  // compact sweeps to a tolerance leave x to the end (8 B per node and sweep
+  // fewer), unless the variances of every round are kept too
+  cfg.x_at_end = !small && c->layout == kLayoutCompact && !exact && !ait && !stf && !cfg.pt2[0];
   if (!small) GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
   gabp_status rs = small ? run_small(c, cfg, x, var) : run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
   const double* xs[2] = {c->x64_d[0], c->x64_d[1]};
   const double* ps[2] = {c->pt64_d[0], c->pt64_d[1]};
-  if (!small) GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
+  if (cfg.x_at_end)
+    GABP_HIP(c, launch_x_from_agg(c->agg_d, honly, c->st_d, max_iter, x, c->n, s));
+  else if (!small)
+    GABP_HIP(c, launch_copy_round(xs, ps, c->st_d, max_iter, x, honly ? nullptr : var, c->n, s));
   if (ait) GABP_HIP(c, hipMemcpyAsync(x, c->ait_y_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   if (var && honly) GABP_HIP(c, hipMemcpyAsync(var, c->inv_pt_d, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
   DevStatus st;

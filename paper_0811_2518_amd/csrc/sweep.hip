@@ -88,19 +88,21 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
   __shared__ double s_red[kFinishBlock / 64];
   if (gate_on_done && st->done) return;
   // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
-  // v1, each in increasing j.  Sixteen loads are issued before their
-  // additions (one L2 round trip per sixteen, not per two); a missing element
+  // v1, each in increasing j.  Thirty-two loads are issued before their
+  // additions, so up to 32768 partials (16,384 workgroups at 512 slots on
+  // the 2^20-node graphs) cost one round trip to memory; a missing element
   // counts as +0.0, which leaves a sum of squares bit for bit unchanged.
+  constexpr int kAhead = 32;
   double v0 = 0.0, v1 = 0.0;
-  for (int j0 = 0; j0 * kFinishBlock < nblk; j0 += 16) {
-    double p[16];
+  for (int j0 = 0; j0 * kFinishBlock < nblk; j0 += kAhead) {
+    double p[kAhead];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kAhead; ++u) {
       const int i = threadIdx.x + (j0 + u) * kFinishBlock;
       p[u] = i < nblk ? partials[i] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 16; u += 2) {
+    for (int u = 0; u < kAhead; u += 2) {
       v0 += p[u];
       v1 += p[u + 1];
     }
@@ -614,6 +616,25 @@ hipError_t launch_copy_round(const double* const* x2, const double* const* pt2, 
   const int blocks = std::min((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_copy_round, dim3(blocks), dim3(256), 0, s, x2[0], x2[1], pt2 ? pt2[0] : nullptr,
                      pt2 ? pt2[1] : nullptr, st, fallback_round, x, var, n);
+  return hipGetLastError();
+}
+
+__global__ void k_x_from_agg(const double2* a0, const double2* a1, const double2* a2, int32_t honly,
+                             const DevStatus* st, int32_t fallback, double* x, int32_t n) {
+  const int round = st->conv_round >= 0 ? st->conv_round : fallback;
+  const double2* a = (round % 3 == 0) ? a0 : (round % 3 == 1) ? a1 : a2;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double2 v = a[i];
+    x[i] = honly ? v.y * v.x : v.y / v.x;
+  }
+}
+
+hipError_t launch_x_from_agg(void* const* agg, bool honly, const DevStatus* st, int32_t fallback_round, double* x,
+                             int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = std::min((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_x_from_agg, dim3(blocks), dim3(256), 0, s, (const double2*)agg[0], (const double2*)agg[1],
+                     (const double2*)agg[2], honly ? 1 : 0, st, fallback_round, x, n);
   return hipGetLastError();
 }
 

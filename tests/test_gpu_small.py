@@ -113,12 +113,15 @@ def test_reuse_and_adjoint_follow_the_same_state():
     assert same(ga, gb) and same(gva, gvb)
 
 
-def test_caps_and_statuses_match():
-    """max_iter caps, M = 0 with a tolerance, and an unreachable tolerance."""
-    p = workloads.config1()
-    one, multi = pair(p, reuse_precision=False)
+@pytest.mark.parametrize("name", ["grid32", "grid3d_10"])  # rows of at most 4 and of 6 slots
+@pytest.mark.parametrize("check_every", [1, 3])
+def test_caps_and_statuses_match(name, check_every):
+    """max_iter caps, M = 0 with a tolerance, and an unreachable tolerance: the
+    one-launch loop must end after sweep M and the check of round M."""
+    p = CASES[name]()
+    one, multi = pair(p, reuse_precision=False, check_every=check_every)
     b = dev(p.b)
-    for tol, M in ((1e-10, 0), (1e-10, 1), (1e-10, 10), (1e-300, 40), (0.5, 5)):
+    for tol, M in ((1e-10, 0), (1e-10, 1), (1e-10, 10), (1e-300, 40), (1e-300, 41), (0.5, 5)):
         x1, i1 = one.solve(b, tol=tol, max_iter=M, check=False)
         x2, i2 = multi.solve(b, tol=tol, max_iter=M, check=False)
         assert (i1["status"], i1["sweeps"], i1["converged"]) == (i2["status"], i2["sweeps"], i2["converged"]), (tol, M)
