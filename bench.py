@@ -58,13 +58,14 @@ def sweep_bytes(n, E, elt, check=True, honly=False):
 
 
 def source_hash(src="compact.hip"):
-    """Hash of one kernel's source file, the shared internal header and the
-    row-order sources (XCD parts, time slabs, colour classes), with comments
-    and whitespace removed: traffic counters are valid for this code and this
-    row order only."""
+    """Hash of one kernel's source file, the shared internal header, the
+    launch code (which buffers a sweep reads and writes) and the row-order
+    sources (XCD parts, time slabs, colour classes), with comments and
+    whitespace removed: traffic counters are valid for this code and this row
+    order only."""
     import re
     h = hashlib.sha256()
-    for f in (src, "gabp_internal.h", "partition.hip", "colour.hip"):
+    for f in (src, "gabp_internal.h", "solve.hip", "partition.hip", "colour.hip"):
         with open(os.path.join(ROOT, "paper_0811_2518_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
