@@ -12,14 +12,16 @@
 //      the nodes.
 //   2. Each part is cut into 8 time slabs of equal work.  Workgroups are
 //      dispatched in order, so at any moment every XCD sweeps rows of about
-//      the same slab; a gather whose neighbour lies in that slab (of any
-//      part) finds a line that the other XCDs' concurrent gathers, or its own
-//      XCD's, have just brought into L2.  The slabs are grown breadth-first
-//      over the whole graph from 8 seeds, a node joining a slab only while
-//      its part's share of that slab has room, then refined by label
-//      propagation on the slab label alone (the part is kept).  On G(n, 4n)
-//      the slabs hold 43% of the edges, as the parts do, and two thirds of
-//      the edges lie inside a part or a slab.
+//      the same slab, and the aggregates of that slab (of all parts, an
+//      eighth of the array) are what its gathers mostly touch: a gather whose
+//      neighbour lies in the current slab is likely to find the line in its
+//      XCD's L2, brought there by a recent gather of the same XCD, as is one
+//      whose neighbour lies in the XCD's own part.  The slabs are grown
+//      breadth-first over the whole graph from 8 seeds, a node joining a slab
+//      only while its part's share of that slab has room, then refined by
+//      two passes of label propagation on the slab label alone (the part is
+//      kept).  On G(n, 4n) the slabs hold 43% of the edges, as the parts do,
+//      and two thirds of the edges lie inside a part or a slab.
 //   3. The rows are renumbered part by part, slab by slab inside a part.
 //   4. The workgroup partition pads every part to the same number of
 //      workgroups, so the XCD-aware workgroup map sends part x to XCD x.
