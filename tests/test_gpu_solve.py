@@ -251,6 +251,27 @@ def test_iteration_cap_reports_not_converged(layout):
     assert rel(x, ref["x"]) <= 1e-14
 
 
+@pytest.mark.parametrize("multi", [False, True])
+@pytest.mark.parametrize("reuse", [False, True])
+def test_capped_solve_returns_the_last_round(multi, reuse):
+    """A solve to a tolerance that stops at max_iter returns x of round
+    max_iter.  The compact sweeps of such a solve write no means; x is formed
+    at the end from the aggregate record of the returned round (also after a
+    converged solve, and on frozen precisions with the reuse flag)."""
+    p = workloads.er_problem(3001, 8, 77, ratio=1.1) if not multi else workloads.config1()
+    s = solver(p, layout="compact", multi_launch=multi, reuse_precision=reuse)
+    for T in (1, 2, 3, 7):
+        ref = oracle_T(p, T)
+        x, info = s.solve(dev(p.b), tol=1e-14, max_iter=T)
+        assert info["status"] == binding.NOT_CONVERGED and info["sweeps"] == T, (T, info)
+        assert rel(x, ref["x"]) <= 1e-13, T
+    ref = oracle.dense_solve(p.dense(), p.b)
+    for _ in range(2):  # the second solve runs on frozen precisions with the reuse flag
+        x, info = s.solve(dev(p.b), tol=1e-12, max_iter=2000)
+        assert info["converged"] == 1
+        assert rel(x, ref) <= 1e-10
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_non_walk_summable_diverges_without_loading(layout):
     p = workloads.config5(n=2000, rows=4000)
