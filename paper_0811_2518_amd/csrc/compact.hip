@@ -483,9 +483,11 @@ __global__ void k_cnode_out(int32_t n, const int32_t* __restrict__ off_ptr, cons
 
 // The prior of every node as the aggregate record of round 0: (A_ii, b_i), or
 // (1 / P~_i, b_i) with frozen precisions.  Gathered like any later round.
+// With rst, the run's status is reset here too (one launch fewer).
 template <typename T>
 __global__ void k_cnode_prior(int32_t n, const T* __restrict__ first, const T* __restrict__ rhs,
-                              vec2<T>* __restrict__ out) {
+                              vec2<T>* __restrict__ out, DevStatus* rst) {
+  if (rst && blockIdx.x == 0 && threadIdx.x == 0) reset_status_dev(rst);
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     vec2<T> v;
     v.x = first[r];
@@ -499,14 +501,15 @@ __global__ void k_cnode_prior(int32_t n, const T* __restrict__ first, const T* _
 size_t cnode_lds_bytes(int K, int elt) { return cn_lds(K, elt, true); }
 
 template <typename T>
-hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s, DevStatus* reset) {
+  if (n <= 0) return reset ? launch_reset_status(reset, 1, s) : hipSuccess;
   const int blocks = std::min((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_cnode_prior<T>, dim3(blocks), dim3(256), 0, s, n, first, rhs, (vec2<T>*)out);
+  hipLaunchKernelGGL(k_cnode_prior<T>, dim3(blocks), dim3(256), 0, s, n, first, rhs, (vec2<T>*)out, reset);
   return hipGetLastError();
 }
-template hipError_t launch_cnode_prior<double>(int32_t, const double*, const double*, void*, hipStream_t);
-template hipError_t launch_cnode_prior<float>(int32_t, const float*, const float*, void*, hipStream_t);
+template hipError_t launch_cnode_prior<double>(int32_t, const double*, const double*, void*, hipStream_t,
+                                               DevStatus*);
+template hipError_t launch_cnode_prior<float>(int32_t, const float*, const float*, void*, hipStream_t, DevStatus*);
 
 template <typename T>
 hipError_t launch_cnode(int mode, int K, const CnodeArgs<T>& a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {

@@ -30,6 +30,19 @@ struct DevStatus {
   int32_t prev_round;  // round of prev_rel (-1: none)
   int32_t pad2;
 };
+// The status of a solve that has not begun: no round checked, nothing done.
+__device__ __forceinline__ void reset_status_dev(DevStatus* st) {
+  st->done = 0;
+  st->conv_round = -1;
+  st->error = 0;
+  st->ticket = 0;
+  st->last_rel = -1.0;
+  st->last_round = -1;
+  st->pad = 0;
+  st->prev_rel = -1.0;
+  st->prev_round = -1;
+  st->pad2 = 0;
+}
 constexpr int32_t kErrNonfinite = 1;
 constexpr int32_t kErrDiverged = 2;
 
@@ -459,6 +472,12 @@ struct OuterArgs {
   double* xnew;
   const float* d32[2];    // inner iterates (FP32) by round parity
   const double* d64[2];   // inner iterates (FP64) by round parity
+  // or, when dagg_elt is 4 (FP32) or 8 (FP64): the inner compact run's
+  // aggregate records by round mod 3, {P~, h~} (d = h~ / P~) or with frozen
+  // precisions {1 / P~, h~} (d = h~ * (1 / P~)), as the sweep forms means
+  const void* dagg[3];
+  int32_t dagg_elt;
+  int32_t dagg_honly;
   const DevStatus* st_in; // selects the inner round
   int32_t in_fallback;    // inner round when the inner solve did not converge
   int32_t use_d;          // 0: no correction (x_new = x_old)
@@ -472,6 +491,7 @@ struct OuterArgs {
   int32_t nblk;
   int32_t n;
   const DevStatus* gate;  // nullable: the launch returns at once once gate->done is set
+  int32_t reset_st;       // launch_outer: the first kernel resets *st before the step's finish
 };
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s);
@@ -506,7 +526,8 @@ hipError_t launch_cnode_out(int32_t n, const int32_t* off_ptr, const double* a, 
                             const void* agg_prev, bool zero_in, double* P, double* h, hipStream_t s);
 size_t cnode_lds_bytes(int K, int elt);
 template <typename T>
-hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s);
+hipError_t launch_cnode_prior(int32_t n, const T* first, const T* rhs, void* out, hipStream_t s,
+                              DevStatus* reset = nullptr);
 template <typename T>
 hipError_t launch_serial(const SerialArgs<T>& a, int K, bool resid, hipStream_t s);
 template <typename T>

@@ -357,11 +357,11 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   a.damp = (T)cfg.damp;
   a.chk_diag = (const T*)cfg.chk_diag;
   const double tol = exact ? -1.0 : cfg.tol;
-  GABP_HIP(c, launch_reset_status(cfg.st, 1, s));
 
-  // round 0: the prior as aggregate record, (A_ii, b_i) or (1 / P~_i, b_i)
+  // round 0: the prior as aggregate record, (A_ii, b_i) or (1 / P~_i, b_i);
+  // the same launch resets the run's status
   GABP_HIP(c, launch_cnode_prior<T>(c->n, cfg.honly ? (const T*)c->inv_pt_d : (const T*)cfg.diag,
-                                    (const T*)cfg.rhs, c->agg_d[0], s));
+                                    (const T*)cfg.rhs, c->agg_d[0], s, cfg.st));
   const int main_mode = cfg.honly ? kHOnly : kJoint;
   // test aid: stale buffers filled with NaN around every sweep
   const bool poison = (c->opts.flags & GABP_FLAG_POISON_STALE) && c->E > 0;
@@ -896,7 +896,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
   o.tol = tol;
   o.nblk = c->nblk;
   o.n = c->n;
-  GABP_HIP(c, launch_reset_status(st_out, 1, s));
+  o.reset_st = 1;  // each outer launch resets the outer status first
   GABP_HIP(c, launch_outer(c->K, o, s));
   DevStatus so, si;
   gabp_status r = read_status(c, st_out, &so);
@@ -931,6 +931,9 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     cfg.x2[0] = fp32 ? (void*)c->x32_d[0] : (void*)c->x64_d[0];
     cfg.x2[1] = fp32 ? (void*)c->x32_d[1] : (void*)c->x64_d[1];
     cfg.st = st_in;
+    // compact inner solves write no means; the outer step forms d from the
+    // returned round's aggregate record (the single loop keeps them)
+    cfg.x_at_end = !single && c->layout == kLayoutCompact;
     r = fp32 ? run_sweeps<float>(c, cfg) : run_sweeps<double>(c, cfg);
     if (r != GABP_OK) return r;
     if (c->run_seen_final && c->tev_used == 0) {  // the poller already waited for the final status
@@ -963,7 +966,9 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     o.xnew = c->xo_d[cur ^ 1];
     o.use_d = 1;
     o.in_fallback = budget;
-    GABP_HIP(c, launch_reset_status(st_out, 1, s));
+    for (int q = 0; q < 3; ++q) o.dagg[q] = c->agg_d[q];
+    o.dagg_elt = cfg.x_at_end ? (fp32 ? 4 : 8) : 0;
+    o.dagg_honly = cfg.honly ? 1 : 0;
     GABP_HIP(c, launch_outer(c->K, o, s));
     cur ^= 1;
     ++k;

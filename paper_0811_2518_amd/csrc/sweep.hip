@@ -414,13 +414,25 @@ template hipError_t launch_sweep<float>(int, int, const SweepArgs<float>&, hipSt
 // x_new = x_old + d, the correction d taken from the inner solve's round that
 // met the inner tolerance (chosen on the device by the inner status).
 __global__ void k_update(OuterArgs A) {
+  if (A.reset_st && blockIdx.x == 0 && threadIdx.x == 0) reset_status_dev(A.st);
   const DevStatus* si = A.st_in;
   const int round = (si && si->conv_round >= 0) ? si->conv_round : A.in_fallback;
   const float* d32 = A.d32[round & 1];
   const double* d64 = A.d64[round & 1];
+  const void* agg = A.dagg[round % 3];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
     double v = A.xold ? A.xold[i] : 0.0;
-    if (A.use_d) v += d64 ? d64[i] : (double)d32[i];
+    if (A.use_d) {
+      if (A.dagg_elt == 4) {
+        const float2 g = ((const float2*)agg)[i];
+        v += (double)(A.dagg_honly ? g.y * g.x : g.y / g.x);
+      } else if (A.dagg_elt == 8) {
+        const double2 g = ((const double2*)agg)[i];
+        v += A.dagg_honly ? g.y * g.x : g.y / g.x;
+      } else {
+        v += d64 ? d64[i] : (double)d32[i];
+      }
+    }
     A.xnew[i] = v;
   }
 }
@@ -477,6 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
 // the residual norm is that of k_outer bit for bit.
 __global__ __launch_bounds__(kBlock) void k_outer_zero(OuterArgs A) {
   __shared__ double s_red[kBlock / 64];
+  if (A.reset_st && blockIdx.x == 0 && threadIdx.x == 0) reset_status_dev(A.st);
   const int b = xcd_remap(blockIdx.x, A.nblk);
   const int r0 = A.blk_row[b], r1 = A.blk_row[b + 1];
   double res2 = 0.0;
@@ -492,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_zero(OuterArgs A) {
 }
 
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
-  if (a.nblk <= 0) return hipSuccess;
+  if (a.nblk <= 0) return a.reset_st ? launch_reset_status(a.st, 1, s) : hipSuccess;
   hipError_t e;
   if (!a.xold && !a.use_d) {
     hipLaunchKernelGGL(k_outer_zero, dim3(a.nblk), dim3(kBlock), 0, s, a);
@@ -525,18 +538,7 @@ hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s) {
 
 __global__ void k_reset_status(DevStatus* st, int count) {
   const int i = threadIdx.x;
-  if (i < count) {
-    st[i].done = 0;
-    st[i].conv_round = -1;
-    st[i].error = 0;
-    st[i].ticket = 0;
-    st[i].last_rel = -1.0;
-    st[i].last_round = -1;
-    st[i].pad = 0;
-    st[i].prev_rel = -1.0;
-    st[i].prev_round = -1;
-    st[i].pad2 = 0;
-  }
+  if (i < count) reset_status_dev(st + i);
 }
 
 hipError_t launch_reset_status(DevStatus* st, int count, hipStream_t s) {
