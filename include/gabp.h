@@ -187,6 +187,17 @@ typedef struct {
  * and a save buffer of one slot-state half kept by the handle. */
 #define GABP_FLAG_POISON_STALE 128
 
+/* Test aid for the compact layout (implies one launch per sweep).  A solve to
+ * a tolerance ends with the sweep that carries the check of the returned
+ * round; when the residuals so far predict that round t-1 meets the
+ * tolerance, launch t is instead the residual-only check of round t-1, and
+ * sweep t (without that check) follows only if the check fails.  With this flag every checked launch from round 2
+ * on is made that way, so both outcomes run constantly; the rounds, the
+ * checks and the results are the same bits as without the flag.  Runs that a
+ * freeze of the precisions follows (GABP_FLAG_REUSE_PRECISION, loading), and
+ * Aitken's, Steffensen's and the single-loop runs, never take that form. */
+#define GABP_FLAG_PREDICT_ALL 256
+
 typedef struct {
   int32_t sweeps;        /* message sweeps run (inner sweeps summed over outer steps) */
   int32_t outer_iters;   /* outer steps (0 for the plain FP64 iteration)              */

@@ -30,6 +30,7 @@ FLAG_AITKEN = 16
 FLAG_MULTI_LAUNCH = 32
 FLAG_STEFFENSEN = 64
 FLAG_POISON_STALE = 128
+FLAG_PREDICT_ALL = 256
 LAYOUTS = {"auto": 0, "edge": 1, "node": 2, "compact": 3, "serial": 4}
 
 # every entry point declared in include/gabp.h
@@ -231,6 +232,7 @@ class Solver:
                  gamma=0.0, loading_delta=0.05, inner_tol=1e-5, inner_max_iter=10000, max_outer=1000,
                  reuse_precision=True, time_sweeps=False, layout="auto", single_loop=False, damping=0.5,
                  natural_order=False, aitken=False, steffensen=False, multi_launch=False, poison_stale=False,
+                 predict_all=False,
                  device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
@@ -248,7 +250,8 @@ class Solver:
             flags=(FLAG_REUSE_PRECISION if reuse_precision else 0) | (FLAG_TIME_SWEEPS if time_sweeps else 0)
             | (FLAG_SINGLE_LOOP if single_loop else 0) | (FLAG_NATURAL_ORDER if natural_order else 0)
             | (FLAG_AITKEN if aitken else 0) | (FLAG_STEFFENSEN if steffensen else 0)
-            | (FLAG_MULTI_LAUNCH if multi_launch else 0) | (FLAG_POISON_STALE if poison_stale else 0))
+            | (FLAG_MULTI_LAUNCH if multi_launch else 0) | (FLAG_POISON_STALE if poison_stale else 0)
+            | (FLAG_PREDICT_ALL if predict_all else 0))
         h = ctypes.c_void_p()
         st = lib().gabp_create(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val),
                                ctypes.byref(self.opts), sh, ctypes.byref(h))

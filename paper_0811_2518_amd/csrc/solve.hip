@@ -44,6 +44,9 @@ struct RunCfg {
   // forms x of the returned round from that round's aggregate record, which
   // the three rotating buffers still hold when the run ends
   bool x_at_end = false;
+  // the caller freezes the precisions of the last computed round after the
+  // run, so the run must end with the sweep that checks the returned round
+  bool keep_held = false;
 };
 
 template <typename T>
@@ -104,6 +107,11 @@ struct ChunkPlan {
   double rel0 = -1.0, rel1 = -1.0;
   int round0 = -1, round1 = -1;
   int idle = 0;
+  // the round predicted to meet the tolerance with a margin of 10% in the
+  // residual (checking every round), else -1; near convergence the residual
+  // of GaBP falls by a steady factor per round (on G(n, 4n), 0.377 with
+  // extrapolations over eight rounds within 1%)
+  int pass_round = -1;
   int first(int lag, int check_every) {
     chunk = std::min(16, 2 * std::max(1, check_every) + lag);
     return chunk;
@@ -123,7 +131,8 @@ struct ChunkPlan {
       rel1 = p.seen.last_rel;
       round1 = p.seen.last_round;
     }
-    if (tol > 0.0 && round0 >= 0 && rel0 > 0.0 && rel1 > tol && rel1 < rel0) {
+    pass_round = -1;
+    if (tol > 0.0 && round0 >= 0 && round1 > round0 && rel0 > 0.0 && rel1 > tol && rel1 < rel0) {
       const double rate = std::pow(rel1 / rel0, 1.0 / (round1 - round0));
       if (rate < 1.0) {
         const double m = std::ceil(std::log(tol / rel1) / std::log(rate));
@@ -132,6 +141,7 @@ struct ChunkPlan {
           int need = round1 + std::max(1, (int)m);
           need = ((need + ce - 1) / ce) * ce;  // the next checked round at or after it
           c = std::max(0, std::min(16, need + lag - queued_through));
+          if (ce == 1 && rel1 * std::pow(rate, (double)(need - round1)) <= 0.9 * tol) pass_round = need;
         }
       }
     }
@@ -375,11 +385,36 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   ChunkPlan plan;
   int t = 1, chunk = plan.first(lag, ce);
   bool stop = false;
+  // Predicted last check: when the planner expects round t-1 to meet the
+  // tolerance with a margin, launch t is the residual-only mode (the
+  // neighbour gathers and 12 B per slot instead of a full sweep) and the
+  // chunk ends there; only if that check fails does sweep t follow, without
+  // repeating the check.  Same rounds, same checks, same results.
+  const bool can_predict = !exact && !ait && !stf && !poison && !cfg.feedback && !cfg.keep_held && lag == 1;
+  const bool predict_all = (c->opts.flags & GABP_FLAG_PREDICT_ALL) != 0;  // test aid
+  int checked_ahead = -1;  // position whose check a residual-only launch has already made
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
+    bool predicted_end = false;
     for (; t <= tend; ++t) {
       const int mode = (t <= M) ? main_mode : kResid;
       if (ait && mode == kResid) continue;
+      if (can_predict && mode == main_mode && t >= 2 && (t - 1 == plan.pass_round || predict_all) &&
+          checked_ahead != t && in_set(t - 1)) {
+        CnodeArgs<T> k = a;
+        k.second = (t == 2);
+        k.cin = cin_buf<T>(c, t);
+        k.agg1 = c->agg_d[(t - 1) % 3];
+        k.agg2 = c->agg_d[(t + 1) % 3];
+        k.anew = c->agg_d[t % 3];
+        k.check = 1;
+        GABP_HIP(c, launch_cnode<T>(kResid, c->K, k, s, nullptr, nullptr));
+        GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
+                                        true, s));
+        checked_ahead = t;
+        predicted_end = true;
+        break;  // t stays: sweep t runs only if the check fails
+      }
       CnodeArgs<T> k = a;
       k.first = (t == 1);
       k.second = (t == 2);
@@ -396,7 +431,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
         k.xout_prev = stf ? (T*)cfg.stf_start : (T*)cfg.x2[0];  // Steffensen: round 0 starts cycle 1
         k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
       }
-      const bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1)));
+      const bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1))) && checked_ahead != t;
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
       void* other = poison ? cin_buf<T>(c, t + 1) : nullptr;  // in^(t-1): not sweep t's to touch
@@ -429,6 +464,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       }
     }
     stop = poll.step(c, cfg.st);
+    if (predicted_end && !stop) stop = poll.step(c, cfg.st);  // wait for the predicted check itself
     chunk = plan.next(poll, t - 1, lag, ce, exact ? -1.0 : cfg.tol);
   }
   return finish_run(c, poll);
@@ -584,7 +620,8 @@ gabp_status run_small(Ctx* c, const RunCfg& cfg, double* x, double* var) {
 // Plain FP64 solves of small compact-layout handles take the one-launch path.
 bool use_small(const Ctx* c, const RunCfg& cfg) {
   return c->layout == kLayoutCompact && !cfg.honly && !cfg.feedback && !cfg.ait_y && !cfg.stf_start &&
-         !(c->opts.flags & (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS | GABP_FLAG_POISON_STALE)) &&
+         !(c->opts.flags &
+           (GABP_FLAG_MULTI_LAUNCH | GABP_FLAG_TIME_SWEEPS | GABP_FLAG_POISON_STALE | GABP_FLAG_PREDICT_ALL)) &&
          (small_fits(c->n, c->E) || small_rows_fit(c->n, c->max_degree));
 }
 
@@ -768,6 +805,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
   // compact sweeps to a tolerance leave x to the end (8 B per node and sweep
   // fewer), unless the variances of every round are kept too
   cfg.x_at_end = !small && c->layout == kLayoutCompact && !exact && !ait && !stf && !cfg.pt2[0];
+  cfg.keep_held = (c->opts.flags & GABP_FLAG_REUSE_PRECISION) != 0;  // the freeze below takes the held round
   if (!small) GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
   gabp_status rs = small ? run_small(c, cfg, x, var) : run_sweeps<double>(c, cfg);
   if (rs != GABP_OK) return rs;
@@ -934,6 +972,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     // compact inner solves write no means; the outer step forms d from the
     // returned round's aggregate record (the single loop keeps them)
     cfg.x_at_end = !single && c->layout == kLayoutCompact;
+    cfg.keep_held = (c->opts.flags & GABP_FLAG_REUSE_PRECISION) || c->gamma_used > 0.0;  // a freeze may follow
     r = fp32 ? run_sweeps<float>(c, cfg) : run_sweeps<double>(c, cfg);
     if (r != GABP_OK) return r;
     if (c->run_seen_final && c->tev_used == 0) {  // the poller already waited for the final status
