@@ -66,6 +66,8 @@ gabp_status common_setup(Ctx* c) {
   GABP_HIP(c, hipHostMalloc((void**)&c->st_h, 4 * sizeof(DevStatus), hipHostMallocDefault));
   GABP_HIP(c, hipHostMalloc((void**)&c->st_small_h, sizeof(DevStatus), hipHostMallocMapped | hipHostMallocCoherent));
   GABP_HIP(c, hipHostGetDevicePointer((void**)&c->st_small_d, c->st_small_h, 0));
+  GABP_HIP(c, hipHostMalloc((void**)&c->st_mir_h, 3 * sizeof(DevStatus), hipHostMallocMapped | hipHostMallocCoherent));
+  GABP_HIP(c, hipHostGetDevicePointer((void**)&c->st_mir_d, c->st_mir_h, 0));
   for (auto& e : c->ev) GABP_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   TRY(dev_alloc(c, (void**)&c->st_d, 2 * sizeof(DevStatus)));
   TRY(dev_alloc(c, (void**)&c->norms_d, 4 * sizeof(double)));
@@ -665,6 +667,7 @@ void gabp_destroy(gabp_handle h) {
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->st_h) (void)hipHostFree(c->st_h);
   if (c->st_small_h) (void)hipHostFree(c->st_small_h);
+  if (c->st_mir_h) (void)hipHostFree(c->st_mir_h);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->tev)

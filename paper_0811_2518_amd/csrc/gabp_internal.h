@@ -349,6 +349,11 @@ struct Ctx {
   DevStatus* st_h = nullptr;              // pinned host mirror [4]
   DevStatus* st_small_h = nullptr;        // pinned, coherent: written by the one-launch solve itself
   DevStatus* st_small_d = nullptr;        // ... its device address
+  // pinned, coherent: copies of the device status written by finish kernels
+  // (two slots for the chunks of a compact run, one for the outer step), so
+  // the host reads them without a copy launch
+  DevStatus* st_mir_h = nullptr;
+  DevStatus* st_mir_d = nullptr;          // ... their device address
   DevStatus run_seen{};                   // status the last sweep loop's poller observed
   bool run_seen_final = false;            // ... and it was final (done set, nothing runs after)
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -492,12 +497,13 @@ struct OuterArgs {
   int32_t n;
   const DevStatus* gate;  // nullable: the launch returns at once once gate->done is set
   int32_t reset_st;       // launch_outer: the first kernel resets *st before the step's finish
+  DevStatus* mirror;      // nullable: the step's finish also writes *st there (host memory)
 };
 hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s);
 hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
                                double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s,
-                               double diverge_limit = kDivergeLimit);
+                               double diverge_limit = kDivergeLimit, DevStatus* mirror = nullptr);
 // Aitken step after the sweep of round t (Ch. 3 Sec. 3.2): with make_y,
 // y = hist - (x1 - hist)^2 / (x2 - 2 x1 + hist), or x2 where undefined; then
 // hist = x1.  x1 and x2 are the means of rounds t-1 and t, hist those of

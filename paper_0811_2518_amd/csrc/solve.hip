@@ -2,6 +2,7 @@
 // (iterative refinement / diagonal loading of Ch. 5), the adjoint solve and
 // the block-size autotuner.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -56,34 +57,46 @@ const T* coef_array(const Ctx* c) {
 }
 
 // Host-side polling of the device status: after each chunk of sweeps the
-// status is copied to pinned memory; the host waits for the copy of the
-// previous chunk while the current one runs.  Returns true once the device
-// reported convergence or failure.
+// status reaches pinned memory, either written there by the chunk's finish
+// kernels (mirrored) or by a copy; the host waits for the previous chunk
+// while the current one runs.  Returns true once the device reported
+// convergence or failure.
 struct Poller {
   int pending = -1, slot = 0;
+  bool from_mirror[2] = {false, false};
   gabp_status err = GABP_OK;
   DevStatus seen{};  // the last status observed on the host
   bool have = false;
-  bool step(Ctx* c, const DevStatus* st) {
-    hipError_t e = hipMemcpyAsync(&c->st_h[slot], st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], c->stream);
-    bool done = false;
-    if (e == hipSuccess && pending >= 0) {
-      e = hipEventSynchronize(c->ev[pending]);
-      if (e == hipSuccess) {
-        seen = c->st_h[pending];
-        have = true;
-        done = seen.done != 0;
-      }
-    }
+  // where the finish kernels of the current chunk write the status
+  DevStatus* mirror(const Ctx* c) const { return c->st_mir_d + slot; }
+  bool read(Ctx* c, int q) {
+    hipError_t e = hipEventSynchronize(c->ev[q]);
     if (e != hipSuccess) {
       err = hip_fail(c, e, "status poll");
       return true;
     }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    seen = from_mirror[q] ? c->st_mir_h[q] : c->st_h[q];
+    have = true;
+    return seen.done != 0;
+  }
+  // mirrored: the chunk's last finish kernel wrote the status to mirror(c)
+  bool step(Ctx* c, const DevStatus* st, bool mirrored = false) {
+    hipError_t e = hipSuccess;
+    if (!mirrored) e = hipMemcpyAsync(&c->st_h[slot], st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream);
+    from_mirror[slot] = mirrored;
+    if (e == hipSuccess) e = hipEventRecord(c->ev[slot], c->stream);
+    if (e != hipSuccess) {
+      err = hip_fail(c, e, "status poll");
+      return true;
+    }
+    const bool done = pending >= 0 && read(c, pending);
     pending = slot;
     slot ^= 1;
-    return done;
+    return done || err != GABP_OK;
   }
+  // wait for the chunk just polled as well
+  bool drain(Ctx* c) { return pending >= 0 && read(c, pending); }
 };
 
 // A sweep loop has ended: keep the status its poller observed.  Once done is
@@ -393,9 +406,14 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const bool can_predict = !exact && !ait && !stf && !poison && !cfg.feedback && !cfg.keep_held && lag == 1;
   const bool predict_all = (c->opts.flags & GABP_FLAG_PREDICT_ALL) != 0;  // test aid
   int checked_ahead = -1;  // position whose check a residual-only launch has already made
+  // the finish kernels of a chunk leave the status in pinned memory (not with
+  // Aitken's extra finish, which checks y with its own limit)
+  const bool mirror_ok = !ait;
   while (t <= last && !stop) {
     const int tend = std::min(last, t + chunk - 1);
     bool predicted_end = false;
+    bool mirrored = false;  // the last launch of the chunk is a mirrored finish
+    DevStatus* mir = mirror_ok ? poll.mirror(c) : nullptr;
     for (; t <= tend; ++t) {
       const int mode = (t <= M) ? main_mode : kResid;
       if (ait && mode == kResid) continue;
@@ -410,7 +428,8 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
         k.check = 1;
         GABP_HIP(c, launch_cnode<T>(kResid, c->K, k, s, nullptr, nullptr));
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
-                                        true, s));
+                                        true, s, kDivergeLimit, mir));
+        mirrored = mir != nullptr;
         checked_ahead = t;
         predicted_end = true;
         break;  // t stays: sweep t runs only if the check fails
@@ -444,10 +463,13 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
       start_timed<T>(c, (c->opts.flags & GABP_FLAG_TIME_SWEEPS) && mode == main_mode && (ck || ait), &e0, &e1);
       if (e0) c->timed_mode = cfg.honly ? 1 : 0;
       GABP_HIP(c, launch_cnode<T>(mode, c->K, k, s, e0, e1));
+      mirrored = false;
       if (poison) GABP_HIP(c, hipMemcpyAsync(other, c->poison_save_d, half, hipMemcpyDeviceToDevice, s));
-      if (ck)
+      if (ck) {
         GABP_HIP(c, launch_check_finish(c->partials_d, c->nblk, cfg.st, cfg.rhs_norm, tol, t - 1, nullptr,
-                                        true, s));
+                                        true, s, kDivergeLimit, mir));
+        mirrored = mir != nullptr;
+      }
       if (stf && mode != kResid && t >= 2 && (t & 1) == 0)  // end of a cycle: y replaces x_t
         GABP_HIP(c, launch_steffensen((const double*)cfg.x2[(t - 1) & 1], (double*)cfg.x2[t & 1], cfg.stf_start,
                                       c->agg_d[t % 3], cfg.st, c->n, s));
@@ -463,8 +485,8 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
         }
       }
     }
-    stop = poll.step(c, cfg.st);
-    if (predicted_end && !stop) stop = poll.step(c, cfg.st);  // wait for the predicted check itself
+    stop = poll.step(c, cfg.st, mirrored);
+    if (predicted_end && !stop) stop = poll.drain(c);  // wait for the predicted check itself
     chunk = plan.next(poll, t - 1, lag, ce, exact ? -1.0 : cfg.tol);
   }
   return finish_run(c, poll);
@@ -672,6 +694,24 @@ gabp_status read_status(Ctx* c, const DevStatus* st_d, DevStatus* out) {
   return collect_timing(c);
 }
 
+// The status a finish kernel left in pinned memory slot q, once the stream
+// has drained (no copy launch).
+gabp_status read_mirror(Ctx* c, int q, DevStatus* out) {
+  GABP_HIP(c, hipStreamSynchronize(c->stream));
+  std::atomic_thread_fence(std::memory_order_acquire);
+  *out = c->st_mir_h[q];
+  return collect_timing(c);
+}
+
+// The final status of a sweep run: the one its poller already saw when that
+// was final, else a read of the device status.
+gabp_status read_run_status(Ctx* c, const DevStatus* st_d, DevStatus* out) {
+  if (!c->run_seen_final) return read_status(c, st_d, out);
+  GABP_HIP(c, hipStreamSynchronize(c->stream));
+  *out = c->run_seen;
+  return collect_timing(c);
+}
+
 // Freeze the precisions of the messages of round `round`: the h update
 // coefficient -A_ij / (P~_i - P_ji) of every message and 1 / P~_i of every
 // node, so that later sweeps update the h messages only (the P update has no
@@ -823,7 +863,7 @@ gabp_status solve_plain(Ctx* c, const double* b, double* x, double* var, double 
     GABP_HIP(c, hipStreamSynchronize(s));
     st = *c->st_small_h;
   } else {
-    r = read_status(c, c->st_d, &st);
+    r = read_run_status(c, c->st_d, &st);
   }
   if (r != GABP_OK) return r;
   r = map_status(c, st, exact);
@@ -906,7 +946,8 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
   reset_timing(c);
   // frozen precisions of an earlier call are used only when asked for
   if (!(c->opts.flags & GABP_FLAG_REUSE_PRECISION)) c->frozen_valid = false;
-  GABP_HIP(c, launch_norm(b, c->n, c->partials_d, std::max(1, c->nblk), c->norms_d, nullptr, s));
+  // ||b|| comes from the first outer step's check of r = b (no separate norm)
+  if (c->nblk <= 0) GABP_HIP(c, launch_norm(b, c->n, c->partials_d, 1, c->norms_d, nullptr, s));
   DevStatus* st_out = c->st_d + 1;
   DevStatus* st_in = c->st_d;
 
@@ -935,9 +976,18 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
   o.nblk = c->nblk;
   o.n = c->n;
   o.reset_st = 1;  // each outer launch resets the outer status first
+  o.mirror = c->nblk > 0 ? c->st_mir_d + 2 : nullptr;  // and its finish leaves it in pinned memory
+  auto read_outer = [&](DevStatus* out) { return o.mirror ? read_mirror(c, 2, out) : read_status(c, st_out, out); };
+  // step 0 (x = 0, r = b): its check measures ||r|| = ||b|| and keeps it as ||b||
+  if (c->nblk > 0) {
+    o.b_norm = nullptr;
+    o.r_norm = c->norms_d;
+  }
   GABP_HIP(c, launch_outer(c->K, o, s));
+  o.b_norm = c->norms_d;
+  o.r_norm = c->norms_d + 1;
   DevStatus so, si;
-  gabp_status r = read_status(c, st_out, &so);
+  gabp_status r = read_outer(&so);
   if (r != GABP_OK) return r;
 
   int cur = 0, k = 0, total = 0;
@@ -962,7 +1012,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
       cfg.damp = c->opts.damping;
       cfg.chk_diag = fp32 ? (const void*)c->d32_d : (const void*)c->d64_d;
     }
-    cfg.rhs_norm = c->norms_d + 1;
+    cfg.rhs_norm = k == 0 ? c->norms_d : c->norms_d + 1;  // ||r|| (= ||b|| before the first step)
     cfg.tol = c->opts.inner_tol;
     cfg.max_iter = budget;
     cfg.check_every = c->opts.check_every;
@@ -1011,7 +1061,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     GABP_HIP(c, launch_outer(c->K, o, s));
     cur ^= 1;
     ++k;
-    r = read_status(c, st_out, &so);
+    r = read_outer(&so);
     if (r != GABP_OK) return r;
   }
   GABP_HIP(c, hipMemcpyAsync(x, c->xo_d[cur], sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));

@@ -84,9 +84,13 @@ constexpr int kFinishBlock = 1024;
 __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __restrict__ partials, int nblk,
                                                                DevStatus* st, const double* rhs_norm,
                                                                double tol, int round, double* norm_out,
-                                                               int gate_on_done, double diverge_limit) {
+                                                               int gate_on_done, double diverge_limit,
+                                                               DevStatus* mirror) {
   __shared__ double s_red[kFinishBlock / 64];
-  if (gate_on_done && st->done) return;
+  if (gate_on_done && st->done) {
+    if (mirror && threadIdx.x == 0) *mirror = *st;  // the host reads the final status there
+    return;
+  }
   // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
   // v1, each in increasing j.  Thirty-two loads are issued before their
   // additions, so up to 32768 partials (16,384 workgroups at 512 slots on
@@ -113,8 +117,8 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < kFinishBlock / 64; ++w) tot += s_red[w];
-    const double nb = *rhs_norm;
     const double rn = sqrt(tot);
+    const double nb = rhs_norm ? *rhs_norm : rn;  // without one: relative to itself
     const double rel = nb > 0.0 ? rn / nb : rn;
     if (norm_out) *norm_out = rn;
     st->prev_rel = st->last_rel;
@@ -128,14 +132,15 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
       st->error |= kErrDiverged;
       st->done = 1;
     }
+    if (mirror) *mirror = *st;
   }
 }
 
 hipError_t launch_check_finish(const double* partials, int nblk, DevStatus* st, const double* rhs_norm,
                                double tol, int round, double* norm_out, bool gate_on_done, hipStream_t s,
-                               double diverge_limit) {
+                               double diverge_limit, DevStatus* mirror) {
   hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(kFinishBlock), 0, s, partials, nblk, st, rhs_norm, tol,
-                     round, norm_out, gate_on_done ? 1 : 0, diverge_limit);
+                     round, norm_out, gate_on_done ? 1 : 0, diverge_limit, mirror);
   return hipGetLastError();
 }
 
@@ -511,14 +516,16 @@ hipError_t launch_outer(int K, const OuterArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_outer_zero, dim3(a.nblk), dim3(kBlock), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s);
+    return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s, kDivergeLimit,
+                               a.mirror);
   }
   hipLaunchKernelGGL(k_update, dim3(std::min((a.n + 255) / 256, 4096)), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_outer_only(K, a, s);
   if (e != hipSuccess) return e;
-  return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s);
+  return launch_check_finish(a.partials, a.nblk, a.st, a.b_norm, a.tol, 0, a.r_norm, false, s, kDivergeLimit,
+                             a.mirror);
 }
 
 hipError_t launch_outer_only(int K, const OuterArgs& a, hipStream_t s) {
