@@ -91,6 +91,14 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
     if (mirror && threadIdx.x == 0) *mirror = *st;  // the host reads the final status there
     return;
   }
+  // the status and the norm of b are read before the partials, so that their
+  // latency overlaps that of the partials
+  DevStatus cur{};
+  double nbv = 0.0;
+  if (threadIdx.x == 0) {
+    cur = *st;
+    if (rhs_norm) nbv = *rhs_norm;
+  }
   // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
   // v1, each in increasing j.  Thirty-two loads are issued before their
   // additions, so up to 32768 partials (16,384 workgroups at 512 slots on
@@ -118,21 +126,22 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
     double tot = 0.0;
     for (int w = 0; w < kFinishBlock / 64; ++w) tot += s_red[w];
     const double rn = sqrt(tot);
-    const double nb = rhs_norm ? *rhs_norm : rn;  // without one: relative to itself
+    const double nb = rhs_norm ? nbv : rn;  // without one: relative to itself
     const double rel = nb > 0.0 ? rn / nb : rn;
     if (norm_out) *norm_out = rn;
-    st->prev_rel = st->last_rel;
-    st->prev_round = st->last_round;
-    st->last_rel = rel;
-    st->last_round = round;
+    cur.prev_rel = cur.last_rel;
+    cur.prev_round = cur.last_round;
+    cur.last_rel = rel;
+    cur.last_round = round;
     if (rel <= tol) {
-      st->conv_round = round;
-      st->done = 1;
+      cur.conv_round = round;
+      cur.done = 1;
     } else if (!(rel <= diverge_limit)) {
-      st->error |= kErrDiverged;
-      st->done = 1;
+      cur.error |= kErrDiverged;
+      cur.done = 1;
     }
-    if (mirror) *mirror = *st;
+    *st = cur;
+    if (mirror) *mirror = cur;
   }
 }
 
@@ -470,16 +479,41 @@ __global__ __launch_bounds__(kBlock) void k_outer(OuterArgs A) {
       res2 = res * res;
     }
   } else {
-    for (int i = tid; i <= nrow; i += kBlock) s_ptr[i] = A.off_ptr[r0 + i] - e0;
+    // every independent load first (the slots' columns and coefficients,
+    // streamed once, then the rows' own data), the x gathers next, so that
+    // their latencies overlap
+    int c[K];
+    double av[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * kBlock;
-      if (i < ne) s_ax[i] = A.a[e0 + i] * x[A.off_col[e0 + i]];
+      if (i < ne) {
+        c[k] = __builtin_nontemporal_load(A.off_col + e0 + i);
+        av[k] = __builtin_nontemporal_load(A.a + e0 + i);
+      }
+    }
+    for (int i = tid; i <= nrow; i += kBlock) s_ptr[i] = A.off_ptr[r0 + i] - e0;
+    double br = 0.0, dr = 0.0, xr = 0.0;
+    if (tid < nrow) {
+      br = A.b[r0 + tid];
+      dr = A.diag[r0 + tid];
+      xr = x[r0 + tid];
+    }
+    double xg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * kBlock;
+      if (i < ne) xg[k] = x[c[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * kBlock;
+      if (i < ne) s_ax[i] = av[k] * xg[k];
     }
     __syncthreads();
     if (tid < nrow) {
       const int r = r0 + tid;
-      double res = A.b[r] - A.diag[r] * x[r];
+      double res = br - dr * xr;
       res = lds_row_sub(res, s_ax, s_ptr[tid], s_ptr[tid + 1]);
       if (A.rin32) A.rin32[r] = (float)res;
       if (A.rin64) A.rin64[r] = res;
