@@ -712,7 +712,8 @@ def suite_batched(torch, g, workloads, sample=48):
     return {"workload": "4096 systems: 2-D/3-D grids and random graphs, n log-uniform in [64, 65536], "
                         "1..32 right-hand sides, dominance 1.05..1.5",
             "num_sys": bt.num_sys, "sum_n": int(bt.sys_row_off[-1]), "sum_nk": int(bt.rhs_off[-1]),
-            "E": int(E_s.sum()), "generate_s": gen_s, "time_to_tol_ms": 1e3 * dt, "status": st,
+            "E": int(E_s.sum()), "generate_s": gen_s, "inner_tol": bs.opts.inner_tol,
+            "time_to_tol_ms": 1e3 * dt, "status": st,
             "converged_systems": nconv, "worst_rel_residual": worst,
             "slot_rhs_updates_per_s": slot_rhs / dt,
             # one FP32 h-only update of a (slot, right-hand side): the h message

@@ -407,8 +407,11 @@ gabp_status gabp_create_batched(int32_t num_sys, const int32_t *sys_row_off,
  * h-update coefficients.  The second takes work items of 1, 2, 4 or 8
  * right-hand sides of one system, all reading that system's frozen
  * coefficients, and runs the FP64 refinement loop on each (FP64 residual,
- * FP32 h-only inner sweeps to opts.inner_tol, at most opts.max_outer outer
- * steps).  Returns the worst status over systems.
+ * FP32 h-only inner sweeps until the largest change of the correction is at
+ * most opts.inner_tol times its largest magnitude, at most opts.max_outer
+ * outer steps).  Returns the worst status over systems.  A tighter inner_tol
+ * than gabp_default_opts' 1e-5 saves outer steps here: on the 4096-system
+ * benchmark batch 2e-6 is the fastest of 1e-4 ... 1e-6.
  */
 gabp_status gabp_solve_batched(gabp_handle h, const int32_t *nrhs, const int64_t *rhs_off,
                                const double *B, double *X, double tol, int32_t max_iter,

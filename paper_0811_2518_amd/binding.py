@@ -432,7 +432,9 @@ def try_create(row_ptr, col, val, **kw):
 class BatchedSolver:
     """Many independent systems (block-diagonal CSR with global columns)."""
 
-    def __init__(self, sys_row_off, row_ptr, col, val, *, inner_tol=1e-5, check_every=1,
+    # inner_tol: an outer step's FP32 sweeps stop once the largest change of
+    # the correction is at most inner_tol times its largest magnitude
+    def __init__(self, sys_row_off, row_ptr, col, val, *, inner_tol=2e-6, check_every=1,
                  inner_max_iter=10000, max_outer=1000, layout="auto", device="cuda", stream=None):
         torch = _torch()
         self.device = torch.device(device)
