@@ -87,18 +87,15 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
                                                                int gate_on_done, double diverge_limit,
                                                                DevStatus* mirror) {
   __shared__ double s_red[kFinishBlock / 64];
-  if (gate_on_done && st->done) {
-    if (mirror && threadIdx.x == 0) *mirror = *st;  // the host reads the final status there
-    return;
-  }
-  // the status and the norm of b are read before the partials, so that their
-  // latency overlaps that of the partials
+  // the status, the norm of b and the partials are all requested before the
+  // gate on a finished solve is taken, so that one round trip covers them
   DevStatus cur{};
   double nbv = 0.0;
   if (threadIdx.x == 0) {
     cur = *st;
     if (rhs_norm) nbv = *rhs_norm;
   }
+  const int gated = gate_on_done ? st->done : 0;
   // thread t adds partials t + j * kFinishBlock: even j into v0, odd j into
   // v1, each in increasing j.  Thirty-two loads are issued before their
   // additions, so up to 32768 partials (16,384 workgroups at 512 slots on
@@ -118,6 +115,10 @@ __global__ __launch_bounds__(kFinishBlock) void k_check_finish(const double* __r
       v0 += p[u];
       v1 += p[u + 1];
     }
+  }
+  if (gated) {
+    if (mirror && threadIdx.x == 0) *mirror = cur;  // the host reads the final status there
+    return;
   }
   double v = wave_sum(v0 + v1);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
