@@ -193,7 +193,11 @@ typedef struct {
  * tolerance, launch t is instead the residual-only check of round t-1, and
  * sweep t (without that check) follows only if the check fails.  With this flag every checked launch from round 2
  * on is made that way, so both outcomes run constantly; the rounds, the
- * checks and the results are the same bits as without the flag.  Runs that a
+ * checks and the results are the same bits as without the flag, except in
+ * the inner solves of the FP32 refinement: without the flag those check only
+ * rounds 0-2, at least every fourth round, and the rounds from one before
+ * the one their residuals predict to meet the inner tolerance, so they may
+ * stop a few rounds later; with it they check every round.  Runs that a
  * freeze of the precisions follows (GABP_FLAG_REUSE_PRECISION, loading), and
  * Aitken's, Steffensen's and the single-loop runs, never take that form. */
 #define GABP_FLAG_PREDICT_ALL 256

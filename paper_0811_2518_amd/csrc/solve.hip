@@ -48,6 +48,10 @@ struct RunCfg {
   // the caller freezes the precisions of the last computed round after the
   // run, so the run must end with the sweep that checks the returned round
   bool keep_held = false;
+  // an inner solve of the refinement (compact layout): once the residuals
+  // give a decay rate, checks of rounds it places well above the tolerance
+  // are left out, so the run stops at the first checked round that meets it
+  bool sparse_checks = false;
 };
 
 template <typename T>
@@ -125,6 +129,8 @@ struct ChunkPlan {
   // of GaBP falls by a steady factor per round (on G(n, 4n), 0.377 with
   // extrapolations over eight rounds within 1%)
   int pass_round = -1;
+  // the round predicted to meet the tolerance (no margin), else -1
+  int need_round = -1;
   int first(int lag, int check_every) {
     chunk = std::min(16, 2 * std::max(1, check_every) + lag);
     return chunk;
@@ -145,6 +151,7 @@ struct ChunkPlan {
       round1 = p.seen.last_round;
     }
     pass_round = -1;
+    need_round = -1;
     if (tol > 0.0 && round0 >= 0 && round1 > round0 && rel0 > 0.0 && rel1 > tol && rel1 < rel0) {
       const double rate = std::pow(rel1 / rel0, 1.0 / (round1 - round0));
       if (rate < 1.0) {
@@ -153,6 +160,7 @@ struct ChunkPlan {
           const int ce = std::max(1, check_every);
           int need = round1 + std::max(1, (int)m);
           need = ((need + ce - 1) / ce) * ce;  // the next checked round at or after it
+          need_round = need;
           c = std::max(0, std::min(16, need + lag - queued_through));
           if (ce == 1 && rel1 * std::pow(rate, (double)(need - round1)) <= 0.9 * tol) pass_round = need;
         }
@@ -406,6 +414,13 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
   const bool can_predict = !exact && !ait && !stf && !poison && !cfg.feedback && !cfg.keep_held && lag == 1;
   const bool predict_all = (c->opts.flags & GABP_FLAG_PREDICT_ALL) != 0;  // test aid
   int checked_ahead = -1;  // position whose check a residual-only launch has already made
+  // Sparse checks (inner solves of the refinement): rounds 0-2 are checked
+  // for the decay rate, later rounds only from one before the predicted one
+  // on, and at least every fourth round.  The stop then falls on the first
+  // checked round that meets the tolerance; the test aid above checks all.
+  const bool sparse = cfg.sparse_checks && !exact && !ait && !stf && !cfg.feedback && !cfg.keep_held && ce == 1 &&
+                      !predict_all;
+  int last_ck = -1;  // last round whose check has been queued
   // the finish kernels of a chunk leave the status in pinned memory (not with
   // Aitken's extra finish, which checks y with its own limit)
   const bool mirror_ok = !ait;
@@ -431,6 +446,7 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
                                         true, s, kDivergeLimit, mir));
         mirrored = mir != nullptr;
         checked_ahead = t;
+        last_ck = t - 1;
         predicted_end = true;
         break;  // t stays: sweep t runs only if the check fails
       }
@@ -450,7 +466,12 @@ gabp_status run_cnode(Ctx* c, const RunCfg& cfg) {
         k.xout_prev = stf ? (T*)cfg.stf_start : (T*)cfg.x2[0];  // Steffensen: round 0 starts cycle 1
         k.ptout_prev = cfg.pt2[0] ? (T*)cfg.pt2[0] : nullptr;
       }
-      const bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1))) && checked_ahead != t;
+      bool ck = !ait && (exact ? (t == M + 1) : (in_set(t - 1) && checked(t - 1))) && checked_ahead != t;
+      if (ck && sparse && mode == main_mode) {
+        const int j = t - 1;
+        ck = j <= 2 || plan.need_round < 0 || j >= plan.need_round - 1 || j - last_ck >= 4;
+      }
+      if (ck) last_ck = t - 1;
       k.check = ck ? 1 : 0;
       if (mode == kResid && !ck) continue;
       void* other = poison ? cin_buf<T>(c, t + 1) : nullptr;  // in^(t-1): not sweep t's to touch
@@ -1023,6 +1044,7 @@ gabp_status solve_outer(Ctx* c, const double* b, double* x, double tol, int32_t 
     // returned round's aggregate record (the single loop keeps them)
     cfg.x_at_end = !single && c->layout == kLayoutCompact;
     cfg.keep_held = (c->opts.flags & GABP_FLAG_REUSE_PRECISION) || c->gamma_used > 0.0;  // a freeze may follow
+    cfg.sparse_checks = true;  // the outer step, not the inner stop round, sets the accuracy
     r = fp32 ? run_sweeps<float>(c, cfg) : run_sweeps<double>(c, cfg);
     if (r != GABP_OK) return r;
     if (c->run_seen_final && c->tev_used == 0) {  // the poller already waited for the final status

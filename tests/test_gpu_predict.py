@@ -6,7 +6,10 @@ round t-1 meets the tolerance, launch t is the residual-only check of round
 t-1 instead, and sweep t, without repeating that check, follows only if the
 check fails.  GABP_FLAG_PREDICT_ALL takes that form at every checked launch
 from round 2 on, so both outcomes run all the time: every result must be the
-same bits as a handle without the flag.
+same bits as a handle without the flag.  The inner solves of the FP32
+refinement are the exception: without the flag they skip the checks of rounds
+far above their predicted stop, so there the two handles must each reach the
+tolerance, with corrections that agree to the inner tolerance.
 """
 import numpy as np
 import pytest
@@ -72,5 +75,11 @@ def test_fp64_solves(name, check_every):
 def test_fp32_refinement(name):
     p = CASES[name]()
     a, b = pair(p, precision="fp32")
-    info = same(a, b, dev(p.b), tol=1e-10, max_iter=20000)
-    assert info["converged"] == 1 and info["outer_iters"] >= 1
+    bv = dev(p.b)
+    xa, ia = a.solve(bv, check=False, tol=1e-10, max_iter=20000)
+    xb, ib = b.solve(bv, check=False, tol=1e-10, max_iter=20000)
+    for info in (ia, ib):
+        assert info["status"] == 0 and info["converged"] == 1 and info["outer_iters"] >= 1, info
+        assert info["rel_residual"] <= 1e-10, info
+    # both are within tol of the solution, so within about kappa * tol of each other
+    assert float(torch.linalg.norm(xa - xb) / torch.linalg.norm(xb)) <= 1e-8
