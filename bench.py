@@ -723,7 +723,7 @@ def suite_batched(torch, g, workloads, sample=48):
                          "achieved_GBs": 12 * slot_rhs / dt / 1e9,
                          "frac": 12 * slot_rhs / dt / 1e9 / HBM_PEAK_GBS,
                          "note": "algorithmic bytes over the whole solve (precision phase included); the "
-                                 "counters put the true traffic at 18-35 B per update, at about the device "
+                                 "counters put the true traffic at 18-34 B per update, at about the device "
                                  "copy rate (profiles/k_brhs_batch512_traffic.md)"},
             "load_balance": prof, "serial": serial,
             "per_system_loop": {"sample_systems": len(systems), "sample_rhs": int(kk.sum()),
